@@ -1,0 +1,176 @@
+/*
+ * sr.h -- C ABI of the structured random phase retrieval library (libsrpr.so).
+ *
+ * The library applies the structured sensing operator of Hu, Tachella, Unser
+ * and Dong, "Structured Random Model for Fast and Robust Phase Retrieval"
+ * (arXiv 2409.05734), section III, Eq. (5), oversampled case:
+ *
+ *     A = F D_L ... F D_1 U,      y = |A x|^2                       (Eq. (1))
+ *
+ * U zero-pads the signal (n = N1*N2 entries) into the centred window of an
+ * m = M1*M2 grid (offset floor((M-N)/2) per axis), D_l = diag(exp(i theta_l))
+ * are the random phase diagonals and F is the unitary DFT (1D, or the
+ * separable 2D DFT for images).  On top of A and A^H it runs the paper's two
+ * solvers: the spectral initialisation (shifted power iteration on
+ * A^H diag(T(y)) A, section II-B.2, Eq. (3)-(4)) and gradient descent on the
+ * l2 intensity loss (section II-B.1, Eq. (2)), and it also provides the dense
+ * i.i.d. complex Gaussian model (section II-A) as an MFMA baseline.
+ *
+ * Conventions shared by every call:
+ *  - Complex numbers are interleaved float pairs (re, im) ("complex64"),
+ *    arrays are row-major and contiguous.
+ *  - Every data pointer is a DEVICE pointer owned by the caller unless the
+ *    comment says "host".  The library never frees caller memory.
+ *  - Calls are asynchronous and ordered on the plan's HIP stream; argument and
+ *    shape errors are reported synchronously by the return value, before any
+ *    work is enqueued.  Device-side failures surface at sr_plan_sync().
+ *  - A plan holds several problems; per-problem arrays are concatenated in
+ *    problem order (offsets from sr_plan_offsets).
+ *  - No call aborts the process and no C++ exception crosses this boundary.
+ *    sr_last_error() gives a thread-local description of the last failure.
+ *  - A plan must not be used from two host threads at the same time.
+ */
+#ifndef SR_H_
+#define SR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sr_plan_s* sr_plan;
+
+typedef enum {
+  SR_OK = 0,
+  SR_E_ARG = -1,          /* null pointer, bad count or value */
+  SR_E_SHAPE = -2,        /* inconsistent shapes (M < N, theta out of range, ...) */
+  SR_E_UNSUPPORTED = -3,  /* valid but not implemented (e.g. an FFT length with a prime factor > 3) */
+  SR_E_HIP = -4,          /* a HIP runtime call failed */
+  SR_E_NONFINITE = -5,    /* a non-finite value was met */
+  SR_E_STATE = -6,        /* call not valid for this plan (e.g. structured call on a dense plan) */
+  SR_E_NOMEM = -7         /* device allocation failed, or a caller workspace is too small */
+} sr_status;
+
+typedef enum {
+  SR_STRUCTURED = 0,  /* A = F D_L ... F D_1 U (section III, Eq. (5), alpha > 1) */
+  SR_DENSE = 1        /* i.i.d. complex Gaussian A given as an explicit m x n matrix (section II-A) */
+} sr_kind;
+
+typedef enum {
+  SR_SCHED_AUTO = 0,       /* library's choice */
+  SR_SCHED_LOOP = 1,       /* one problem after another, one launch per fused pass */
+  SR_SCHED_BATCHED = 2     /* all problems together (persistent batched launches) */
+} sr_schedule;
+
+/* One phase-retrieval problem.
+ *  ndim      1 (vector) or 2 (image)
+ *  n[0..1]   signal shape N1 (, N2); n[1] ignored for ndim == 1
+ *  m[0..1]   measurement shape M1 (, M2) with M_k >= N_k (oversampling alpha = m/n >= 1)
+ *  layers    L >= 1 phase layers (structured only)
+ *  kind      sr_kind; all problems of a plan have the same kind
+ *  theta_offset  offset, in floats, of this problem's L*m phases inside the
+ *            plan's theta buffer (problems may share a set of phases)        */
+typedef struct {
+  int32_t ndim;
+  int32_t n[2];
+  int32_t m[2];
+  int32_t layers;
+  int32_t kind;
+  int64_t theta_offset;
+} sr_problem;
+
+/* Create a plan for nprob problems.
+ *  probs        host array of nprob problem descriptors
+ *  theta_host   host, theta_len floats: phases theta_l of every problem, each
+ *               problem's block is L consecutive m-grids (layer-major, row-major
+ *               grid) starting at probs[p].theta_offset.  Copied into the plan.
+ *               Must be NULL (theta_len 0) for SR_DENSE plans.
+ *  dense_A      SR_DENSE only: device pointer to the m x n complex64 matrix,
+ *               row-major, shared by all problems of the plan (all problems
+ *               must then have the same shape); the caller keeps it alive
+ *               until sr_plan_destroy.  NULL for SR_STRUCTURED.
+ *  hip_stream   hipStream_t to order all work on (NULL = default stream)
+ * FFT lengths along each grid axis must be one of 32, 64, 96, 128, 192, 256,
+ * 384, 512, 768, 1024, 2048 (2D) or 32 ... 4096 with L*m <= 4096 (1D);
+ * otherwise SR_E_UNSUPPORTED.  Allocates the plan's device workspace.     */
+sr_status sr_plan_create(sr_plan* out, const sr_problem* probs, int32_t nprob, const float* theta_host,
+                         int64_t theta_len, const void* dense_A, void* hip_stream);
+
+/* Replace the plan's phases by theta_len floats read from DEVICE memory
+ * (stream-ordered copy; same layout as at creation).                          */
+sr_status sr_plan_set_theta(sr_plan plan, const float* theta_dev, int64_t theta_len);
+
+/* Bytes of device workspace the plan uses (allocated by sr_plan_create).      */
+sr_status sr_plan_workspace_size(sr_plan plan, size_t* bytes);
+
+/* Per-problem offsets (in complex elements) into concatenated signal arrays
+ * (x_off, n-sized) and measurement arrays (y_off, m-sized).  Both are host
+ * arrays of nprob + 1 entries; either may be NULL.                           */
+sr_status sr_plan_offsets(sr_plan plan, int64_t* x_off, int64_t* y_off);
+
+/* Choose how multi-problem plans are scheduled (sr_schedule).                */
+sr_status sr_plan_set_schedule(sr_plan plan, int32_t schedule);
+
+/* Wait for all work of the plan's stream; reports device-side failures.      */
+sr_status sr_plan_sync(sr_plan plan);
+
+/* Free the plan and its workspace (after waiting for its stream).             */
+sr_status sr_plan_destroy(sr_plan plan);
+
+/* z = A x and/or y = |A x|^2 (Eq. (1), Eq. (5)).
+ *  x  complex64, concatenated signals (x_off layout)
+ *  z  complex64, concatenated m-grids (y_off layout), or NULL
+ *  y  float, concatenated m-grids (y_off layout), or NULL                    */
+sr_status sr_forward(sr_plan plan, const void* x, void* z, float* y);
+
+/* x_out = A^H r (adjoint of Eq. (5)).  r: complex64 (y_off layout);
+ * x_out: complex64 (x_off layout).                                            */
+sr_status sr_adjoint(sr_plan plan, const void* r, void* x_out);
+
+/* Spectral initialisation (section II-B.2, Eq. (3)-(4)).  With y~ = y/mean(y),
+ * T(y~) = max(1 - 1/y~, lambda) (T = lambda where y = 0), the shifted power
+ * iteration v <- B v / ||B v||, B = A^H diag(T) A / (m c) - 2 lambda I, with
+ * c = 1/m for SR_STRUCTURED and c = 1 for SR_DENSE, runs `iters` times from
+ * v0/||v0||; x0_out = sqrt(sum(y)/(m c)) * v_iters.
+ *  y       float, measurements (y_off layout)
+ *  v0      complex64 start vectors (x_off layout), not modified
+ *  lambda  threshold, lambda < 0
+ *  x0_out  complex64 (x_off layout); must not alias v0                        */
+sr_status sr_spectral_init(sr_plan plan, const float* y, const void* v0, int32_t iters, float lambda,
+                           void* x0_out);
+
+/* Gradient descent on the intensity loss || |Ax|^2 - y ||^2 (section II-B.1,
+ * Eq. (2) read with diag(A x)): x <- x - eta * A^H((|Ax|^2 - y) . Ax) / m,
+ * `iters` times, in place.
+ *  y           float measurements (y_off layout)
+ *  x_inout     complex64 iterates (x_off layout), updated in place
+ *  eta_host    HOST array of nprob raw step sizes (no hidden normalisation)
+ *  loss_trace  device float[iters * nprob] (problem-major) receiving the loss
+ *              before each step, or NULL                                       */
+sr_status sr_gd_solve(sr_plan plan, const float* y, void* x_inout, int32_t iters, const float* eta_host,
+                      float* loss_trace);
+
+/* Reverse-mode derivatives (gradients follow PyTorch's complex convention
+ * dL/dRe + i dL/dIm), for differentiating through A and A^H.
+ * sr_forward_vjp: given x and a cotangent gz of z = A x, writes
+ *   gx_out = A^H gz and ADDS d<gz, A x>/d theta into gtheta_accum (theta layout,
+ *   problems sharing a set of phases accumulate into the same entries).
+ * sr_adjoint_vjp: given r and a cotangent gv of v = A^H r, writes gr_out = A gv
+ *   and ADDS the phase cotangent into gtheta_accum.
+ * gx_out / gr_out may be NULL.  Structured plans only.                         */
+sr_status sr_forward_vjp(sr_plan plan, const void* x, const void* gz, void* gx_out, float* gtheta_accum);
+sr_status sr_adjoint_vjp(sr_plan plan, const void* r, const void* gv, void* gr_out, float* gtheta_accum);
+
+/* Static description of a status code.                                        */
+const char* sr_status_string(sr_status s);
+
+/* Thread-local description of the last failure on this thread ("" if none).  */
+const char* sr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SR_H_ */

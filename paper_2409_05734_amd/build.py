@@ -1,0 +1,83 @@
+"""Build libsrpr.so (the HIP library behind include/sr.h) for gfx950.
+
+Compiles every translation unit under csrc/ with hipcc (the per-length pass
+kernels once per supported FFT length, in parallel) and links them into
+paper_2409_05734_amd/libsrpr.so.  Run as a script or call build().
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+BUILD = os.path.join(ROOT, "_build")
+LIB = os.path.join(PKG, "libsrpr.so")
+
+FFT_LENGTHS = (32, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 2048)
+SOURCES = ("sr_api.hip", "plan.hip", "dispatch.hip", "util_kernels.hip", "dense.hip", "vjp.hip", "persist.hip")
+
+ARCH = os.environ.get("SR_OFFLOAD_ARCH", "gfx950")
+
+
+def hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found (ROCm is required to build libsrpr)")
+
+
+def common_flags() -> list:
+    return [
+        "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+        # keep the compiler from forming packed-FP32 instructions
+        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
+        "-Wno-unused-command-line-argument",
+    ]
+
+
+def _compile(src: str, obj: str, extra: list) -> tuple:
+    cmd = [hipcc()] + common_flags() + extra + ["-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    # hipcc's host pass warns about the device-only target feature; drop that noise
+    err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
+    return r.returncode, " ".join(cmd), err
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    tasks = []
+    for n in FFT_LENGTHS:
+        tasks.append((os.path.join(CSRC, "passes_inst.hip"), os.path.join(BUILD, f"passes_{n}.o"), [f"-DSR_FFT_N={n}"]))
+    for s in SOURCES:
+        tasks.append((os.path.join(CSRC, s), os.path.join(BUILD, s.replace(".hip", ".o")), []))
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    failures = []
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        futs = {ex.submit(_compile, *t): t for t in tasks}
+        for f in cf.as_completed(futs):
+            rc, cmd, err = f.result()
+            if rc != 0:
+                failures.append((cmd, err))
+            elif verbose and err.strip():
+                print(err, file=sys.stderr)
+    if failures:
+        msg = "\n\n".join(f"$ {c}\n{e}" for c, e in failures)
+        raise RuntimeError("libsrpr build failed:\n" + msg)
+    objs = [t[1] for t in tasks]
+    tmp = LIB + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("libsrpr link failed:\n" + r.stderr)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,84 @@
+// Runtime dispatch from FFT length to the per-length kernel instantiations.
+#include "fused1d.hpp"
+#include "launch.hpp"
+
+namespace sr {
+
+#define SR_FOR_EACH_2D_LEN(X) X(32) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(2048)
+
+hipError_t launch_pass(int N, int kind, bool col, int B, const PassArgs& a, hipStream_t s) {
+  if (B <= 0) B = default_tile(N, col);
+  switch (N) {
+#define SR_CASE(n) \
+  case n:          \
+    return launch_pass_n<n>(kind, col, B, a, s);
+    SR_FOR_EACH_2D_LEN(SR_CASE)
+#undef SR_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+int tile_options(int N, bool col, int* out, int max_out) {
+  switch (N) {
+#define SR_CASE(n) \
+  case n:          \
+    return tile_options_n<n>(col, out, max_out);
+    SR_FOR_EACH_2D_LEN(SR_CASE)
+#undef SR_CASE
+    default:
+      return 0;
+  }
+}
+
+// Default tile: the widest column tile (longest contiguous segments) and the
+// four-wave row tile.
+int default_tile(int N, bool col) {
+  int opts[8];
+  const int n = tile_options(N, col, opts, 8);
+  return n > 0 ? opts[n - 1] : 1;
+}
+
+int pass_groups(int N, bool col, int B, int ntr) {
+  if (B <= 0) B = default_tile(N, col);
+  return (ntr + B - 1) / B;
+}
+
+namespace {
+template <int N>
+hipError_t go1d(int op, const Fused1DArgs& a, hipStream_t s) {
+  constexpr int NT = Tile<N, 1, false>::THREADS;
+  switch (op) {
+    case F1_FORWARD:
+      hipLaunchKernelGGL((fused1d_kernel<N, F1_FORWARD>), dim3(1), dim3(NT), 0, s, a);
+      break;
+    case F1_ADJOINT:
+      hipLaunchKernelGGL((fused1d_kernel<N, F1_ADJOINT>), dim3(1), dim3(NT), 0, s, a);
+      break;
+    case F1_GD:
+      hipLaunchKernelGGL((fused1d_kernel<N, F1_GD>), dim3(1), dim3(NT), 0, s, a);
+      break;
+    case F1_SPECTRAL:
+      hipLaunchKernelGGL((fused1d_kernel<N, F1_SPECTRAL>), dim3(1), dim3(NT), 0, s, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_fused1d(int m, int op, const Fused1DArgs& a, hipStream_t s) {
+  switch (m) {
+#define SR_CASE(n) \
+  case n:          \
+    return go1d<n>(op, a, s);
+    SR_FOR_EACH_2D_LEN(SR_CASE)
+    SR_CASE(4096)
+#undef SR_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace sr

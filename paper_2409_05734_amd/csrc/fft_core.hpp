@@ -1,0 +1,281 @@
+// Device-side FFT core for gfx950: complex helpers, radix butterflies and a
+// register/LDS Stockham transform over a tile of B independent length-N
+// transforms.
+//
+// Layout contract ("canonical" register layout): the TPT = N/E threads of one
+// transform each hold E elements; thread t holds elements k = t + j*TPT,
+// j = 0..E-1.  Both the input and the output of `Tile::fft` use this layout,
+// so that pointwise work between two transforms (phase diagonals, epilogues)
+// happens in registers, and global loads/stores along a contiguous axis are
+// coalesced.
+//
+// Each radix-R Stockham stage (span p = product of the previous radices)
+// takes inputs at i + r*N/R, i = t + q*TPT, multiplies by the twiddles
+// w^(r*k) with k = i mod p and w = exp(-+2 pi i/(p R)), applies the R-point
+// DFT and writes output r to (i div p)*p*R + k + r*p.  Intermediate stages
+// exchange through LDS (ping-pong buffers, one barrier per stage); the last
+// stage's outputs land back in canonical order.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sr {
+
+// ----------------------------------------------------------- complex helpers
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float cabs2(float2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// multiply by -i (forward quarter turn) or +i (inverse quarter turn)
+template <bool INV>
+__device__ __forceinline__ float2 quarter(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+// e^{i theta} scaled by s, with an optional conjugate
+template <bool CONJ>
+__device__ __forceinline__ float2 phase(float theta, float s) {
+  float sn, cs;
+  sincosf(theta, &sn, &cs);
+  return make_float2(cs * s, CONJ ? -sn * s : sn * s);
+}
+
+// Deterministic workgroup sum (fixed tree order); every thread gets the
+// result.  NTHREADS must be a power of two and equal blockDim.x.
+template <int NTHREADS>
+__device__ __forceinline__ float block_sum(float v, float* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NTHREADS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const float r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// --------------------------------------------------------------- butterflies
+// In-place R-point DFT, y_k = sum_j u_j w^(jk), w = exp(-2 pi i/R) (forward)
+// or exp(+2 pi i/R) (INV).  No scaling.
+template <int R, bool INV>
+struct Dft;
+
+template <bool INV>
+struct Dft<2, INV> {
+  __device__ __forceinline__ static void run(float2* u) {
+    float2 a = u[0], b = u[1];
+    u[0] = cadd(a, b);
+    u[1] = csub(a, b);
+  }
+};
+
+template <bool INV>
+struct Dft<3, INV> {
+  __device__ __forceinline__ static void run(float2* u) {
+    const float h = 0.866025403784438646763723170752936183f;  // sqrt(3)/2
+    float2 s = cadd(u[1], u[2]);
+    float2 d = csub(u[1], u[2]);
+    float2 m = make_float2(u[0].x - 0.5f * s.x, u[0].y - 0.5f * s.y);
+    float2 q = cscale(quarter<INV>(d), h);  // -+ i sqrt(3)/2 (u1 - u2)
+    u[0] = cadd(u[0], s);
+    u[1] = cadd(m, q);
+    u[2] = csub(m, q);
+  }
+};
+
+template <bool INV>
+struct Dft<4, INV> {
+  __device__ __forceinline__ static void run(float2* u) {
+    float2 t0 = cadd(u[0], u[2]);
+    float2 t1 = csub(u[0], u[2]);
+    float2 t2 = cadd(u[1], u[3]);
+    float2 t3 = quarter<INV>(csub(u[1], u[3]));
+    u[0] = cadd(t0, t2);
+    u[2] = csub(t0, t2);
+    u[1] = cadd(t1, t3);
+    u[3] = csub(t1, t3);
+  }
+};
+
+template <bool INV>
+struct Dft<8, INV> {
+  __device__ __forceinline__ static void run(float2* u) {
+    const float c = 0.707106781186547524400844362104849039f;  // sqrt(2)/2
+    float2 e[4] = {u[0], u[2], u[4], u[6]};
+    float2 o[4] = {u[1], u[3], u[5], u[7]};
+    Dft<4, INV>::run(e);
+    Dft<4, INV>::run(o);
+    // w8^1 = (c, -+c), w8^2 = -+i, w8^3 = (-c, -+c)
+    float2 o1 = INV ? make_float2(c * (o[1].x - o[1].y), c * (o[1].x + o[1].y))
+                    : make_float2(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x));
+    float2 o2 = quarter<INV>(o[2]);
+    float2 o3 = INV ? make_float2(-c * (o[3].x + o[3].y), c * (o[3].x - o[3].y))
+                    : make_float2(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y));
+    u[0] = cadd(e[0], o[0]);
+    u[4] = csub(e[0], o[0]);
+    u[1] = cadd(e[1], o1);
+    u[5] = csub(e[1], o1);
+    u[2] = cadd(e[2], o2);
+    u[6] = csub(e[2], o2);
+    u[3] = cadd(e[3], o3);
+    u[7] = csub(e[3], o3);
+  }
+};
+
+// ------------------------------------------------------------- radix lists
+template <int... Rs>
+struct RadixList {
+  static constexpr int count = sizeof...(Rs);
+  static constexpr int values[count] = {Rs...};
+  static constexpr int product() {
+    int p = 1;
+    for (int i = 0; i < count; ++i) p *= values[i];
+    return p;
+  }
+  static constexpr int span(int s) {  // product of the first s radices
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= values[i];
+    return p;
+  }
+};
+
+// Factorisation and elements-per-thread for each supported length.
+template <int N>
+struct FftShape;
+template <> struct FftShape<16>   { static constexpr int E = 4;  using R = RadixList<4, 4>; };
+template <> struct FftShape<32>   { static constexpr int E = 8;  using R = RadixList<8, 4>; };
+template <> struct FftShape<64>   { static constexpr int E = 8;  using R = RadixList<8, 8>; };
+template <> struct FftShape<128>  { static constexpr int E = 8;  using R = RadixList<8, 4, 4>; };
+template <> struct FftShape<256>  { static constexpr int E = 8;  using R = RadixList<8, 8, 4>; };
+template <> struct FftShape<512>  { static constexpr int E = 8;  using R = RadixList<8, 8, 8>; };
+template <> struct FftShape<1024> { static constexpr int E = 8;  using R = RadixList<8, 8, 4, 4>; };
+template <> struct FftShape<2048> { static constexpr int E = 8;  using R = RadixList<8, 8, 8, 4>; };
+template <> struct FftShape<4096> { static constexpr int E = 8;  using R = RadixList<8, 8, 8, 8>; };
+template <> struct FftShape<24>   { static constexpr int E = 12; using R = RadixList<3, 4, 2>; };
+template <> struct FftShape<48>   { static constexpr int E = 12; using R = RadixList<3, 4, 4>; };
+template <> struct FftShape<96>   { static constexpr int E = 12; using R = RadixList<3, 4, 4, 2>; };
+template <> struct FftShape<192>  { static constexpr int E = 12; using R = RadixList<3, 4, 4, 4>; };
+template <> struct FftShape<384>  { static constexpr int E = 12; using R = RadixList<3, 4, 4, 4, 2>; };
+template <> struct FftShape<768>  { static constexpr int E = 12; using R = RadixList<3, 4, 4, 4, 4>; };
+
+// ------------------------------------------------------------------- tile
+// A tile of B transforms of length N.  COL selects the thread mapping used for
+// column-mode tiles: lane = t*B + b (consecutive lanes walk the batch, which is
+// the contiguous direction in memory) with LDS layout [k][b]; otherwise
+// lane = b*TPT + t with LDS layout [b][k + pad].
+template <int N, int B, bool COL, int E_ = FftShape<N>::E, class RL = typename FftShape<N>::R>
+struct Tile {
+  static constexpr int E = E_;
+  static constexpr int TPT = N / E;
+  static constexpr int THREADS = TPT * B;
+  static constexpr int PAD = COL ? 0 : 0;
+  static constexpr int LD = N + PAD;          // row-mode LDS stride
+  static constexpr int BUF = B * LD;          // complex elements per LDS buffer
+  static_assert(N % E == 0, "E must divide N");
+  static_assert(RL::product() == N, "radix list must multiply to N");
+
+  __device__ __forceinline__ static int lidx(int b, int k) { return COL ? (k * B + b) : (b * LD + k); }
+  __device__ __forceinline__ static int thread_t() { return COL ? (int)(threadIdx.x / B) : (int)(threadIdx.x % TPT); }
+  __device__ __forceinline__ static int thread_b() { return COL ? (int)(threadIdx.x % B) : (int)(threadIdx.x / TPT); }
+  __device__ __forceinline__ static int elem(int t, int j) { return t + j * TPT; }
+
+  // Twiddle factors this thread needs, preloaded into registers once
+  // (stages >= 1; stage 0 has span 1 and no twiddles).  Forward and inverse
+  // transforms of the same length share them (the inverse conjugates).
+  static constexpr int tw_offset(int S) {
+    int c = 0;
+    for (int s = 1; s < S && s < RL::count; ++s) c += (E / RL::values[s]) * (RL::values[s] - 1);
+    return c;
+  }
+  static constexpr int NTW = tw_offset(RL::count) > 0 ? tw_offset(RL::count) : 1;
+  using Twiddles = float2[NTW];
+
+  // tw: table exp(-2 pi i e/N), e = 0..N-1, rounded from float64.
+  __device__ __forceinline__ static void load_twiddles(Twiddles& w, const float2* __restrict__ tw, int t) {
+    load_tw_stage<1>(w, tw, t);
+  }
+
+  // Forward (INV=false) or inverse (INV=true) unscaled DFT of the B transforms.
+  // v: canonical registers in, canonical registers out.  lds: two buffers of
+  // BUF elements; `phase` selects which buffer the first exchange writes and
+  // is advanced so that consecutive transforms keep alternating buffers.
+  template <bool INV>
+  __device__ __forceinline__ static void fft(float2 (&v)[E], float2* lds, int& phase, const Twiddles& w, int t,
+                                             int b) {
+    stage<INV, 0>(v, lds, phase, w, t, b);
+  }
+
+ private:
+  template <int S>
+  __device__ __forceinline__ static void load_tw_stage(Twiddles& w, const float2* __restrict__ tw, int t) {
+    if constexpr (S < RL::count) {
+      constexpr int R = RL::values[S];
+      constexpr int P = RL::span(S);
+      constexpr int Q = E / R;
+      constexpr int STRIDE = N / (P * R);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int k = (t + q * TPT) % P;
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[tw_offset(S) + q * (R - 1) + (r - 1)] = tw[r * k * STRIDE];
+      }
+      load_tw_stage<S + 1>(w, tw, t);
+    }
+  }
+
+  template <bool INV, int S>
+  __device__ __forceinline__ static void stage(float2 (&v)[E], float2* lds, int& phase, const Twiddles& w, int t,
+                                               int b) {
+    if constexpr (S < RL::count) {
+      constexpr int R = RL::values[S];
+      constexpr int P = RL::span(S);
+      constexpr int Q = E / R;  // butterflies per thread in this stage
+      static_assert(E % R == 0, "radix must divide elements per thread");
+      if constexpr (S > 0) {
+        // inputs of this stage: canonical positions in the buffer written last
+        __syncthreads();
+        float2* src = lds + (phase ^ 1) * BUF;
+#pragma unroll
+        for (int j = 0; j < E; ++j) v[j] = src[lidx(b, elem(t, j))];
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        float2 u[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[r] = v[q + r * Q];
+        const int i = t + q * TPT;
+        const int k = i % P;
+        if constexpr (S > 0) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            const float2 tf = w[tw_offset(S) + q * (R - 1) + (r - 1)];
+            u[r] = INV ? cmulc(u[r], tf) : cmul(u[r], tf);
+          }
+        }
+        Dft<R, INV>::run(u);
+        if constexpr (S + 1 < RL::count) {
+          float2* dst = lds + phase * BUF;
+          const int base = (i / P) * P * R + k;
+#pragma unroll
+          for (int r = 0; r < R; ++r) dst[lidx(b, base + r * P)] = u[r];
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) v[q + r * Q] = u[r];
+        }
+      }
+      if constexpr (S + 1 < RL::count) phase ^= 1;
+      stage<INV, S + 1>(v, lds, phase, w, t, b);
+    }
+  }
+};
+
+}  // namespace sr

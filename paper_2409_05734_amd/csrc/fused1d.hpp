@@ -1,0 +1,188 @@
+// LDS-resident kernels for one-dimensional problems: the whole m-vector of a
+// problem lives in one workgroup (registers + LDS), so an operator
+// application, or every iteration of a GD / spectral solve, runs in a single
+// launch with no global-memory round trip between layers or iterations.
+//
+// 1D operator (section III, Eq. (5), oversampled case):
+//   A x = F D_L ... F D_1 U x with F the unitary m-point DFT.
+#pragma once
+#include "fft_core.hpp"
+
+namespace sr {
+
+// Capacity of the per-workgroup table of layer phases (L*m entries).
+constexpr int kFused1DPhaseSlots = 4096;
+
+enum Fused1DOp : int { F1_FORWARD = 0, F1_ADJOINT = 1, F1_GD = 2, F1_SPECTRAL = 3 };
+
+struct Fused1DArgs {
+  int n, m, L, off;          // signal length, measurement length, layers, pad offset
+  const float* theta;        // L*m phases
+  const float2* tw;          // exp(-2 pi i e/m), e = 0..m-1
+  const float2* x_in;        // forward: x; spectral: v0
+  float2* x_out;             // adjoint / spectral: output; GD: iterate (in place)
+  const float2* r_in;        // adjoint input
+  float2* z_out;             // forward: z (nullable)
+  float* y_out;              // forward: |z|^2 (nullable)
+  const float* y;            // GD / spectral measurements
+  int iters;
+  float step;                // GD: eta/m; spectral: 1/(m c)
+  float lam;                 // spectral lambda
+  float* loss_trace;         // GD: loss before each step (nullable)
+};
+
+template <int N, int OP>
+__global__ void __launch_bounds__((Tile<N, 1, false>::THREADS)) fused1d_kernel(const Fused1DArgs a) {
+  using T = Tile<N, 1, false>;
+  constexpr int E = T::E;
+  constexpr int NT = T::THREADS;
+  __shared__ float2 lds[2 * T::BUF];
+  __shared__ float2 dl[kFused1DPhaseSlots];  // e^{i theta_l}, L*m <= slots
+  __shared__ float red[NT];
+  const int t = threadIdx.x;
+  const float s = rsqrtf((float)N);
+  const int L = a.L;
+
+  for (int e = t; e < L * N; e += NT) {
+    float sn, cs;
+    sincosf(a.theta[e], &sn, &cs);
+    dl[e] = make_float2(cs, sn);
+  }
+  __syncthreads();
+
+  auto in_window = [&](int k) { return k >= a.off && k < a.off + a.n; };
+  typename T::Twiddles w;
+  T::load_twiddles(w, a.tw, t);
+  int ph = 0;
+  float2 v[E];
+
+  // forward layers from v = U x (already in registers); leaves z = A x in v
+  auto forward_layers = [&]() {
+    for (int l = 0; l < L; ++l) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = cmul(v[j], dl[l * N + T::elem(t, j)]);
+      T::template fft<false>(v, lds, ph, w, t, 0);
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = cscale(v[j], s);
+    }
+  };
+  // adjoint layers from v = r; leaves D_1^* F^H ... in v (crop left to caller)
+  auto adjoint_layers = [&]() {
+    for (int l = L - 1; l >= 0; --l) {
+      T::template fft<true>(v, lds, ph, w, t, 0);
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = cscale(cmulc(v[j], dl[l * N + T::elem(t, j)]), s);
+    }
+  };
+
+  if constexpr (OP == F1_FORWARD) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int k = T::elem(t, j);
+      v[j] = in_window(k) ? a.x_in[k - a.off] : make_float2(0.f, 0.f);
+    }
+    forward_layers();
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int k = T::elem(t, j);
+      if (a.z_out) a.z_out[k] = v[j];
+      if (a.y_out) a.y_out[k] = cabs2(v[j]);
+    }
+  } else if constexpr (OP == F1_ADJOINT) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = a.r_in[T::elem(t, j)];
+    adjoint_layers();
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int k = T::elem(t, j);
+      if (in_window(k)) a.x_out[k - a.off] = v[j];
+    }
+  } else if constexpr (OP == F1_GD) {
+    float2 x[E];
+    float yv[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int k = T::elem(t, j);
+      x[j] = in_window(k) ? a.x_out[k - a.off] : make_float2(0.f, 0.f);
+      yv[j] = a.y[k];
+    }
+    for (int it = 0; it < a.iters; ++it) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = x[j];
+      forward_layers();
+      float acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        float d = cabs2(v[j]) - yv[j];
+        acc += d * d;
+        v[j] = cscale(v[j], d);
+      }
+      if (a.loss_trace) {
+        float tot = block_sum<NT>(acc, red);
+        if (t == 0) a.loss_trace[it] = tot;
+      }
+      adjoint_layers();
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int k = T::elem(t, j);
+        if (in_window(k)) x[j] = make_float2(x[j].x - a.step * v[j].x, x[j].y - a.step * v[j].y);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int k = T::elem(t, j);
+      if (in_window(k)) a.x_out[k - a.off] = x[j];
+    }
+  } else {  // F1_SPECTRAL
+    float yv[E];
+    float2 u[E];
+    float ys = 0.f, un = 0.f;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int k = T::elem(t, j);
+      yv[j] = a.y[k];
+      ys += yv[j];
+      u[j] = in_window(k) ? a.x_in[k - a.off] : make_float2(0.f, 0.f);
+      un += cabs2(u[j]);
+    }
+    const float ysum = block_sum<NT>(ys, red);
+    const float ybar = ysum / (float)N;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      float w = a.lam;
+      if (yv[j] > 0.f) w = fmaxf(1.f - ybar / yv[j], a.lam);
+      yv[j] = w;  // yv now holds T(y)
+    }
+    float inv = rsqrtf(block_sum<NT>(un, red));
+    for (int it = 0; it < a.iters; ++it) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        u[j] = cscale(u[j], inv);  // v_k = u / ||u||
+        v[j] = u[j];
+      }
+      forward_layers();
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = cscale(v[j], yv[j]);
+      adjoint_layers();
+      float acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int k = T::elem(t, j);
+        float2 nu = make_float2(0.f, 0.f);
+        if (in_window(k))
+          nu = make_float2(a.step * v[j].x - 2.f * a.lam * u[j].x, a.step * v[j].y - 2.f * a.lam * u[j].y);
+        u[j] = nu;
+        acc += cabs2(nu);
+      }
+      inv = rsqrtf(block_sum<NT>(acc, red));
+    }
+    const float scale = sqrtf(ysum * a.step) * inv;  // sqrt(sum(y)/(m c)) / ||u||
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int k = T::elem(t, j);
+      if (in_window(k)) a.x_out[k - a.off] = cscale(u[j], scale);
+    }
+  }
+}
+
+}  // namespace sr

@@ -1,0 +1,72 @@
+// Host-side launch interface between the plan logic and the per-length
+// kernel translation units (one object file per FFT length).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "passes.hpp"
+
+namespace sr {
+
+// The fused pass shapes used by the operator and the solvers.
+enum PassKind : int {
+  PK_FIRST_FWD = 0,   // [U, D_1, F_0]           column mode over the support columns
+  PK_MID_FWD = 1,     // [F_a, D_k, F_a]
+  PK_LAST_STORE = 2,  // [F_a -> z, |z|^2]
+  PK_TURN_GD = 3,     // [F_a -> (|z|^2 - y) z -> F_a^H]
+  PK_TURN_SPEC = 4,   // [F_a -> T(y) z -> F_a^H]
+  PK_FIRST_ADJ = 5,   // [F_a^H]
+  PK_MID_ADJ = 6,     // [F_a^H, D_k^*, F_a^H]
+  PK_LAST_ADJ = 7,    // [F_0^H, D_1^*, U^H]      column mode over the support columns
+  PK_LAST_GD = 8,     // ... then x <- x - step * g
+  PK_LAST_SPEC = 9,   // ... then u <- step * g - 2 lambda u/||u|| (+ norm partials)
+  PK_COUNT = 10
+};
+
+// Tile widths: each length is compiled for a few tile widths (transforms per
+// workgroup) in each mode; the plan's tuner picks one per (length, mode).
+// Row mode: 1 wave or 4 waves per workgroup.  Column mode: 4, 8 or 16
+// adjacent columns (32-, 64- or 128-byte row segments), within 1024 threads
+// and the LDS budget (double-buffered tiles).
+template <int N>
+struct TileCfg {
+  static constexpr int E = FftShape<N>::E;
+  static constexpr int TPT = N / E;
+  static constexpr int lds_bytes(int b) { return 2 * b * N * 8; }
+  static constexpr bool col_ok(int b) {
+    return b * TPT <= 1024 && (lds_bytes(b) <= 65536 || (b == 4 && lds_bytes(b) <= 131072));
+  }
+  static constexpr bool row_ok(int b) { return b >= 1 && b * TPT <= 1024 && lds_bytes(b) <= 65536; }
+  static constexpr int ROW_SMALL = TPT >= 64 ? 1 : 64 / TPT;   // one wave
+  static constexpr int ROW_BIG = TPT >= 256 ? 1 : 256 / TPT;   // four waves
+};
+
+// Tile widths available for a length and mode (ascending), and the default.
+int tile_options(int N, bool col, int* out, int max_out);
+int default_tile(int N, bool col);
+
+// Number of workgroups a pass of this length/mode/tile launches.
+int pass_groups(int N, bool col, int B, int ntr);
+
+// Launch one fused pass with tile width B (0 = default).  Returns the launch
+// error, or hipErrorInvalidValue for an unsupported length or tile width.
+hipError_t launch_pass(int N, int kind, bool col, int B, const PassArgs& a, hipStream_t s);
+
+// Per-length entry points, each defined in its own translation unit.
+template <int N>
+hipError_t launch_pass_n(int kind, bool col, int B, const PassArgs& a, hipStream_t s);
+template <int N>
+int tile_options_n(bool col, int* out, int max_out);
+
+// 1D LDS-resident kernels (fused1d.hpp)
+struct Fused1DArgs;
+hipError_t launch_fused1d(int m, int op, const Fused1DArgs& a, hipStream_t s);
+
+}  // namespace sr
+
+namespace sr {
+struct PersistArgs;
+bool persistent_supported(int N, int B);
+// Cooperative launch of a whole GD (op 0) or spectral (op 1) solve; `grid`
+// is clamped to the number of co-resident workgroups.
+hipError_t launch_persistent(int N, int B, int op, const PersistArgs& pa, int grid, hipStream_t s);
+}  // namespace sr

@@ -1,0 +1,111 @@
+// Kernel instantiations for one FFT length, selected by -DSR_FFT_N=<length>.
+// The build compiles this file once per supported length so the lengths
+// compile in parallel.
+#include "launch.hpp"
+
+#ifndef SR_FFT_N
+#error "compile with -DSR_FFT_N=<length>"
+#endif
+
+namespace sr {
+
+namespace {
+
+template <int N, int B, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST>
+hipError_t go(const PassArgs& a, hipStream_t s) {
+  using T = Tile<N, B, COL>;
+  auto kern = pass_kernel<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST>;
+  const size_t lds = 2 * sizeof(float2) * (size_t)T::BUF;
+  if (lds > 65536) {
+    static bool raised = false;  // once per instantiation
+    if (!raised) {
+      hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      raised = true;
+    }
+  }
+  const int groups = (a.ntr + B - 1) / B;
+  if (groups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kern, dim3(groups), dim3(T::THREADS), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int N, bool COL, int B>
+hipError_t dispatch(int kind, const PassArgs& a, hipStream_t s) {
+  if constexpr (COL) {
+    switch (kind) {
+      case PK_FIRST_FWD:
+        return go<N, B, COL, PRE_PHASE, MID_NONE, false, false, false, POST_STORE>(a, s);
+      case PK_LAST_ADJ:
+        return go<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_PHASE_CONJ_STORE>(a, s);
+      case PK_LAST_GD:
+        return go<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_GD>(a, s);
+      case PK_LAST_SPEC:
+        return go<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_SPEC>(a, s);
+      default:
+        break;
+    }
+  }
+  switch (kind) {
+    case PK_MID_FWD:
+      return go<N, B, COL, PRE_NONE, MID_PHASE, true, false, false, POST_STORE>(a, s);
+    case PK_LAST_STORE:
+      return go<N, B, COL, PRE_NONE, MID_STORE, false, false, false, POST_STORE>(a, s);
+    case PK_TURN_GD:
+      return go<N, B, COL, PRE_NONE, MID_GD, true, false, true, POST_STORE>(a, s);
+    case PK_TURN_SPEC:
+      return go<N, B, COL, PRE_NONE, MID_SPEC, true, false, true, POST_STORE>(a, s);
+    case PK_FIRST_ADJ:
+      return go<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_STORE>(a, s);
+    case PK_MID_ADJ:
+      return go<N, B, COL, PRE_NONE, MID_PHASE_CONJ, true, true, true, POST_STORE>(a, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+using Cfg = TileCfg<SR_FFT_N>;
+constexpr int kColOpts[3] = {4, 8, 16};
+
+}  // namespace
+
+template <>
+int tile_options_n<SR_FFT_N>(bool col, int* out, int max_out) {
+  int n = 0;
+  if (col) {
+    for (int b : kColOpts)
+      if (Cfg::col_ok(b) && n < max_out) out[n++] = b;
+  } else {
+    if (n < max_out) out[n++] = Cfg::ROW_SMALL;
+    if (Cfg::ROW_BIG != Cfg::ROW_SMALL && n < max_out) out[n++] = Cfg::ROW_BIG;
+  }
+  return n;
+}
+
+template <>
+hipError_t launch_pass_n<SR_FFT_N>(int kind, bool col, int B, const PassArgs& a, hipStream_t s) {
+  constexpr int N = SR_FFT_N;
+  if (col) {
+    switch (B) {
+      case 4:
+        if constexpr (Cfg::col_ok(4)) return dispatch<N, true, 4>(kind, a, s);
+        break;
+      case 8:
+        if constexpr (Cfg::col_ok(8)) return dispatch<N, true, 8>(kind, a, s);
+        break;
+      case 16:
+        if constexpr (Cfg::col_ok(16)) return dispatch<N, true, 16>(kind, a, s);
+        break;
+      default:
+        break;
+    }
+    return hipErrorInvalidValue;
+  }
+  if (B == Cfg::ROW_SMALL) return dispatch<N, false, Cfg::ROW_SMALL>(kind, a, s);
+  if constexpr (Cfg::ROW_BIG != Cfg::ROW_SMALL) {
+    if (B == Cfg::ROW_BIG) return dispatch<N, false, Cfg::ROW_BIG>(kind, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace sr

@@ -1,0 +1,124 @@
+// Plan construction: geometry offsets, FFT twiddle tables, workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <set>
+#include <vector>
+
+#include "launch.hpp"
+#include "plan.hpp"
+
+using sr::Geo;
+
+namespace {
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+}  // namespace
+
+sr_status sr_plan_s::init(const float* theta_host) {
+  const size_t np = geo.size();
+  xoff.assign(np + 1, 0);
+  yoff.assign(np + 1, 0);
+  for (size_t i = 0; i < np; ++i) {
+    xoff[i + 1] = xoff[i] + geo[i].n;
+    yoff[i + 1] = yoff[i] + geo[i].m;
+  }
+
+  // twiddle tables exp(-2 pi i e/N), evaluated in float64 and rounded once
+  std::set<int> lens;
+  int64_t max_m = 0;
+  int cap = 1;
+  for (const Geo& g : geo) {
+    max_m = std::max(max_m, g.m);
+    if (kind != SR_STRUCTURED) continue;
+    lens.insert(g.M1);
+    if (g.ndim == 2) lens.insert(g.M2);
+  }
+  size_t tw_elems = 0;
+  for (int N : lens) tw_elems += N;
+  std::vector<float2> host_tw(tw_elems);
+  {
+    size_t o = 0;
+    for (int N : lens) {
+      for (int e = 0; e < N; ++e) {
+        const double ang = -2.0 * M_PI * (double)e / (double)N;
+        host_tw[o + e] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+      }
+      o += N;
+    }
+  }
+
+  // partial sums: one per workgroup of any pass (at most one per transform)
+  for (const Geo& g : geo) cap = std::max<int>(cap, (int)std::max(g.M1, g.M2) + 1);
+  part_cap = std::max(cap, 64);
+  int64_t grid_elems = (kind == SR_DENSE) ? (int64_t)max_m * (int64_t)np : max_m;
+  size_t b_theta = align256(sizeof(float) * (size_t)std::max<int64_t>(theta_len, 0));
+  size_t b_tw = align256(sizeof(float2) * tw_elems);
+  size_t b_grid = align256(sizeof(float2) * (size_t)grid_elems);
+  size_t b_part = align256(sizeof(float) * 2 * (size_t)part_cap);
+  size_t b_ysum = align256(sizeof(double) * (np + 8));
+  size_t b_fs = align256(sizeof(float) * (8 * np + 64));
+  size_t b_sync = 256;
+  int ngrid = (kind == SR_DENSE) ? 2 : 4;
+  ws_bytes = b_theta + b_tw + ngrid * b_grid + b_part + b_ysum + b_fs + b_sync;
+  hipError_t e = hipMalloc(&ws, ws_bytes);
+  if (e != hipSuccess) {
+    ws = nullptr;
+    return sr::fail(SR_E_NOMEM, std::string("workspace allocation failed: ") + hipGetErrorString(e));
+  }
+  char* c = (char*)ws;
+  theta = theta_len > 0 ? (float*)c : nullptr;
+  c += b_theta;
+  twbuf = (float2*)c;
+  c += b_tw;
+  bufA = (float2*)c;
+  c += b_grid;
+  bufB = (float2*)c;
+  c += b_grid;
+  if (ngrid == 4) {
+    bufC = (float2*)c;
+    c += b_grid;
+    bufD = (float2*)c;
+    c += b_grid;
+  }
+  part = (float*)c;
+  c += b_part;
+  ysum = (double*)c;
+  c += b_ysum;
+  fscratch = (float*)c;
+  c += b_fs;
+  sync = (unsigned*)c;
+
+  size_t o = 0;
+  for (int N : lens) {
+    tw[N] = twbuf + o;
+    o += N;
+  }
+  if (tw_elems) {
+    e = hipMemcpy(twbuf, host_tw.data(), sizeof(float2) * tw_elems, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return sr::hip_fail(e, "twiddle upload");
+  }
+  if (theta_len > 0) {
+    e = hipMemcpy(theta, theta_host, sizeof(float) * theta_len, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return sr::hip_fail(e, "theta upload");
+  }
+  // the tuner runs iterations on zeroed stand-in data in bufC / bufD
+  if (bufC != nullptr) {
+    e = hipMemset(bufC, 0, 2 * b_grid);
+    if (e != hipSuccess) return sr::hip_fail(e, "workspace clear");
+  }
+  e = hipMemset(sync, 0, b_sync);
+  if (e != hipSuccess) return sr::hip_fail(e, "workspace clear");
+  e = hipMemset(part, 0, b_part);
+  if (e != hipSuccess) return sr::hip_fail(e, "workspace clear");
+  return SR_OK;
+}
+
+const float2* sr_plan_s::twiddles(int N) const {
+  auto it = tw.find(N);
+  return it == tw.end() ? nullptr : it->second;
+}
+
+sr_plan_s::~sr_plan_s() {
+  if (ws) hipFree(ws);
+}

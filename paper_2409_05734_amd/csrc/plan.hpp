@@ -1,0 +1,90 @@
+// Plan object shared by the host-side translation units of libsrpr.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/sr.h"
+
+namespace sr {
+
+// Geometry of one problem.  2D: signal N1 x N2 zero-padded into the centred
+// window (offsets o1, o2) of an M1 x M2 grid.  1D problems use N1, M1, o1 and
+// N2 = M2 = 1.
+struct Geo {
+  int ndim = 0;
+  int N1 = 1, N2 = 1, M1 = 1, M2 = 1;
+  int o1 = 0, o2 = 0;
+  int L = 0;
+  int64_t n = 0, m = 0;
+  int64_t th_off = 0;
+};
+
+sr_status fail(sr_status s, const std::string& msg);
+sr_status hip_fail(hipError_t e, const char* what);
+
+}  // namespace sr
+
+struct sr_plan_s {
+  std::vector<sr::Geo> geo;
+  int kind = SR_STRUCTURED;
+  hipStream_t stream = nullptr;
+  std::vector<int64_t> xoff, yoff;  // concatenation offsets (complex elements)
+
+  float* theta = nullptr;  // device copy of the phases
+  int64_t theta_len = 0;
+  const float2* dense_A = nullptr;  // caller-owned dense matrix (SR_DENSE)
+
+  std::map<int, float2*> tw;  // FFT length -> device twiddle table
+  float2* twbuf = nullptr;
+
+  // workspace carved out of one allocation
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  float2* bufA = nullptr;  // ping-pong pass buffers (max m complex each)
+  float2* bufB = nullptr;
+  float2* bufC = nullptr;  // extra grid buffers for derivatives
+  float2* bufD = nullptr;
+  float* part = nullptr;   // 2 x part_cap partial sums
+  int part_cap = 0;
+  double* ysum = nullptr;  // sum(y) scratch (per problem)
+  float* fscratch = nullptr;  // float scratch (dense solver scalars)
+  unsigned* sync = nullptr;   // [0] grid-barrier counter, [1] barrier error flag
+
+  int schedule = SR_SCHED_AUTO;
+  std::map<std::pair<int, int>, int> tiles;  // (FFT length, column mode) -> tuned tile width
+
+  int tile(int N, bool col) const {
+    auto it = tiles.find({N, col ? 1 : 0});
+    return it == tiles.end() ? 0 : it->second;
+  }
+
+  sr_status init(const float* theta_host);
+  const float2* twiddles(int N) const;
+  const float* theta_l(const sr::Geo& g, int l) const;
+  ~sr_plan_s();
+};
+
+namespace sr {
+
+// util_kernels.hip
+sr_status reduce_partials(sr_plan_s* p, const float* part, int n, float* out);
+sr_status sum_floats(sr_plan_s* p, const float* y, int64_t n, double* out);
+sr_status norm2_partial(sr_plan_s* p, const float2* x, int64_t n, float* out);
+sr_status final_scale(sr_plan_s* p, float2* x, int64_t n, const float* part, int npart, const double* ysum,
+                      float inv_mc);
+
+// dense.hip (i.i.d. complex Gaussian baseline)
+sr_status dense_forward(sr_plan_s* p, const float2* x, float2* z, float* y);
+sr_status dense_adjoint(sr_plan_s* p, const float2* r, float2* x);
+sr_status dense_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta, float* loss_trace);
+sr_status dense_spectral(sr_plan_s* p, const float* y, const float2* v0, int iters, float lam, float2* x0);
+
+// vjp.hip (reverse-mode derivatives of A and A^H)
+sr_status vjp_forward(sr_plan_s* p, const float2* x, const float2* gz, float2* gx, float* gtheta);
+sr_status vjp_adjoint(sr_plan_s* p, const float2* r, const float2* gv, float2* gr, float* gtheta);
+
+}  // namespace sr

@@ -1,0 +1,751 @@
+// C ABI of libsrpr: plan creation and validation, pass scheduling for the
+// structured operator (section III, Eq. (5)), the spectral initialisation
+// (section II-B.2, Eq. (3)-(4)) and gradient descent (section II-B.1, Eq. (2)).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sr.h"
+#include "fused1d.hpp"
+#include "launch.hpp"
+#include "persist.hpp"
+#include "plan.hpp"
+
+using sr::Geo;
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+namespace sr {
+
+sr_status fail(sr_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+sr_status hip_fail(hipError_t e, const char* what) {
+  return fail(SR_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool supported_len_2d(int M) {
+  switch (M) {
+    case 32: case 64: case 96: case 128: case 192: case 256: case 384: case 512: case 768: case 1024: case 2048:
+      return true;
+    default:
+      return false;
+  }
+}
+
+bool supported_len_1d(int M) {
+  switch (M) {
+    case 32: case 64: case 96: case 128: case 192: case 256: case 384: case 512: case 768: case 1024: case 2048:
+    case 4096:
+      return true;
+    default:
+      return false;
+  }
+}
+
+}  // namespace sr
+
+using namespace sr;
+
+#define SR_HIP(call)                                  \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+#define SR_CHECK(st)                  \
+  do {                                \
+    sr_status s_ = (st);              \
+    if (s_ != SR_OK) return s_;       \
+  } while (0)
+
+// ------------------------------------------------------------------ helpers
+
+static int pass_col(int k) { return (k % 2) == 1; }  // forward pass k (1-based): odd -> axis 0
+static int pass_len(const Geo& g, int k) { return pass_col(k) ? g.M1 : g.M2; }
+
+static PassArgs base_args(const sr_plan_s* p, const Geo& g, int k) {
+  PassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.grid_ld = g.M2;
+  a.tw = p->twiddles(pass_len(g, k));
+  a.scale_pre = 1.f;
+  a.scale_mid = 1.f;
+  a.scale_out = 1.f;
+  a.inv_m = 1.f / (float)g.m;
+  return a;
+}
+
+// Buffer layouts between passes.  "Compact" buffers hold only the N2 support
+// columns (M1 x N2, row-major); "full" buffers hold the whole M1 x M2 grid.
+// The output of forward pass 1 and the input of the last adjoint pass are
+// compact; every other intermediate is full.
+
+// Row-mode input from a compact buffer (pass 2 reads the output of pass 1).
+static void in_compact(PassArgs& a, const Geo& g, const float2* buf) {
+  a.in = buf;
+  a.in_ld = g.N2;
+  a.in_lo = g.o2;
+  a.in_hi = g.o2 + g.N2;
+  a.ntr = g.M1;
+  a.tr_lo = 0;
+}
+
+// Input from a full grid buffer, for a pass on the axis of forward pass k.
+static void in_full(PassArgs& a, const Geo& g, int k, const float2* buf) {
+  a.in = buf;
+  a.in_ld = g.M2;
+  a.in_lo = 0;
+  a.in_hi = pass_len(g, k);
+  a.ntr = pass_col(k) ? g.M2 : g.M1;
+  a.tr_lo = 0;
+}
+
+// Input of forward pass k >= 2 (the output of pass k-1).
+static void set_in(PassArgs& a, const Geo& g, int k, const float2* buf) {
+  if (k == 2) in_compact(a, g, buf);
+  else in_full(a, g, k, buf);
+}
+
+// Output of a pass on the axis of pass k: compact for k == 2, full otherwise.
+static void set_out(PassArgs& a, const Geo& g, int k, float2* buf) {
+  a.out = buf;
+  if (k == 2) {
+    a.out_ld = g.N2;
+    a.out_lo = g.o2;
+    a.out_hi = g.o2 + g.N2;
+  } else {
+    a.out_ld = g.M2;
+    a.out_lo = 0;
+    a.out_hi = pass_len(g, k);
+  }
+}
+
+static void out_full(PassArgs& a, const Geo& g, int k, float2* buf) {
+  a.out = buf;
+  a.out_ld = g.M2;
+  a.out_lo = 0;
+  a.out_hi = pass_len(g, k);
+}
+
+// Launch one fused pass, or, while a persistent schedule is being recorded,
+// append it to the recording instead.
+struct PassRecord {
+  int k, kind;
+  PassArgs a;
+};
+static std::vector<PassRecord>* g_recording = nullptr;
+
+static sr_status launch(sr_plan_s* p, const Geo& g, int k, int kind, const PassArgs& a) {
+  if (g_recording != nullptr) {
+    g_recording->push_back({k, kind, a});
+    return SR_OK;
+  }
+  const int N = pass_len(g, k);
+  const bool col = pass_col(k);
+  hipError_t e = launch_pass(N, kind, col, p->tile(N, col), a, p->stream);
+  if (e != hipSuccess) return hip_fail(e, "pass launch");
+  return SR_OK;
+}
+
+const float* sr_plan_s::theta_l(const Geo& g, int l) const { return theta + g.th_off + (int64_t)(l - 1) * g.m; }
+
+// Forward passes 1..L (through D_L's first transform), starting from x.
+// Returns the buffer holding the result (compact if L == 1, else full).
+static sr_status forward_body(sr_plan_s* p, const Geo& g, const float2* x, float in_scale, const float* part_in,
+                              int npart, float2** cur_out) {
+  float2* bufs[2] = {p->bufA, p->bufB};
+  int which = 0;
+  {
+    PassArgs a = base_args(p, g, 1);
+    a.in = x;
+    a.in_ld = g.N2;
+    a.in_lo = g.o1;
+    a.in_hi = g.o1 + g.N1;
+    a.ntr = g.N2;
+    a.tr_lo = g.o2;
+    a.th_pre = p->theta_l(g, 1);
+    a.scale_pre = in_scale;
+    a.part_in = part_in;
+    a.npart = npart;
+    a.out = bufs[which];
+    a.out_ld = g.N2;
+    a.out_lo = 0;
+    a.out_hi = g.M1;
+    a.scale_out = 1.f / std::sqrt((float)g.M1);
+    SR_CHECK(launch(p, g, 1, PK_FIRST_FWD, a));
+  }
+  for (int k = 2; k <= g.L; ++k) {
+    PassArgs a = base_args(p, g, k);
+    set_in(a, g, k, bufs[which]);
+    out_full(a, g, k, bufs[which ^ 1]);
+    a.th_mid = p->theta_l(g, k);
+    const float s = 1.f / std::sqrt((float)pass_len(g, k));
+    a.scale_mid = s;
+    a.scale_out = s;
+    SR_CHECK(launch(p, g, k, PK_MID_FWD, a));
+    which ^= 1;
+  }
+  *cur_out = bufs[which];
+  return SR_OK;
+}
+
+// Adjoint passes L..1 starting from `cur` (layout of the output of pass L+1's
+// mirror: compact if L == 1, full otherwise), ending with the column pass that
+// applies D_1^*, crops, and performs `last_kind` into x.
+static sr_status adjoint_body(sr_plan_s* p, const Geo& g, float2* cur, int last_kind, float2* x, float step,
+                              float two_lam, const float* part_in, int npart, float* part_out) {
+  float2* other = (cur == p->bufA) ? p->bufB : p->bufA;
+  for (int k = g.L; k >= 2; --k) {
+    PassArgs a = base_args(p, g, k);
+    in_full(a, g, k, cur);
+    set_out(a, g, k, other);
+    a.th_mid = p->theta_l(g, k);
+    const float s = 1.f / std::sqrt((float)pass_len(g, k));
+    a.scale_mid = s;
+    a.scale_out = s;
+    SR_CHECK(launch(p, g, k, PK_MID_ADJ, a));
+    std::swap(cur, other);
+  }
+  PassArgs a = base_args(p, g, 1);
+  a.in = cur;
+  a.in_ld = g.N2;
+  a.in_lo = 0;
+  a.in_hi = g.M1;
+  a.ntr = g.N2;
+  a.tr_lo = g.o2;
+  a.out = x;
+  a.out_ld = g.N2;
+  a.out_lo = g.o1;
+  a.out_hi = g.o1 + g.N1;
+  a.th_post = p->theta_l(g, 1);
+  a.scale_out = 1.f / std::sqrt((float)g.M1);
+  a.step = step;
+  a.two_lam = two_lam;
+  a.part_in = part_in;
+  a.npart = npart;
+  a.part_out = part_out;
+  return launch(p, g, 1, last_kind, a);
+}
+
+// The turnaround pass (index L+1): from the forward result `cur` through the
+// epilogue and back; writes into the other ping-pong buffer.
+static sr_status turnaround(sr_plan_s* p, const Geo& g, float2* cur, int kind, const float* y, float lam,
+                            const double* ysum, float* part_out, float2** out) {
+  const int k = g.L + 1;
+  float2* other = (cur == p->bufA) ? p->bufB : p->bufA;
+  PassArgs a = base_args(p, g, k);
+  set_in(a, g, k, cur);
+  set_out(a, g, k, other);
+  const float s = 1.f / std::sqrt((float)pass_len(g, k));
+  a.scale_mid = s;
+  a.scale_out = s;
+  a.y = y;
+  a.lam = lam;
+  a.ysum = ysum;
+  a.part_out = part_out;
+  SR_CHECK(launch(p, g, k, kind, a));
+  *out = other;
+  return SR_OK;
+}
+
+// --------------------------------------------------------------- 2D drivers
+
+static sr_status forward_2d(sr_plan_s* p, const Geo& g, const float2* x, float2* z, float* y) {
+  float2* cur = nullptr;
+  SR_CHECK(forward_body(p, g, x, 1.f, nullptr, 0, &cur));
+  const int k = g.L + 1;
+  PassArgs a = base_args(p, g, k);
+  set_in(a, g, k, cur);
+  a.scale_mid = 1.f / std::sqrt((float)pass_len(g, k));
+  a.z_out = z;
+  a.y_out = y;
+  return launch(p, g, k, PK_LAST_STORE, a);
+}
+
+static sr_status adjoint_2d(sr_plan_s* p, const Geo& g, const float2* r, float2* x) {
+  const int k = g.L + 1;
+  PassArgs a = base_args(p, g, k);
+  in_full(a, g, k, r);
+  set_out(a, g, k, p->bufA);
+  a.scale_out = 1.f / std::sqrt((float)pass_len(g, k));
+  SR_CHECK(launch(p, g, k, PK_FIRST_ADJ, a));
+  return adjoint_body(p, g, p->bufA, PK_LAST_ADJ, x, 0.f, 0.f, nullptr, 0, nullptr);
+}
+
+static sr_status gd_iter_2d(sr_plan_s* p, const Geo& g, const float* y, float2* x, float step, float* loss_part) {
+  float2* cur = nullptr;
+  SR_CHECK(forward_body(p, g, x, 1.f, nullptr, 0, &cur));
+  float2* back = nullptr;
+  SR_CHECK(turnaround(p, g, cur, PK_TURN_GD, y, 0.f, nullptr, loss_part, &back));
+  return adjoint_body(p, g, back, PK_LAST_GD, x, step, 0.f, nullptr, 0, nullptr);
+}
+
+static sr_status spec_iter_2d(sr_plan_s* p, const Geo& g, const float* y, float2* u, float lam, float inv_mc,
+                              const double* ysum, const float* part_in, int npart_in, float* part_out) {
+  float2* cur = nullptr;
+  SR_CHECK(forward_body(p, g, u, 1.f, part_in, npart_in, &cur));
+  float2* back = nullptr;
+  SR_CHECK(turnaround(p, g, cur, PK_TURN_SPEC, y, lam, ysum, nullptr, &back));
+  return adjoint_body(p, g, back, PK_LAST_SPEC, u, inv_mc, 2.f * lam, part_in, npart_in, part_out);
+}
+
+static int last_pass_groups(const sr_plan_s* p, const Geo& g) { return pass_groups(g.M1, true, p->tile(g.M1, true), g.N2); }
+static int turn_groups(const sr_plan_s* p, const Geo& g) {
+  const int k = g.L + 1;
+  const int ntr = (k == 2) ? g.M1 : (pass_col(k) ? g.M2 : g.M1);
+  const int N = pass_len(g, k);
+  return pass_groups(N, pass_col(k), p->tile(N, pass_col(k)), ntr);
+}
+
+// ------------------------------------------------------------------ tuner
+// Picks the tile width of every (FFT length, mode) a plan uses by timing one
+// GD iteration of each 2D problem shape for every combination of the
+// compiled column- and row-tile widths (on zeroed stand-in data in the
+// plan's spare buffers), keeping the fastest.  SR_TUNE=0 keeps the defaults;
+// SR_TUNE_CACHE=<file> reuses and records decisions across processes.
+
+static std::string tune_key(const Geo& g) {
+  return std::to_string(g.M1) + "x" + std::to_string(g.M2) + ":" + std::to_string(g.N1) + "x" +
+         std::to_string(g.N2) + ":L" + std::to_string(g.L);
+}
+
+static bool tune_cache_lookup(const char* path, const std::string& key, int* cb, int* rb) {
+  if (path == nullptr) return false;
+  FILE* f = std::fopen(path, "r");
+  if (f == nullptr) return false;
+  char k[128];
+  int c = 0, r = 0;
+  bool found = false;
+  while (std::fscanf(f, "%127s %d %d", k, &c, &r) == 3)
+    if (key == k) {
+      *cb = c;
+      *rb = r;
+      found = true;
+    }
+  std::fclose(f);
+  return found;
+}
+
+static void tune_cache_store(const char* path, const std::string& key, int cb, int rb) {
+  if (path == nullptr) return;
+  FILE* f = std::fopen(path, "a");
+  if (f == nullptr) return;
+  std::fprintf(f, "%s %d %d\n", key.c_str(), cb, rb);
+  std::fclose(f);
+}
+
+static sr_status tune_plan(sr_plan_s* p) {
+  const char* env = std::getenv("SR_TUNE");
+  if (env != nullptr && std::atoi(env) == 0) return SR_OK;
+  const char* cache = std::getenv("SR_TUNE_CACHE");
+  std::vector<std::string> done;
+  for (const Geo& g : p->geo) {
+    if (g.ndim != 2) continue;
+    const std::string key = tune_key(g);
+    if (std::find(done.begin(), done.end(), key) != done.end()) continue;
+    done.push_back(key);
+    if (p->tiles.count({g.M1, 1}) && p->tiles.count({g.M2, 0})) continue;  // decided by an earlier shape
+    int cb = 0, rb = 0;
+    if (!tune_cache_lookup(cache, key, &cb, &rb)) {
+      int copt[8], ropt[8];
+      const int nc = tile_options(g.M1, true, copt, 8);
+      const int nr = tile_options(g.M2, false, ropt, 8);
+      float best = 1e30f;
+      hipEvent_t e0, e1;
+      SR_HIP(hipEventCreate(&e0));
+      SR_HIP(hipEventCreate(&e1));
+      float2* x = p->bufC;
+      const float* y = (const float*)p->bufD;
+      for (int i = 0; i < nc; ++i)
+        for (int j = 0; j < nr; ++j) {
+          p->tiles[{g.M1, 1}] = copt[i];
+          p->tiles[{g.M2, 0}] = ropt[j];
+          for (int w = 0; w < 3; ++w) SR_CHECK(gd_iter_2d(p, g, y, x, 0.f, nullptr));
+          SR_HIP(hipEventRecord(e0, p->stream));
+          for (int w = 0; w < 10; ++w) SR_CHECK(gd_iter_2d(p, g, y, x, 0.f, nullptr));
+          SR_HIP(hipEventRecord(e1, p->stream));
+          SR_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          SR_HIP(hipEventElapsedTime(&ms, e0, e1));
+          if (ms < best) {
+            best = ms;
+            cb = copt[i];
+            rb = ropt[j];
+          }
+        }
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      tune_cache_store(cache, key, cb, rb);
+    }
+    p->tiles[{g.M1, 1}] = cb;
+    p->tiles[{g.M2, 0}] = rb;
+  }
+  return SR_OK;
+}
+
+// ------------------------------------------------- persistent (one launch)
+
+// Tile width of the persistent kernels (SR_PERSIST_B overrides; 0 disables).
+static int persist_b() {
+  const char* e = std::getenv("SR_PERSIST_B");
+  if (e != nullptr) return std::atoi(e);
+  return 0;  // grid barriers cost more than kernel boundaries on this path; opt-in
+}
+
+static bool use_persistent(const sr_plan_s* p, const Geo& g) {
+  if (p->schedule == SR_SCHED_LOOP) return false;
+  if (g.ndim != 2 || g.M1 != g.M2 || g.L > (kMaxPersistPasses - 1) / 2) return false;
+  return persistent_supported(g.M1, persist_b());
+}
+
+// Record one iteration's passes (with `record`) and run `iters` iterations of
+// them in one cooperative launch.
+template <class F>
+static sr_status run_persistent(sr_plan_s* p, const Geo& g, int op, int iters, F&& record, float* loss_trace,
+                                int npart0) {
+  std::vector<PassRecord> rec;
+  g_recording = &rec;
+  sr_status st = record();
+  g_recording = nullptr;
+  SR_CHECK(st);
+  if ((int)rec.size() > kMaxPersistPasses) return fail(SR_E_UNSUPPORTED, "too many passes for one launch");
+  const int B = persist_b();
+  PersistArgs pa;
+  std::memset(&pa, 0, sizeof(pa));
+  int max_tiles = 1;
+  pa.loss_pass = -1;
+  for (size_t i = 0; i < rec.size(); ++i) {
+    pa.pass[i] = rec[i].a;
+    pa.kind[i] = rec[i].kind;
+    pa.col[i] = pass_col(rec[i].k);
+    max_tiles = std::max(max_tiles, (rec[i].a.ntr + B - 1) / B);
+    if (rec[i].kind == PK_TURN_GD) pa.loss_pass = (int)i;
+    if (rec[i].kind == PK_TURN_GD) pa.loss_nparts = (rec[i].a.ntr + B - 1) / B;
+    if (rec[i].kind == PK_LAST_SPEC) pa.npart_iter = (rec[i].a.ntr + B - 1) / B;
+  }
+  if (max_tiles > p->part_cap) return fail(SR_E_UNSUPPORTED, "partial-sum buffer too small for the persistent tile");
+  pa.npass = (int)rec.size();
+  pa.iters = iters;
+  pa.bar = p->sync;
+  pa.err = (int*)(p->sync + 1);
+  pa.part_base = p->part;
+  pa.part_cap = p->part_cap;
+  pa.npart0 = npart0;
+  pa.loss_trace = loss_trace;
+  hipError_t e = launch_persistent(g.M1, B, op, pa, max_tiles, p->stream);
+  if (e != hipSuccess) return hip_fail(e, "persistent launch");
+  return SR_OK;
+}
+
+// ------------------------------------------------------------ 1D (fused)
+
+static sr_status fused_1d(sr_plan_s* p, const Geo& g, int op, Fused1DArgs a) {
+  a.n = g.N1;
+  a.m = g.M1;
+  a.L = g.L;
+  a.off = g.o1;
+  a.theta = p->theta_l(g, 1);
+  a.tw = p->twiddles(g.M1);
+  hipError_t e = launch_fused1d(g.M1, op, a, p->stream);
+  if (e != hipSuccess) return hip_fail(e, "fused 1D launch");
+  return SR_OK;
+}
+
+// ====================================================================== ABI
+
+extern "C" {
+
+const char* sr_status_string(sr_status s) {
+  switch (s) {
+    case SR_OK: return "ok";
+    case SR_E_ARG: return "invalid argument";
+    case SR_E_SHAPE: return "inconsistent shape";
+    case SR_E_UNSUPPORTED: return "unsupported configuration";
+    case SR_E_HIP: return "HIP runtime error";
+    case SR_E_NONFINITE: return "non-finite value";
+    case SR_E_STATE: return "call not valid for this plan";
+    case SR_E_NOMEM: return "out of device memory";
+    default: return "unknown status";
+  }
+}
+
+const char* sr_last_error(void) { return g_last_error.c_str(); }
+
+sr_status sr_plan_create(sr_plan* out, const sr_problem* probs, int32_t nprob, const float* theta_host,
+                         int64_t theta_len, const void* dense_A, void* hip_stream) {
+  g_last_error.clear();
+  if (out == nullptr) return fail(SR_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (probs == nullptr || nprob <= 0) return fail(SR_E_ARG, "need at least one problem");
+  const int kind = probs[0].kind;
+  if (kind != SR_STRUCTURED && kind != SR_DENSE) return fail(SR_E_ARG, "unknown problem kind");
+  std::vector<Geo> geo(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    const sr_problem& q = probs[i];
+    Geo& g = geo[i];
+    if (q.kind != kind) return fail(SR_E_ARG, "all problems of a plan must have the same kind");
+    if (q.ndim != 1 && q.ndim != 2) return fail(SR_E_ARG, "ndim must be 1 or 2");
+    g.ndim = q.ndim;
+    g.N1 = q.n[0];
+    g.M1 = q.m[0];
+    g.N2 = q.ndim == 2 ? q.n[1] : 1;
+    g.M2 = q.ndim == 2 ? q.m[1] : 1;
+    if (g.N1 < 1 || g.N2 < 1) return fail(SR_E_SHAPE, "signal sizes must be positive");
+    if (g.M1 < g.N1 || g.M2 < g.N2) return fail(SR_E_SHAPE, "measurement grid smaller than the signal (alpha < 1)");
+    g.o1 = (g.M1 - g.N1) / 2;
+    g.o2 = (g.M2 - g.N2) / 2;
+    g.n = (int64_t)g.N1 * g.N2;
+    g.m = (int64_t)g.M1 * g.M2;
+    g.L = q.layers;
+    g.th_off = q.theta_offset;
+    if (kind == SR_STRUCTURED) {
+      if (g.L < 1 || g.L > 16) return fail(SR_E_ARG, "layers must be in [1, 16]");
+      if (g.th_off < 0 || g.th_off + (int64_t)g.L * g.m > theta_len)
+        return fail(SR_E_SHAPE, "problem " + std::to_string(i) + ": theta block out of range");
+      if (q.ndim == 1) {
+        if (!supported_len_1d(g.M1)) return fail(SR_E_UNSUPPORTED, "unsupported 1D length " + std::to_string(g.M1));
+        if ((int64_t)g.L * g.M1 > kFused1DPhaseSlots) return fail(SR_E_UNSUPPORTED, "1D problems need L*m <= 4096");
+      } else {
+        if (!supported_len_2d(g.M1) || !supported_len_2d(g.M2))
+          return fail(SR_E_UNSUPPORTED, "unsupported 2D grid " + std::to_string(g.M1) + "x" + std::to_string(g.M2));
+      }
+    } else {
+      if (i > 0 && (g.n != geo[0].n || g.m != geo[0].m))
+        return fail(SR_E_SHAPE, "dense problems of one plan share one matrix and must have one shape");
+    }
+  }
+  if (kind == SR_STRUCTURED) {
+    if (theta_host == nullptr || theta_len <= 0) return fail(SR_E_ARG, "theta is required for structured plans");
+    if (dense_A != nullptr) return fail(SR_E_ARG, "dense_A must be NULL for structured plans");
+  } else {
+    if (dense_A == nullptr) return fail(SR_E_ARG, "dense_A is required for dense plans");
+    if (theta_host != nullptr || theta_len != 0) return fail(SR_E_ARG, "theta must be NULL for dense plans");
+  }
+
+  sr_plan_s* p = new (std::nothrow) sr_plan_s();
+  if (p == nullptr) return fail(SR_E_NOMEM, "host allocation failed");
+  p->geo = geo;
+  p->kind = kind;
+  p->stream = (hipStream_t)hip_stream;
+  p->theta_len = theta_len;
+  p->dense_A = (const float2*)dense_A;
+  sr_status st = p->init(theta_host);
+  if (st == SR_OK && kind == SR_STRUCTURED) st = tune_plan(p);
+  if (st != SR_OK) {
+    delete p;
+    return st;
+  }
+  *out = p;
+  return SR_OK;
+}
+
+sr_status sr_plan_set_theta(sr_plan p, const float* theta_dev, int64_t theta_len) {
+  if (p == nullptr || theta_dev == nullptr) return fail(SR_E_ARG, "NULL argument");
+  if (p->kind != SR_STRUCTURED) return fail(SR_E_STATE, "dense plans have no phases");
+  if (theta_len != p->theta_len) return fail(SR_E_SHAPE, "theta length differs from the plan's");
+  SR_HIP(hipMemcpyAsync(p->theta, theta_dev, sizeof(float) * theta_len, hipMemcpyDeviceToDevice, p->stream));
+  return SR_OK;
+}
+
+sr_status sr_plan_workspace_size(sr_plan p, size_t* bytes) {
+  if (p == nullptr || bytes == nullptr) return fail(SR_E_ARG, "NULL argument");
+  *bytes = p->ws_bytes;
+  return SR_OK;
+}
+
+sr_status sr_plan_offsets(sr_plan p, int64_t* x_off, int64_t* y_off) {
+  if (p == nullptr) return fail(SR_E_ARG, "NULL plan");
+  const size_t np = p->geo.size();
+  for (size_t i = 0; i <= np; ++i) {
+    if (x_off) x_off[i] = p->xoff[i];
+    if (y_off) y_off[i] = p->yoff[i];
+  }
+  return SR_OK;
+}
+
+sr_status sr_plan_set_schedule(sr_plan p, int32_t schedule) {
+  if (p == nullptr) return fail(SR_E_ARG, "NULL plan");
+  if (schedule < SR_SCHED_AUTO || schedule > SR_SCHED_BATCHED) return fail(SR_E_ARG, "unknown schedule");
+  p->schedule = schedule;
+  return SR_OK;
+}
+
+sr_status sr_plan_sync(sr_plan p) {
+  if (p == nullptr) return fail(SR_E_ARG, "NULL plan");
+  SR_HIP(hipStreamSynchronize(p->stream));
+  int err = 0;
+  SR_HIP(hipMemcpy(&err, p->sync + 1, sizeof(int), hipMemcpyDeviceToHost));
+  if (err != 0) {
+    int zero = 0;
+    hipMemcpy(p->sync + 1, &zero, sizeof(int), hipMemcpyHostToDevice);
+    return fail(SR_E_HIP, "a grid-wide barrier wait exceeded its bound; results of that solve are invalid");
+  }
+  return SR_OK;
+}
+
+sr_status sr_plan_destroy(sr_plan p) {
+  if (p == nullptr) return SR_OK;
+  hipStreamSynchronize(p->stream);
+  delete p;
+  return SR_OK;
+}
+
+sr_status sr_forward(sr_plan p, const void* x, void* z, float* y) {
+  if (p == nullptr || x == nullptr) return fail(SR_E_ARG, "NULL argument");
+  if (z == nullptr && y == nullptr) return fail(SR_E_ARG, "need z or y");
+  const float2* xs = (const float2*)x;
+  float2* zs = (float2*)z;
+  if (p->kind == SR_DENSE) return dense_forward(p, xs, zs, y);
+  for (size_t i = 0; i < p->geo.size(); ++i) {
+    const Geo& g = p->geo[i];
+    const float2* xi = xs + p->xoff[i];
+    float2* zi = zs ? zs + p->yoff[i] : nullptr;
+    float* yi = y ? y + p->yoff[i] : nullptr;
+    if (g.ndim == 1) {
+      Fused1DArgs a{};
+      a.x_in = xi;
+      a.z_out = zi;
+      a.y_out = yi;
+      SR_CHECK(fused_1d(p, g, F1_FORWARD, a));
+    } else {
+      SR_CHECK(forward_2d(p, g, xi, zi, yi));
+    }
+  }
+  return SR_OK;
+}
+
+sr_status sr_adjoint(sr_plan p, const void* r, void* x_out) {
+  if (p == nullptr || r == nullptr || x_out == nullptr) return fail(SR_E_ARG, "NULL argument");
+  const float2* rs = (const float2*)r;
+  float2* xs = (float2*)x_out;
+  if (p->kind == SR_DENSE) return dense_adjoint(p, rs, xs);
+  for (size_t i = 0; i < p->geo.size(); ++i) {
+    const Geo& g = p->geo[i];
+    if (g.ndim == 1) {
+      Fused1DArgs a{};
+      a.r_in = rs + p->yoff[i];
+      a.x_out = xs + p->xoff[i];
+      SR_CHECK(fused_1d(p, g, F1_ADJOINT, a));
+    } else {
+      SR_CHECK(adjoint_2d(p, g, rs + p->yoff[i], xs + p->xoff[i]));
+    }
+  }
+  return SR_OK;
+}
+
+sr_status sr_gd_solve(sr_plan p, const float* y, void* x_inout, int32_t iters, const float* eta_host,
+                      float* loss_trace) {
+  if (p == nullptr || y == nullptr || x_inout == nullptr || eta_host == nullptr)
+    return fail(SR_E_ARG, "NULL argument");
+  if (iters < 0) return fail(SR_E_ARG, "iters must be >= 0");
+  for (size_t i = 0; i < p->geo.size(); ++i)
+    if (!std::isfinite(eta_host[i])) return fail(SR_E_NONFINITE, "step size is not finite");
+  if (iters == 0) return SR_OK;
+  float2* xs = (float2*)x_inout;
+  if (p->kind == SR_DENSE) return dense_gd(p, y, xs, iters, eta_host, loss_trace);
+  for (size_t i = 0; i < p->geo.size(); ++i) {
+    const Geo& g = p->geo[i];
+    const float* yi = y + p->yoff[i];
+    float2* xi = xs + p->xoff[i];
+    const float step = eta_host[i] / (float)g.m;
+    float* lt = loss_trace ? loss_trace + (int64_t)i * iters : nullptr;
+    if (g.ndim == 1) {
+      Fused1DArgs a{};
+      a.x_out = xi;
+      a.y = yi;
+      a.iters = iters;
+      a.step = step;
+      a.loss_trace = lt;
+      SR_CHECK(fused_1d(p, g, F1_GD, a));
+      continue;
+    }
+    if (use_persistent(p, g)) {
+      SR_CHECK(run_persistent(
+          p, g, PO_GD, iters, [&]() { return gd_iter_2d(p, g, yi, xi, step, lt ? p->part : nullptr); }, lt, 0));
+      continue;
+    }
+    const int nparts = turn_groups(p, g);
+    for (int it = 0; it < iters; ++it) {
+      SR_CHECK(gd_iter_2d(p, g, yi, xi, step, lt ? p->part : nullptr));
+      if (lt) SR_CHECK(reduce_partials(p, p->part, nparts, lt + it));
+    }
+  }
+  return SR_OK;
+}
+
+sr_status sr_spectral_init(sr_plan p, const float* y, const void* v0, int32_t iters, float lambda, void* x0_out) {
+  if (p == nullptr || y == nullptr || v0 == nullptr || x0_out == nullptr) return fail(SR_E_ARG, "NULL argument");
+  if (iters < 0) return fail(SR_E_ARG, "iters must be >= 0");
+  if (!(lambda < 0.f) || !std::isfinite(lambda)) return fail(SR_E_ARG, "lambda must be finite and negative");
+  if (v0 == x0_out) return fail(SR_E_ARG, "x0_out must not alias v0");
+  const float2* vs = (const float2*)v0;
+  float2* xs = (float2*)x0_out;
+  if (p->kind == SR_DENSE) return dense_spectral(p, y, vs, iters, lambda, xs);
+  for (size_t i = 0; i < p->geo.size(); ++i) {
+    const Geo& g = p->geo[i];
+    const float* yi = y + p->yoff[i];
+    const float2* vi = vs + p->xoff[i];
+    float2* xi = xs + p->xoff[i];
+    const float inv_mc = 1.f;  // structured: c = 1/m
+    if (g.ndim == 1) {
+      Fused1DArgs a{};
+      a.x_in = vi;
+      a.x_out = xi;
+      a.y = yi;
+      a.iters = iters;
+      a.step = inv_mc;
+      a.lam = lambda;
+      SR_CHECK(fused_1d(p, g, F1_SPECTRAL, a));
+      continue;
+    }
+    // sum(y), then u_0 = v0 with its squared-norm partial
+    SR_CHECK(sum_floats(p, yi, g.m, p->ysum));
+    SR_HIP(hipMemcpyAsync(xi, vi, sizeof(float2) * g.n, hipMemcpyDeviceToDevice, p->stream));
+    float* parts[2] = {p->part, p->part + p->part_cap};
+    SR_CHECK(norm2_partial(p, xi, g.n, parts[0]));
+    int npart = 1;
+    if (use_persistent(p, g) && iters > 0) {
+      SR_CHECK(run_persistent(
+          p, g, PO_SPEC, iters,
+          [&]() { return spec_iter_2d(p, g, yi, xi, lambda, inv_mc, p->ysum, parts[0], 1, parts[1]); }, nullptr, 1));
+      const int B = persist_b();
+      npart = (g.N2 + B - 1) / B;
+    } else {
+      const int nq = last_pass_groups(p, g);
+      for (int it = 0; it < iters; ++it) {
+        SR_CHECK(spec_iter_2d(p, g, yi, xi, lambda, inv_mc, p->ysum, parts[it & 1], npart, parts[(it + 1) & 1]));
+        npart = nq;
+      }
+    }
+    // x0 = sqrt(sum(y)/(m c)) u / ||u||
+    SR_CHECK(final_scale(p, xi, g.n, parts[iters & 1], npart, p->ysum, inv_mc));
+  }
+  return SR_OK;
+}
+
+sr_status sr_forward_vjp(sr_plan p, const void* x, const void* gz, void* gx_out, float* gtheta_accum) {
+  if (p == nullptr || x == nullptr || gz == nullptr || gtheta_accum == nullptr) return fail(SR_E_ARG, "NULL argument");
+  if (p->kind != SR_STRUCTURED) return fail(SR_E_STATE, "VJPs need a structured plan");
+  return vjp_forward(p, (const float2*)x, (const float2*)gz, (float2*)gx_out, gtheta_accum);
+}
+
+sr_status sr_adjoint_vjp(sr_plan p, const void* r, const void* gv, void* gr_out, float* gtheta_accum) {
+  if (p == nullptr || r == nullptr || gv == nullptr || gtheta_accum == nullptr) return fail(SR_E_ARG, "NULL argument");
+  if (p->kind != SR_STRUCTURED) return fail(SR_E_STATE, "VJPs need a structured plan");
+  return vjp_adjoint(p, (const float2*)r, (const float2*)gv, (float2*)gr_out, gtheta_accum);
+}
+
+}  // extern "C"

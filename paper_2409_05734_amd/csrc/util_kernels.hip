@@ -1,0 +1,98 @@
+// Small deterministic reductions and scalings used by the solvers: sum(y),
+// squared norms, reduction of per-workgroup partials, and the final scaling
+// of the spectral estimate (section II-B.2, Eq. (4)).
+#include <hip/hip_runtime.h>
+
+#include "fft_core.hpp"
+#include "plan.hpp"
+
+namespace sr {
+
+namespace {
+
+constexpr int kRedThreads = 1024;
+
+template <int NT>
+__device__ double block_sum_d(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// out = sum of part[0..n) in index order (one thread: order is fixed)
+__global__ void reduce_partials_kernel(const float* __restrict__ part, int n, float* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) acc += (double)part[i];
+    *out = (float)acc;
+  }
+}
+
+// out = sum(y) with one workgroup (fixed strided order + fixed tree)
+__global__ void __launch_bounds__(kRedThreads) sum_floats_kernel(const float* __restrict__ y, long long n,
+                                                                 double* out) {
+  __shared__ double red[kRedThreads];
+  double acc = 0.0;
+  for (long long i = threadIdx.x; i < n; i += kRedThreads) acc += (double)y[i];
+  const double s = block_sum_d<kRedThreads>(acc, red);
+  if (threadIdx.x == 0) *out = s;
+}
+
+__global__ void __launch_bounds__(kRedThreads) norm2_kernel(const float2* __restrict__ x, long long n, float* out) {
+  __shared__ double red[kRedThreads];
+  double acc = 0.0;
+  for (long long i = threadIdx.x; i < n; i += kRedThreads) {
+    const float2 v = x[i];
+    acc += (double)v.x * v.x + (double)v.y * v.y;
+  }
+  const double s = block_sum_d<kRedThreads>(acc, red);
+  if (threadIdx.x == 0) *out = (float)s;
+}
+
+// x *= sqrt(sum(y) * inv_mc) / ||x||, ||x||^2 = sum of the partials
+__global__ void final_scale_kernel(float2* x, long long n, const float* __restrict__ part, int npart,
+                                   const double* __restrict__ ysum, float inv_mc) {
+  double acc = 0.0;
+  for (int i = 0; i < npart; ++i) acc += (double)part[i];
+  const float sc = (float)(sqrt(*ysum * (double)inv_mc) / sqrt(acc));
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    x[i] = cscale(x[i], sc);
+}
+
+}  // namespace
+
+sr_status reduce_partials(sr_plan_s* p, const float* part, int n, float* out) {
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(64), 0, p->stream, part, n, out);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SR_OK : hip_fail(e, "reduce_partials");
+}
+
+sr_status sum_floats(sr_plan_s* p, const float* y, int64_t n, double* out) {
+  hipLaunchKernelGGL(sum_floats_kernel, dim3(1), dim3(kRedThreads), 0, p->stream, y, (long long)n, out);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SR_OK : hip_fail(e, "sum_floats");
+}
+
+sr_status norm2_partial(sr_plan_s* p, const float2* x, int64_t n, float* out) {
+  hipLaunchKernelGGL(norm2_kernel, dim3(1), dim3(kRedThreads), 0, p->stream, x, (long long)n, out);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SR_OK : hip_fail(e, "norm2");
+}
+
+sr_status final_scale(sr_plan_s* p, float2* x, int64_t n, const float* part, int npart, const double* ysum,
+                      float inv_mc) {
+  int groups = (int)std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(final_scale_kernel, dim3(groups), dim3(256), 0, p->stream, x, (long long)n, part, npart, ysum,
+                     inv_mc);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SR_OK : hip_fail(e, "final_scale");
+}
+
+}  // namespace sr

@@ -144,7 +144,7 @@ def image_2d(seed: int = 1, n_side: int = 256, layers: int = 2, photons: float =
         "theta": phase_masks(s["theta"], layers, m_shape),
         "v0": complex_gaussian(s["v0"], n_shape),
         "noise_rng": s["noise"], "photons": photons,
-        "lam": -1.0, "pi_iters": 100, "gd_iters": 500, "mu": 0.2,
+        "lam": -1.0, "pi_iters": 100, "gd_iters": 500, "mu": 0.05,
     }
 
 
