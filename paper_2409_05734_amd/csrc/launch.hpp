@@ -24,9 +24,9 @@ enum PassKind : int {
 
 // Tile widths: each length is compiled for a few tile widths (transforms per
 // workgroup) in each mode; the plan's tuner picks one per (length, mode).
-// Row mode: 1 wave or 4 waves per workgroup.  Column mode: 4, 8 or 16
-// adjacent columns (32-, 64- or 128-byte row segments), within 1024 threads
-// and the LDS budget (double-buffered tiles).
+// Row mode: 1 wave or 4 waves per workgroup.  Column mode: 2, 4, 8 or 16
+// adjacent columns (16- to 128-byte row segments), within 1024 threads and
+// the LDS budget (double-buffered tiles).
 template <int N>
 struct TileCfg {
   static constexpr int E = FftShape<N>::E;

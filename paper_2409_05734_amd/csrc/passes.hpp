@@ -41,6 +41,11 @@ struct PassArgs {
   const float* th_pre;
   const float* th_mid;
   const float* th_post;
+  // optional precomputed exp(i theta) tables for the same diagonals; when
+  // set they replace the phases (one 8-byte load instead of sincos)
+  const float2* ep_pre;
+  const float2* ep_mid;
+  const float2* ep_post;
   float scale_pre, scale_mid, scale_out;
   // epilogues
   const float* y;        // measurements on the grid (MID_GD, MID_SPEC)
@@ -101,26 +106,49 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
 
   // ---- issue every global load
   float2 v[E];
-  float thp[E];   // pre-diagonal phases
-  float thm[E];   // mid phases
+  float2 dp[E];   // pre-diagonal entries e^{i theta}
+  float2 dm[E];   // mid-diagonal entries
   float yv[E];    // measurements
-  float thq[E];   // post-diagonal phases
+  float2 dq[E];   // post-diagonal entries
   float2 xo[E];   // previous iterate
   typename T::Twiddles w;
   T::load_twiddles(w, a.tw, t);
+  const bool tab_pre = a.ep_pre != nullptr;
+  const bool tab_mid = a.ep_mid != nullptr;
+  const bool tab_post = a.ep_post != nullptr;
+  const float2 one = make_float2(1.f, 0.f);
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int k = T::elem(t, j);
     const bool iw = in_win(k);
     v[j] = iw ? a.in[in_addr(k)] : make_float2(0.f, 0.f);
-    if constexpr (PRE == PRE_PHASE) thp[j] = iw ? a.th_pre[gidx(k)] : 0.f;
-    if constexpr (MID_PH) thm[j] = active ? a.th_mid[gidx(k)] : 0.f;
+    if constexpr (PRE == PRE_PHASE) {
+      if (tab_pre) dp[j] = iw ? a.ep_pre[gidx(k)] : one;
+      else dp[j].x = iw ? a.th_pre[gidx(k)] : 0.f;
+    }
+    if constexpr (MID_PH) {
+      if (tab_mid) dm[j] = active ? a.ep_mid[gidx(k)] : one;
+      else dm[j].x = active ? a.th_mid[gidx(k)] : 0.f;
+    }
     if constexpr (MID_Y) yv[j] = active ? a.y[gidx(k)] : 0.f;
     if constexpr (MID != MID_STORE) {
       const bool ow = out_win(k);
-      if constexpr (POST_PH) thq[j] = ow ? a.th_post[gidx(k)] : 0.f;
+      if constexpr (POST_PH) {
+        if (tab_post) dq[j] = ow ? a.ep_post[gidx(k)] : one;
+        else dq[j].x = ow ? a.th_post[gidx(k)] : 0.f;
+      }
       if constexpr (POST_X) xo[j] = ow ? a.out[out_addr(k)] : make_float2(0.f, 0.f);
     }
+  }
+  // phases -> diagonal entries where no table was given
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    if constexpr (PRE == PRE_PHASE)
+      if (!tab_pre) dp[j] = phase<false>(dp[j].x, 1.f);
+    if constexpr (MID_PH)
+      if (!tab_mid) dm[j] = phase<false>(dm[j].x, 1.f);
+    if constexpr (POST_PH)
+      if (!tab_post) dq[j] = phase<false>(dq[j].x, 1.f);
   }
 
   float s_pre = a.scale_pre;
@@ -133,7 +161,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   // ---- pre-diagonal, first transform
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    if constexpr (PRE == PRE_PHASE) v[j] = cmul(v[j], phase<false>(thp[j], s_pre));
+    if constexpr (PRE == PRE_PHASE) v[j] = cmul(v[j], cscale(dp[j], s_pre));
     else v[j] = cscale(v[j], s_pre);
   }
   int ph = 0;
@@ -143,7 +171,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   float acc = 0.f;
   if constexpr (MID_PH) {
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = cmul(v[j], phase<MID == MID_PHASE_CONJ>(thm[j], a.scale_mid));
+    for (int j = 0; j < E; ++j) {
+      const float2 d = cscale(dm[j], a.scale_mid);
+      v[j] = (MID == MID_PHASE_CONJ) ? cmulc(v[j], d) : cmul(v[j], d);
+    }
   } else if constexpr (MID == MID_GD) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
@@ -182,7 +213,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
       const int k = T::elem(t, j);
       if (out_win(k)) {
         float2 val = cscale(v[j], a.scale_out);
-        if constexpr (POST_PH) val = cmul(val, phase<true>(thq[j], 1.f));
+        if constexpr (POST_PH) val = cmulc(val, dq[j]);
         if constexpr (POST == POST_GD) {
           val = make_float2(xo[j].x - a.step * val.x, xo[j].y - a.step * val.y);
         } else if constexpr (POST == POST_SPEC) {

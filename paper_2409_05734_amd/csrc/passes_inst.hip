@@ -65,7 +65,7 @@ hipError_t dispatch(int kind, const PassArgs& a, hipStream_t s) {
 }
 
 using Cfg = TileCfg<SR_FFT_N>;
-constexpr int kColOpts[3] = {4, 8, 16};
+constexpr int kColOpts[4] = {2, 4, 8, 16};
 
 }  // namespace
 
@@ -87,6 +87,9 @@ hipError_t launch_pass_n<SR_FFT_N>(int kind, bool col, int B, const PassArgs& a,
   constexpr int N = SR_FFT_N;
   if (col) {
     switch (B) {
+      case 2:
+        if constexpr (Cfg::col_ok(2)) return dispatch<N, true, 2>(kind, a, s);
+        break;
       case 4:
         if constexpr (Cfg::col_ok(4)) return dispatch<N, true, 4>(kind, a, s);
         break;

@@ -53,6 +53,7 @@ sr_status sr_plan_s::init(const float* theta_host) {
   part_cap = std::max(cap, 64);
   int64_t grid_elems = (kind == SR_DENSE) ? (int64_t)max_m * (int64_t)np : max_m;
   size_t b_theta = align256(sizeof(float) * (size_t)std::max<int64_t>(theta_len, 0));
+  size_t b_eph = align256(sizeof(float2) * (size_t)std::max<int64_t>(theta_len, 0));
   size_t b_tw = align256(sizeof(float2) * tw_elems);
   size_t b_grid = align256(sizeof(float2) * (size_t)grid_elems);
   size_t b_part = align256(sizeof(float) * 2 * (size_t)part_cap);
@@ -60,7 +61,7 @@ sr_status sr_plan_s::init(const float* theta_host) {
   size_t b_fs = align256(sizeof(float) * (8 * np + 64));
   size_t b_sync = 256;
   int ngrid = (kind == SR_DENSE) ? 2 : 4;
-  ws_bytes = b_theta + b_tw + ngrid * b_grid + b_part + b_ysum + b_fs + b_sync;
+  ws_bytes = b_theta + b_eph + b_tw + ngrid * b_grid + b_part + b_ysum + b_fs + b_sync;
   hipError_t e = hipMalloc(&ws, ws_bytes);
   if (e != hipSuccess) {
     ws = nullptr;
@@ -69,6 +70,8 @@ sr_status sr_plan_s::init(const float* theta_host) {
   char* c = (char*)ws;
   theta = theta_len > 0 ? (float*)c : nullptr;
   c += b_theta;
+  eph = theta_len > 0 ? (float2*)c : nullptr;
+  c += b_eph;
   twbuf = (float2*)c;
   c += b_tw;
   bufA = (float2*)c;
@@ -111,6 +114,12 @@ sr_status sr_plan_s::init(const float* theta_host) {
   if (e != hipSuccess) return sr::hip_fail(e, "workspace clear");
   e = hipMemset(part, 0, b_part);
   if (e != hipSuccess) return sr::hip_fail(e, "workspace clear");
+  e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return sr::hip_fail(e, "capture stream");
+  sr_status st = sr::fill_phase_table(this);
+  if (st != SR_OK) return st;
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return sr::hip_fail(e, "plan setup");
   return SR_OK;
 }
 
@@ -120,5 +129,7 @@ const float2* sr_plan_s::twiddles(int N) const {
 }
 
 sr_plan_s::~sr_plan_s() {
+  for (auto& g : graphs) hipGraphExecDestroy(g.second);
+  if (cap_stream) hipStreamDestroy(cap_stream);
   if (ws) hipFree(ws);
 }

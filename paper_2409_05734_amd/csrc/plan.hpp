@@ -35,6 +35,8 @@ struct sr_plan_s {
   std::vector<int64_t> xoff, yoff;  // concatenation offsets (complex elements)
 
   float* theta = nullptr;  // device copy of the phases
+  float2* eph = nullptr;   // exp(i theta), same layout (filled on device)
+  bool use_table = false;  // passes read eph instead of evaluating sincos(theta)
   int64_t theta_len = 0;
   const float2* dense_A = nullptr;  // caller-owned dense matrix (SR_DENSE)
 
@@ -55,6 +57,8 @@ struct sr_plan_s {
   unsigned* sync = nullptr;   // [0] grid-barrier counter, [1] barrier error flag
 
   int schedule = SR_SCHED_AUTO;
+  hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
+  std::vector<std::pair<std::string, hipGraphExec_t>> graphs;  // captured solver chunks (most recent last)
   std::map<std::pair<int, int>, int> tiles;  // (FFT length, column mode) -> tuned tile width
 
   int tile(int N, bool col) const {
@@ -76,6 +80,7 @@ sr_status sum_floats(sr_plan_s* p, const float* y, int64_t n, double* out);
 sr_status norm2_partial(sr_plan_s* p, const float2* x, int64_t n, float* out);
 sr_status final_scale(sr_plan_s* p, float2* x, int64_t n, const float* part, int npart, const double* ysum,
                       float inv_mc);
+sr_status fill_phase_table(sr_plan_s* p);
 
 // dense.hip (i.i.d. complex Gaussian baseline)
 sr_status dense_forward(sr_plan_s* p, const float2* x, float2* z, float* y);

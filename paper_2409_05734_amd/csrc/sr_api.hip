@@ -148,7 +148,19 @@ struct PassRecord {
 };
 static std::vector<PassRecord>* g_recording = nullptr;
 
-static sr_status launch(sr_plan_s* p, const Geo& g, int k, int kind, const PassArgs& a) {
+// exp(i theta) table entry parallel to a phase pointer (the table mirrors
+// the phase buffer's layout)
+static const float2* table_of(const sr_plan_s* p, const float* th) {
+  return th == nullptr ? nullptr : p->eph + (th - p->theta);
+}
+
+static sr_status launch(sr_plan_s* p, const Geo& g, int k, int kind, const PassArgs& a_in) {
+  PassArgs a = a_in;
+  if (p->use_table) {
+    a.ep_pre = table_of(p, a.th_pre);
+    a.ep_mid = table_of(p, a.th_mid);
+    a.ep_post = table_of(p, a.th_post);
+  }
   if (g_recording != nullptr) {
     g_recording->push_back({k, kind, a});
     return SR_OK;
@@ -310,6 +322,72 @@ static int turn_groups(const sr_plan_s* p, const Geo& g) {
   return pass_groups(N, pass_col(k), p->tile(N, pass_col(k)), ntr);
 }
 
+// ------------------------------------------------------------- graphs
+// Solver iterations are captured once into a hipGraph (on a private stream)
+// and replayed on the plan's stream: one graph launch per chunk of
+// iterations instead of 2L+1 kernel launches per iteration.  Graphs are
+// cached by the call's pointers and scalars; SR_GRAPH=0 disables them.
+
+constexpr int kGraphChunk = 50;  // iterations per captured graph (even)
+constexpr size_t kGraphCacheSize = 8;
+
+static bool graphs_enabled(const sr_plan_s* p) {
+  if (p->schedule == SR_SCHED_LOOP) return false;
+  const char* e = std::getenv("SR_GRAPH");
+  return e == nullptr || std::atoi(e) != 0;
+}
+
+template <class F>
+static sr_status launch_captured(sr_plan_s* p, const std::string& key, F&& enqueue) {
+  for (auto it = p->graphs.begin(); it != p->graphs.end(); ++it) {
+    if (it->first == key) {
+      hipGraphExec_t ex = it->second;
+      std::rotate(it, it + 1, p->graphs.end());  // most recent last
+      SR_HIP(hipGraphLaunch(ex, p->stream));
+      return SR_OK;
+    }
+  }
+  hipStream_t user = p->stream;
+  p->stream = p->cap_stream;
+  hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) {
+    p->stream = user;
+    return hip_fail(e, "hipStreamBeginCapture");
+  }
+  sr_status st = enqueue();
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(p->cap_stream, &graph);
+  p->stream = user;
+  if (st != SR_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  if (p->graphs.size() >= kGraphCacheSize) {
+    hipGraphExecDestroy(p->graphs.front().second);
+    p->graphs.erase(p->graphs.begin());
+  }
+  p->graphs.push_back({key, ex});
+  SR_HIP(hipGraphLaunch(ex, p->stream));
+  return SR_OK;
+}
+
+static std::string ptr_key(const void* a) {
+  char buf[32];
+  std::snprintf(buf, sizeof(buf), "%p", a);
+  return buf;
+}
+
+static std::string float_key(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return std::to_string(u);
+}
+
 // ------------------------------------------------------------------ tuner
 // Picks the tile width of every (FFT length, mode) a plan uses by timing one
 // GD iteration of each 2D problem shape for every combination of the
@@ -322,28 +400,29 @@ static std::string tune_key(const Geo& g) {
          std::to_string(g.N2) + ":L" + std::to_string(g.L);
 }
 
-static bool tune_cache_lookup(const char* path, const std::string& key, int* cb, int* rb) {
+static bool tune_cache_lookup(const char* path, const std::string& key, int* cb, int* rb, int* tb) {
   if (path == nullptr) return false;
   FILE* f = std::fopen(path, "r");
   if (f == nullptr) return false;
   char k[128];
-  int c = 0, r = 0;
+  int c = 0, r = 0, t = 0;
   bool found = false;
-  while (std::fscanf(f, "%127s %d %d", k, &c, &r) == 3)
+  while (std::fscanf(f, "%127s %d %d %d", k, &c, &r, &t) == 4)
     if (key == k) {
       *cb = c;
       *rb = r;
+      *tb = t;
       found = true;
     }
   std::fclose(f);
   return found;
 }
 
-static void tune_cache_store(const char* path, const std::string& key, int cb, int rb) {
+static void tune_cache_store(const char* path, const std::string& key, int cb, int rb, int tb) {
   if (path == nullptr) return;
   FILE* f = std::fopen(path, "a");
   if (f == nullptr) return;
-  std::fprintf(f, "%s %d %d\n", key.c_str(), cb, rb);
+  std::fprintf(f, "%s %d %d %d\n", key.c_str(), cb, rb, tb);
   std::fclose(f);
 }
 
@@ -358,8 +437,8 @@ static sr_status tune_plan(sr_plan_s* p) {
     if (std::find(done.begin(), done.end(), key) != done.end()) continue;
     done.push_back(key);
     if (p->tiles.count({g.M1, 1}) && p->tiles.count({g.M2, 0})) continue;  // decided by an earlier shape
-    int cb = 0, rb = 0;
-    if (!tune_cache_lookup(cache, key, &cb, &rb)) {
+    int cb = 0, rb = 0, tb = 0;
+    if (!tune_cache_lookup(cache, key, &cb, &rb, &tb)) {
       int copt[8], ropt[8];
       const int nc = tile_options(g.M1, true, copt, 8);
       const int nr = tile_options(g.M2, false, ropt, 8);
@@ -369,8 +448,13 @@ static sr_status tune_plan(sr_plan_s* p) {
       SR_HIP(hipEventCreate(&e1));
       float2* x = p->bufC;
       const float* y = (const float*)p->bufD;
+      const char* tab_env = std::getenv("SR_PHASE_TABLE");
+      const int tab_lo = tab_env ? std::atoi(tab_env) : 0;
+      const int tab_hi = tab_env ? std::atoi(tab_env) : 1;
+      for (int tab = tab_lo; tab <= tab_hi; ++tab)
       for (int i = 0; i < nc; ++i)
         for (int j = 0; j < nr; ++j) {
+          p->use_table = tab != 0;
           p->tiles[{g.M1, 1}] = copt[i];
           p->tiles[{g.M2, 0}] = ropt[j];
           for (int w = 0; w < 3; ++w) SR_CHECK(gd_iter_2d(p, g, y, x, 0.f, nullptr));
@@ -384,14 +468,19 @@ static sr_status tune_plan(sr_plan_s* p) {
             best = ms;
             cb = copt[i];
             rb = ropt[j];
+            tb = tab;
           }
         }
       hipEventDestroy(e0);
       hipEventDestroy(e1);
-      tune_cache_store(cache, key, cb, rb);
+      tune_cache_store(cache, key, cb, rb, tb);
     }
     p->tiles[{g.M1, 1}] = cb;
     p->tiles[{g.M2, 0}] = rb;
+    p->use_table = tb != 0;
+    const char* verbose = std::getenv("SR_TUNE_VERBOSE");
+    if (verbose != nullptr && std::atoi(verbose) != 0)
+      std::fprintf(stderr, "[srpr tune] %s: column tile %d, row tile %d, phase table %d\n", key.c_str(), cb, rb, tb);
   }
   return SR_OK;
 }
@@ -557,7 +646,7 @@ sr_status sr_plan_set_theta(sr_plan p, const float* theta_dev, int64_t theta_len
   if (p->kind != SR_STRUCTURED) return fail(SR_E_STATE, "dense plans have no phases");
   if (theta_len != p->theta_len) return fail(SR_E_SHAPE, "theta length differs from the plan's");
   SR_HIP(hipMemcpyAsync(p->theta, theta_dev, sizeof(float) * theta_len, hipMemcpyDeviceToDevice, p->stream));
-  return SR_OK;
+  return fill_phase_table(p);
 }
 
 sr_status sr_plan_workspace_size(sr_plan p, size_t* bytes) {
@@ -678,7 +767,16 @@ sr_status sr_gd_solve(sr_plan p, const float* y, void* x_inout, int32_t iters, c
       continue;
     }
     const int nparts = turn_groups(p, g);
-    for (int it = 0; it < iters; ++it) {
+    int it = 0;
+    if (lt == nullptr && graphs_enabled(p) && iters >= kGraphChunk) {
+      const std::string key = "gd:" + std::to_string(i) + ":" + ptr_key(yi) + ":" + ptr_key(xi) + ":" + float_key(step);
+      for (; it + kGraphChunk <= iters; it += kGraphChunk)
+        SR_CHECK(launch_captured(p, key, [&]() -> sr_status {
+          for (int c = 0; c < kGraphChunk; ++c) SR_CHECK(gd_iter_2d(p, g, yi, xi, step, nullptr));
+          return SR_OK;
+        }));
+    }
+    for (; it < iters; ++it) {
       SR_CHECK(gd_iter_2d(p, g, yi, xi, step, lt ? p->part : nullptr));
       if (lt) SR_CHECK(reduce_partials(p, p->part, nparts, lt + it));
     }
@@ -725,7 +823,26 @@ sr_status sr_spectral_init(sr_plan p, const float* y, const void* v0, int32_t it
       npart = (g.N2 + B - 1) / B;
     } else {
       const int nq = last_pass_groups(p, g);
-      for (int it = 0; it < iters; ++it) {
+      int it = 0;
+      if (iters > 0) {  // the first iteration reads the start vector's single partial
+        SR_CHECK(spec_iter_2d(p, g, yi, xi, lambda, inv_mc, p->ysum, parts[0], npart, parts[1]));
+        npart = nq;
+        it = 1;
+      }
+      if (graphs_enabled(p) && iters - it >= kGraphChunk) {
+        // chunks start at odd iterations, so every chunk has the same partial-buffer parity
+        const std::string key = "spec:" + std::to_string(i) + ":" + ptr_key(yi) + ":" + ptr_key(xi) + ":" +
+                                float_key(lambda);
+        for (; it + kGraphChunk <= iters; it += kGraphChunk)
+          SR_CHECK(launch_captured(p, key, [&]() -> sr_status {
+            for (int c = 0; c < kGraphChunk; ++c) {
+              const int q = it + c;
+              SR_CHECK(spec_iter_2d(p, g, yi, xi, lambda, inv_mc, p->ysum, parts[q & 1], nq, parts[(q + 1) & 1]));
+            }
+            return SR_OK;
+          }));
+      }
+      for (; it < iters; ++it) {
         SR_CHECK(spec_iter_2d(p, g, yi, xi, lambda, inv_mc, p->ysum, parts[it & 1], npart, parts[(it + 1) & 1]));
         npart = nq;
       }

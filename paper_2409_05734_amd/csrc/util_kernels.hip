@@ -66,7 +66,22 @@ __global__ void final_scale_kernel(float2* x, long long n, const float* __restri
     x[i] = cscale(x[i], sc);
 }
 
+// out[i] = exp(i theta[i])
+__global__ void phase_table_kernel(const float* __restrict__ th, long long n, float2* __restrict__ out) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = phase<false>(th[i], 1.f);
+}
+
 }  // namespace
+
+sr_status fill_phase_table(sr_plan_s* p) {
+  if (p->eph == nullptr || p->theta_len <= 0) return SR_OK;
+  const long long n = p->theta_len;
+  const int groups = (int)std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(phase_table_kernel, dim3(groups), dim3(256), 0, p->stream, p->theta, n, p->eph);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SR_OK : hip_fail(e, "phase table");
+}
 
 sr_status reduce_partials(sr_plan_s* p, const float* part, int n, float* out) {
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(64), 0, p->stream, part, n, out);

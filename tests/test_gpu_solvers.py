@@ -162,11 +162,11 @@ def test_zero_iterations_and_edge_inputs(gpu):
 
 @pytest.mark.parametrize("n_shape,m_shape,L", [((256, 256), (512, 512), 2), ((100, 120), (256, 256), 3),
                                                ((128, 128), (256, 256), 1)])
-def test_persistent_schedule_matches_pass_loop(gpu, n_shape, m_shape, L):
-    """The single-launch persistent solver and the one-launch-per-pass loop
-    compute every transform identically: GD iterates agree bit for bit;
-    spectral iterates agree to rounding (partial norms are grouped by tile)."""
-    import torch
+def test_schedules_agree(gpu, monkeypatch, n_shape, m_shape, L):
+    """Graph-replayed chunks, one launch per pass, and the single-launch
+    persistent solver compute every transform identically: GD iterates agree
+    bit for bit; spectral iterates agree to rounding (partial norms are
+    grouped by tile)."""
     import paper_2409_05734_amd as srpr
     rng = np.random.default_rng(50 + L)
     th, xs = random_problem(rng, n_shape, m_shape, L)
@@ -176,13 +176,19 @@ def test_persistent_schedule_matches_pass_loop(gpu, n_shape, m_shape, L):
     x0 = (xs + 0.5 * sr_inputs.complex_gaussian(rng, n_shape)).astype(np.complex64)
     eta = np.float32(oracle.default_step(op, y, 0.2))
     plan = make_plan([(n_shape, m_shape, L)], [th], gpu)
-    gp, lp = _run_gd(plan, y, x0, 30, eta, gpu, loss=True)
-    sp = _run_spec(plan, y, v0, 25, -1.0, gpu)
+    g_auto, _ = _run_gd(plan, y, x0, 120, eta, gpu)            # two graph chunks + 20 direct iterations
+    s_auto = _run_spec(plan, y, v0, 111, -1.0, gpu)
+    g_auto2, _ = _run_gd(plan, y, x0, 120, eta, gpu)           # cached graphs
+    monkeypatch.setenv("SR_PERSIST_B", "8")
+    g_pers, l_pers = _run_gd(plan, y, x0, 120, eta, gpu, loss=True)
+    s_pers = _run_spec(plan, y, v0, 111, -1.0, gpu)
+    monkeypatch.delenv("SR_PERSIST_B")
     srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_LOOP)
-    gl, ll = _run_gd(plan, y, x0, 30, eta, gpu, loss=True)
-    sl = _run_spec(plan, y, v0, 25, -1.0, gpu)
+    g_loop, l_loop = _run_gd(plan, y, x0, 120, eta, gpu, loss=True)
+    s_loop = _run_spec(plan, y, v0, 111, -1.0, gpu)
     srpr.sr_plan_sync(plan)
-    assert np.array_equal(gp, gl)
-    assert np.max(np.abs(lp - ll) / ll) < 1e-5
-    assert rel_l2(sp, sl) < 1e-5
-    assert rel_l2(sp.reshape(n_shape), oracle.spectral_init(op, y, v0, 25, -1.0)) <= TOL_IT
+    assert np.array_equal(g_auto, g_loop) and np.array_equal(g_auto2, g_loop)
+    assert np.array_equal(g_pers, g_loop)
+    assert np.max(np.abs(l_pers - l_loop) / l_loop) < 1e-5
+    assert rel_l2(s_auto, s_loop) < 1e-5 and rel_l2(s_pers, s_loop) < 1e-5
+    assert rel_l2(s_auto.reshape(n_shape), oracle.spectral_init(op, y, v0, 111, -1.0)) <= TOL_IT
