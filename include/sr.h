@@ -92,8 +92,9 @@ typedef struct {
  *               must then have the same shape); the caller keeps it alive
  *               until sr_plan_destroy.  NULL for SR_STRUCTURED.
  *  hip_stream   hipStream_t to order all work on (NULL = default stream)
- * FFT lengths along each grid axis must be one of 32, 64, 96, 128, 192, 256,
- * 384, 512, 768, 1024, 2048 (2D) or 32 ... 4096 with L*m <= 4096 (1D);
+ * FFT lengths along each grid axis must be one of 16, 32, 64, 96, 128, 192,
+ * 256, 384, 512, 768, 1024, 2048 (2D), or one of those or 4096 with
+ * L*m <= 4096 (1D).  Dense problems need an even signal length n;
  * otherwise SR_E_UNSUPPORTED.  Allocates the plan's device workspace.     */
 sr_status sr_plan_create(sr_plan* out, const sr_problem* probs, int32_t nprob, const float* theta_host,
                          int64_t theta_len, const void* dense_A, void* hip_stream);

@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsrpr.so")
 
-FFT_LENGTHS = (32, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 2048)
+FFT_LENGTHS = (16, 32, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 2048)
 SOURCES = ("sr_api.hip", "plan.hip", "dispatch.hip", "util_kernels.hip", "dense.hip", "vjp.hip", "persist.hip")
 
 ARCH = os.environ.get("SR_OFFLOAD_ARCH", "gfx950")
@@ -53,7 +53,9 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
     tasks = []
     for n in FFT_LENGTHS:
-        tasks.append((os.path.join(CSRC, "passes_inst.hip"), os.path.join(BUILD, f"passes_{n}.o"), [f"-DSR_FFT_N={n}"]))
+        for pset in (0, 1):
+            tasks.append((os.path.join(CSRC, "passes_inst.hip"), os.path.join(BUILD, f"passes_{n}_{pset}.o"),
+                          [f"-DSR_FFT_N={n}", f"-DSR_PASS_SET={pset}"]))
     for s in SOURCES:
         tasks.append((os.path.join(CSRC, s), os.path.join(BUILD, s.replace(".hip", ".o")), []))
     jobs = jobs or min(16, os.cpu_count() or 4)

@@ -4,14 +4,15 @@
 
 namespace sr {
 
-#define SR_FOR_EACH_2D_LEN(X) X(32) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(2048)
+#define SR_FOR_EACH_2D_LEN(X) X(16) X(32) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(2048)
 
 hipError_t launch_pass(int N, int kind, bool col, int B, const PassArgs& a, hipStream_t s) {
   if (B <= 0) B = default_tile(N, col);
+  const bool rev = kind >= PK_MID_FWD_SAVE;
   switch (N) {
 #define SR_CASE(n) \
   case n:          \
-    return launch_pass_n<n>(kind, col, B, a, s);
+    return rev ? launch_pass_rev_n<n>(kind, col, B, a, s) : launch_pass_n<n>(kind, col, B, a, s);
     SR_FOR_EACH_2D_LEN(SR_CASE)
 #undef SR_CASE
     default:
@@ -60,6 +61,12 @@ hipError_t go1d(int op, const Fused1DArgs& a, hipStream_t s) {
       break;
     case F1_SPECTRAL:
       hipLaunchKernelGGL((fused1d_kernel<N, F1_SPECTRAL>), dim3(1), dim3(NT), 0, s, a);
+      break;
+    case F1_FWD_VJP:
+      hipLaunchKernelGGL((fused1d_kernel<N, F1_FWD_VJP>), dim3(1), dim3(NT), 0, s, a);
+      break;
+    case F1_ADJ_VJP:
+      hipLaunchKernelGGL((fused1d_kernel<N, F1_ADJ_VJP>), dim3(1), dim3(NT), 0, s, a);
       break;
     default:
       return hipErrorInvalidValue;

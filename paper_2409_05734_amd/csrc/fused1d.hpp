@@ -13,7 +13,7 @@ namespace sr {
 // Capacity of the per-workgroup table of layer phases (L*m entries).
 constexpr int kFused1DPhaseSlots = 4096;
 
-enum Fused1DOp : int { F1_FORWARD = 0, F1_ADJOINT = 1, F1_GD = 2, F1_SPECTRAL = 3 };
+enum Fused1DOp : int { F1_FORWARD = 0, F1_ADJOINT = 1, F1_GD = 2, F1_SPECTRAL = 3, F1_FWD_VJP = 4, F1_ADJ_VJP = 5 };
 
 struct Fused1DArgs {
   int n, m, L, off;          // signal length, measurement length, layers, pad offset
@@ -29,6 +29,7 @@ struct Fused1DArgs {
   float step;                // GD: eta/m; spectral: 1/(m c)
   float lam;                 // spectral lambda
   float* loss_trace;         // GD: loss before each step (nullable)
+  float* gth;                // derivatives: phase-cotangent accumulator (L*m)
 };
 
 template <int N, int OP>
@@ -132,6 +133,80 @@ __global__ void __launch_bounds__((Tile<N, 1, false>::THREADS)) fused1d_kernel(c
     for (int j = 0; j < E; ++j) {
       const int k = T::elem(t, j);
       if (in_window(k)) a.x_out[k - a.off] = x[j];
+    }
+  } else if constexpr (OP == F1_FWD_VJP) {
+    // x_in = x, r_in = cotangent of A x; x_out = A^H gz (nullable); gth += dtheta
+    __shared__ float2 sv[kFused1DPhaseSlots];  // u_l = D_l w_{l-1}
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int k = T::elem(t, j);
+      v[j] = in_window(k) ? a.x_in[k - a.off] : make_float2(0.f, 0.f);
+    }
+    for (int l = 0; l < L; ++l) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int k = T::elem(t, j);
+        v[j] = cmul(v[j], dl[l * N + k]);
+        sv[l * N + k] = v[j];
+      }
+      T::template fft<false>(v, lds, ph, w, t, 0);
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = cscale(v[j], s);
+    }
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = a.r_in[T::elem(t, j)];
+    for (int l = L - 1; l >= 0; --l) {
+      T::template fft<true>(v, lds, ph, w, t, 0);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int k = T::elem(t, j);
+        const float2 u = cscale(v[j], s);
+        const float2 su = sv[l * N + k];
+        a.gth[l * N + k] += u.y * su.x - u.x * su.y;  // Im(u conj(u_l))
+        v[j] = cmulc(u, dl[l * N + k]);
+      }
+    }
+    if (a.x_out) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int k = T::elem(t, j);
+        if (in_window(k)) a.x_out[k - a.off] = v[j];
+      }
+    }
+  } else if constexpr (OP == F1_ADJ_VJP) {
+    // r_in = r, x_in = cotangent of A^H r; z_out = A gv (nullable); gth += dtheta
+    __shared__ float2 sv[kFused1DPhaseSlots];  // q_l = D_l^* F^H s_l
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = a.r_in[T::elem(t, j)];
+    for (int l = L - 1; l >= 0; --l) {
+      T::template fft<true>(v, lds, ph, w, t, 0);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int k = T::elem(t, j);
+        v[j] = cscale(cmulc(v[j], dl[l * N + k]), s);
+        sv[l * N + k] = v[j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int k = T::elem(t, j);
+      v[j] = in_window(k) ? a.x_in[k - a.off] : make_float2(0.f, 0.f);
+    }
+    for (int l = 0; l < L; ++l) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int k = T::elem(t, j);
+        const float2 q = sv[l * N + k];
+        a.gth[l * N + k] += v[j].x * q.y - v[j].y * q.x;  // Im(conj(qbar) q_l)
+        v[j] = cmul(v[j], dl[l * N + k]);
+      }
+      T::template fft<false>(v, lds, ph, w, t, 0);
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = cscale(v[j], s);
+    }
+    if (a.z_out) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) a.z_out[T::elem(t, j)] = v[j];
     }
   } else {  // F1_SPECTRAL
     float yv[E];

@@ -19,7 +19,13 @@ enum PassKind : int {
   PK_LAST_ADJ = 7,    // [F_0^H, D_1^*, U^H]      column mode over the support columns
   PK_LAST_GD = 8,     // ... then x <- x - step * g
   PK_LAST_SPEC = 9,   // ... then u <- step * g - 2 lambda u/||u|| (+ norm partials)
-  PK_COUNT = 10
+  // reverse mode (derivatives with respect to the phases)
+  PK_MID_FWD_SAVE = 10,  // [F_a, D_k (save u_k), F_a]
+  PK_MID_ADJ_GT = 11,    // [F_a^H, gth_k += Im(u conj(u_k)), D_k^*, F_a^H]
+  PK_MID_ADJ_SAVE = 12,  // [F_a^H, D_k^* (save q_k), F_a^H]
+  PK_MID_FWD_GT = 13,    // [F_a, gth_k += Im(conj(q) q_k), D_k, F_a]
+  PK_LAST_ADJ_GT = 14,   // [F_0^H, gth_1 += Im(u conj(D_1 U x)), D_1^*, U^H]
+  PK_COUNT = 15
 };
 
 // Tile widths: each length is compiled for a few tile widths (transforms per
@@ -54,6 +60,8 @@ hipError_t launch_pass(int N, int kind, bool col, int B, const PassArgs& a, hipS
 // Per-length entry points, each defined in its own translation unit.
 template <int N>
 hipError_t launch_pass_n(int kind, bool col, int B, const PassArgs& a, hipStream_t s);
+template <int N>
+hipError_t launch_pass_rev_n(int kind, bool col, int B, const PassArgs& a, hipStream_t s);
 template <int N>
 int tile_options_n(bool col, int* out, int max_out);
 

@@ -21,8 +21,26 @@
 namespace sr {
 
 enum PreOp : int { PRE_NONE = 0, PRE_PHASE = 1 };
-enum MidOp : int { MID_NONE = 0, MID_PHASE = 1, MID_PHASE_CONJ = 2, MID_GD = 3, MID_SPEC = 4, MID_STORE = 5 };
-enum PostOp : int { POST_STORE = 0, POST_PHASE_CONJ_STORE = 1, POST_GD = 2, POST_SPEC = 3 };
+enum MidOp : int {
+  MID_NONE = 0,
+  MID_PHASE = 1,            // v <- D v
+  MID_PHASE_CONJ = 2,       // v <- D^* v
+  MID_GD = 3,               // v <- (|v|^2 - y) v, loss partials
+  MID_SPEC = 4,             // v <- T(y) v
+  MID_STORE = 5,            // z <- v, |z|^2
+  // reverse-mode variants (value u after the first transform; save/gth per layer)
+  MID_PHASE_SAVE = 6,       // u <- D v, save <- u                  (forward recompute)
+  MID_PHASE_CONJ_GT = 7,    // gth += Im(v conj(save)), v <- D^* v   (forward VJP)
+  MID_PHASE_CONJ_SAVE = 8,  // q <- D^* v, save <- q                (adjoint recompute)
+  MID_PHASE_GT = 9          // gth += Im(conj(v) save), v <- D v     (adjoint VJP)
+};
+enum PostOp : int {
+  POST_STORE = 0,
+  POST_PHASE_CONJ_STORE = 1,
+  POST_GD = 2,
+  POST_SPEC = 3,
+  POST_PHASE_CONJ_GT = 4  // gth_1 += Im(v conj(D_1 U x)), then D_1^* and crop
+};
 
 struct PassArgs {
   // input buffer: element (transform b, position k) for k in [in_lo, in_hi)
@@ -60,6 +78,10 @@ struct PassArgs {
   // solver updates (POST_GD, POST_SPEC)
   float step;            // GD: eta/m; spectral: 1/(m c)
   float two_lam;         // spectral: 2 lambda
+  // reverse mode
+  float2* save;          // per-layer intermediate on the grid (written or read)
+  float* gth;            // phase-cotangent accumulator of this pass's diagonal (grid layout)
+  const float2* xin;     // POST_PHASE_CONJ_GT: the signal x (crop layout = output layout)
 };
 
 // Sum of previous-iterate partials, identical on every thread (fixed order).
@@ -82,7 +104,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
                                           int npart, float* part_out) {
   using T = Tile<N, B, COL>;
   constexpr int E = T::E;
-  constexpr bool MID_PH = (MID == MID_PHASE || MID == MID_PHASE_CONJ);
+  constexpr bool MID_PH = (MID == MID_PHASE || MID == MID_PHASE_CONJ || MID >= MID_PHASE_SAVE);
+  constexpr bool MID_SAVED = (MID == MID_PHASE_CONJ_GT || MID == MID_PHASE_GT);
   constexpr bool MID_Y = (MID == MID_GD || MID == MID_SPEC);
   constexpr bool POST_PH = (POST != POST_STORE);
   constexpr bool POST_X = (POST == POST_GD || POST == POST_SPEC);
@@ -110,7 +133,9 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   float2 dm[E];   // mid-diagonal entries
   float yv[E];    // measurements
   float2 dq[E];   // post-diagonal entries
-  float2 xo[E];   // previous iterate
+  float2 xo[E];   // previous iterate (or x for POST_PHASE_CONJ_GT)
+  float2 sv[E];   // saved intermediate
+  float gt[E];    // phase-cotangent accumulator
   typename T::Twiddles w;
   T::load_twiddles(w, a.tw, t);
   const bool tab_pre = a.ep_pre != nullptr;
@@ -131,6 +156,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
       else dm[j].x = active ? a.th_mid[gidx(k)] : 0.f;
     }
     if constexpr (MID_Y) yv[j] = active ? a.y[gidx(k)] : 0.f;
+    if constexpr (MID_SAVED) {
+      sv[j] = active ? a.save[gidx(k)] : make_float2(0.f, 0.f);
+      gt[j] = active ? a.gth[gidx(k)] : 0.f;
+    }
     if constexpr (MID != MID_STORE) {
       const bool ow = out_win(k);
       if constexpr (POST_PH) {
@@ -138,6 +167,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
         else dq[j].x = ow ? a.th_post[gidx(k)] : 0.f;
       }
       if constexpr (POST_X) xo[j] = ow ? a.out[out_addr(k)] : make_float2(0.f, 0.f);
+      if constexpr (POST == POST_PHASE_CONJ_GT) {
+        xo[j] = ow ? a.xin[out_addr(k)] : make_float2(0.f, 0.f);
+        gt[j] = ow ? a.gth[gidx(k)] : 0.f;
+      }
     }
   }
   // phases -> diagonal entries where no table was given
@@ -169,11 +202,31 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
 
   // ---- mid operation
   float acc = 0.f;
-  if constexpr (MID_PH) {
+  if constexpr (MID == MID_PHASE || MID == MID_PHASE_CONJ) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const float2 d = cscale(dm[j], a.scale_mid);
       v[j] = (MID == MID_PHASE_CONJ) ? cmulc(v[j], d) : cmul(v[j], d);
+    }
+  } else if constexpr (MID >= MID_PHASE_SAVE) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int k = T::elem(t, j);
+      const float2 u = cscale(v[j], a.scale_mid);
+      if constexpr (MID == MID_PHASE_SAVE) {
+        v[j] = cmul(u, dm[j]);
+        if (active) a.save[gidx(k)] = v[j];
+      } else if constexpr (MID == MID_PHASE_CONJ_SAVE) {
+        v[j] = cmulc(u, dm[j]);
+        if (active) a.save[gidx(k)] = v[j];
+      } else if constexpr (MID == MID_PHASE_CONJ_GT) {
+        // Im(u conj(s)) = u.y s.x - u.x s.y
+        if (active) a.gth[gidx(k)] = gt[j] + (u.y * sv[j].x - u.x * sv[j].y);
+        v[j] = cmulc(u, dm[j]);
+      } else {  // MID_PHASE_GT: Im(conj(u) s) = u.x s.y - u.y s.x
+        if (active) a.gth[gidx(k)] = gt[j] + (u.x * sv[j].y - u.y * sv[j].x);
+        v[j] = cmul(u, dm[j]);
+      }
     }
   } else if constexpr (MID == MID_GD) {
 #pragma unroll
@@ -213,6 +266,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
       const int k = T::elem(t, j);
       if (out_win(k)) {
         float2 val = cscale(v[j], a.scale_out);
+        if constexpr (POST == POST_PHASE_CONJ_GT) {
+          const float2 u1 = cmul(xo[j], dq[j]);  // u_1 = D_1 U x at this position
+          a.gth[gidx(k)] = gt[j] + (val.y * u1.x - val.x * u1.y);
+        }
         if constexpr (POST_PH) val = cmulc(val, dq[j]);
         if constexpr (POST == POST_GD) {
           val = make_float2(xo[j].x - a.step * val.x, xo[j].y - a.step * val.y);

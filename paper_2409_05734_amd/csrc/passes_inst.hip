@@ -1,10 +1,14 @@
 // Kernel instantiations for one FFT length, selected by -DSR_FFT_N=<length>.
-// The build compiles this file once per supported length so the lengths
-// compile in parallel.
+// SR_PASS_SET=0 builds the operator/solver passes, SR_PASS_SET=1 the
+// reverse-mode passes; the build compiles every (length, set) pair as its own
+// translation unit so they compile in parallel.
 #include "launch.hpp"
 
 #ifndef SR_FFT_N
 #error "compile with -DSR_FFT_N=<length>"
+#endif
+#ifndef SR_PASS_SET
+#define SR_PASS_SET 0
 #endif
 
 namespace sr {
@@ -32,6 +36,7 @@ hipError_t go(const PassArgs& a, hipStream_t s) {
 
 template <int N, bool COL, int B>
 hipError_t dispatch(int kind, const PassArgs& a, hipStream_t s) {
+#if SR_PASS_SET == 0
   if constexpr (COL) {
     switch (kind) {
       case PK_FIRST_FWD:
@@ -62,28 +67,30 @@ hipError_t dispatch(int kind, const PassArgs& a, hipStream_t s) {
     default:
       return hipErrorInvalidValue;
   }
+#else
+  if constexpr (COL) {
+    if (kind == PK_LAST_ADJ_GT)
+      return go<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_PHASE_CONJ_GT>(a, s);
+  }
+  switch (kind) {
+    case PK_MID_FWD_SAVE:
+      return go<N, B, COL, PRE_NONE, MID_PHASE_SAVE, true, false, false, POST_STORE>(a, s);
+    case PK_MID_ADJ_GT:
+      return go<N, B, COL, PRE_NONE, MID_PHASE_CONJ_GT, true, true, true, POST_STORE>(a, s);
+    case PK_MID_ADJ_SAVE:
+      return go<N, B, COL, PRE_NONE, MID_PHASE_CONJ_SAVE, true, true, true, POST_STORE>(a, s);
+    case PK_MID_FWD_GT:
+      return go<N, B, COL, PRE_NONE, MID_PHASE_GT, true, false, false, POST_STORE>(a, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+#endif
 }
 
 using Cfg = TileCfg<SR_FFT_N>;
 constexpr int kColOpts[4] = {2, 4, 8, 16};
 
-}  // namespace
-
-template <>
-int tile_options_n<SR_FFT_N>(bool col, int* out, int max_out) {
-  int n = 0;
-  if (col) {
-    for (int b : kColOpts)
-      if (Cfg::col_ok(b) && n < max_out) out[n++] = b;
-  } else {
-    if (n < max_out) out[n++] = Cfg::ROW_SMALL;
-    if (Cfg::ROW_BIG != Cfg::ROW_SMALL && n < max_out) out[n++] = Cfg::ROW_BIG;
-  }
-  return n;
-}
-
-template <>
-hipError_t launch_pass_n<SR_FFT_N>(int kind, bool col, int B, const PassArgs& a, hipStream_t s) {
+hipError_t by_tile(int kind, bool col, int B, const PassArgs& a, hipStream_t s) {
   constexpr int N = SR_FFT_N;
   if (col) {
     switch (B) {
@@ -110,5 +117,32 @@ hipError_t launch_pass_n<SR_FFT_N>(int kind, bool col, int B, const PassArgs& a,
   }
   return hipErrorInvalidValue;
 }
+
+}  // namespace
+
+#if SR_PASS_SET == 0
+template <>
+int tile_options_n<SR_FFT_N>(bool col, int* out, int max_out) {
+  int n = 0;
+  if (col) {
+    for (int b : kColOpts)
+      if (Cfg::col_ok(b) && n < max_out) out[n++] = b;
+  } else {
+    if (n < max_out) out[n++] = Cfg::ROW_SMALL;
+    if (Cfg::ROW_BIG != Cfg::ROW_SMALL && n < max_out) out[n++] = Cfg::ROW_BIG;
+  }
+  return n;
+}
+
+template <>
+hipError_t launch_pass_n<SR_FFT_N>(int kind, bool col, int B, const PassArgs& a, hipStream_t s) {
+  return by_tile(kind, col, B, a, s);
+}
+#else
+template <>
+hipError_t launch_pass_rev_n<SR_FFT_N>(int kind, bool col, int B, const PassArgs& a, hipStream_t s) {
+  return by_tile(kind, col, B, a, s);
+}
+#endif
 
 }  // namespace sr

@@ -131,5 +131,6 @@ const float2* sr_plan_s::twiddles(int N) const {
 sr_plan_s::~sr_plan_s() {
   for (auto& g : graphs) hipGraphExecDestroy(g.second);
   if (cap_stream) hipStreamDestroy(cap_stream);
+  if (vjp_buf) hipFree(vjp_buf);
   if (ws) hipFree(ws);
 }

@@ -55,6 +55,8 @@ struct sr_plan_s {
   double* ysum = nullptr;  // sum(y) scratch (per problem)
   float* fscratch = nullptr;  // float scratch (dense solver scalars)
   unsigned* sync = nullptr;   // [0] grid-barrier counter, [1] barrier error flag
+  float2* vjp_buf = nullptr;  // per-layer intermediates for derivatives (allocated on first use)
+  size_t vjp_elems = 0;
 
   int schedule = SR_SCHED_AUTO;
   hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs

@@ -18,6 +18,7 @@
 #include "launch.hpp"
 #include "persist.hpp"
 #include "plan.hpp"
+#include "schedule.hpp"
 
 using sr::Geo;
 
@@ -38,7 +39,7 @@ sr_status hip_fail(hipError_t e, const char* what) {
 
 bool supported_len_2d(int M) {
   switch (M) {
-    case 32: case 64: case 96: case 128: case 192: case 256: case 384: case 512: case 768: case 1024: case 2048:
+    case 16: case 32: case 64: case 96: case 128: case 192: case 256: case 384: case 512: case 768: case 1024: case 2048:
       return true;
     default:
       return false;
@@ -47,7 +48,7 @@ bool supported_len_2d(int M) {
 
 bool supported_len_1d(int M) {
   switch (M) {
-    case 32: case 64: case 96: case 128: case 192: case 256: case 384: case 512: case 768: case 1024: case 2048:
+    case 16: case 32: case 64: case 96: case 128: case 192: case 256: case 384: case 512: case 768: case 1024: case 2048:
     case 4096:
       return true;
     default:
@@ -70,107 +71,6 @@ using namespace sr;
     sr_status s_ = (st);              \
     if (s_ != SR_OK) return s_;       \
   } while (0)
-
-// ------------------------------------------------------------------ helpers
-
-static int pass_col(int k) { return (k % 2) == 1; }  // forward pass k (1-based): odd -> axis 0
-static int pass_len(const Geo& g, int k) { return pass_col(k) ? g.M1 : g.M2; }
-
-static PassArgs base_args(const sr_plan_s* p, const Geo& g, int k) {
-  PassArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.grid_ld = g.M2;
-  a.tw = p->twiddles(pass_len(g, k));
-  a.scale_pre = 1.f;
-  a.scale_mid = 1.f;
-  a.scale_out = 1.f;
-  a.inv_m = 1.f / (float)g.m;
-  return a;
-}
-
-// Buffer layouts between passes.  "Compact" buffers hold only the N2 support
-// columns (M1 x N2, row-major); "full" buffers hold the whole M1 x M2 grid.
-// The output of forward pass 1 and the input of the last adjoint pass are
-// compact; every other intermediate is full.
-
-// Row-mode input from a compact buffer (pass 2 reads the output of pass 1).
-static void in_compact(PassArgs& a, const Geo& g, const float2* buf) {
-  a.in = buf;
-  a.in_ld = g.N2;
-  a.in_lo = g.o2;
-  a.in_hi = g.o2 + g.N2;
-  a.ntr = g.M1;
-  a.tr_lo = 0;
-}
-
-// Input from a full grid buffer, for a pass on the axis of forward pass k.
-static void in_full(PassArgs& a, const Geo& g, int k, const float2* buf) {
-  a.in = buf;
-  a.in_ld = g.M2;
-  a.in_lo = 0;
-  a.in_hi = pass_len(g, k);
-  a.ntr = pass_col(k) ? g.M2 : g.M1;
-  a.tr_lo = 0;
-}
-
-// Input of forward pass k >= 2 (the output of pass k-1).
-static void set_in(PassArgs& a, const Geo& g, int k, const float2* buf) {
-  if (k == 2) in_compact(a, g, buf);
-  else in_full(a, g, k, buf);
-}
-
-// Output of a pass on the axis of pass k: compact for k == 2, full otherwise.
-static void set_out(PassArgs& a, const Geo& g, int k, float2* buf) {
-  a.out = buf;
-  if (k == 2) {
-    a.out_ld = g.N2;
-    a.out_lo = g.o2;
-    a.out_hi = g.o2 + g.N2;
-  } else {
-    a.out_ld = g.M2;
-    a.out_lo = 0;
-    a.out_hi = pass_len(g, k);
-  }
-}
-
-static void out_full(PassArgs& a, const Geo& g, int k, float2* buf) {
-  a.out = buf;
-  a.out_ld = g.M2;
-  a.out_lo = 0;
-  a.out_hi = pass_len(g, k);
-}
-
-// Launch one fused pass, or, while a persistent schedule is being recorded,
-// append it to the recording instead.
-struct PassRecord {
-  int k, kind;
-  PassArgs a;
-};
-static std::vector<PassRecord>* g_recording = nullptr;
-
-// exp(i theta) table entry parallel to a phase pointer (the table mirrors
-// the phase buffer's layout)
-static const float2* table_of(const sr_plan_s* p, const float* th) {
-  return th == nullptr ? nullptr : p->eph + (th - p->theta);
-}
-
-static sr_status launch(sr_plan_s* p, const Geo& g, int k, int kind, const PassArgs& a_in) {
-  PassArgs a = a_in;
-  if (p->use_table) {
-    a.ep_pre = table_of(p, a.th_pre);
-    a.ep_mid = table_of(p, a.th_mid);
-    a.ep_post = table_of(p, a.th_post);
-  }
-  if (g_recording != nullptr) {
-    g_recording->push_back({k, kind, a});
-    return SR_OK;
-  }
-  const int N = pass_len(g, k);
-  const bool col = pass_col(k);
-  hipError_t e = launch_pass(N, kind, col, p->tile(N, col), a, p->stream);
-  if (e != hipSuccess) return hip_fail(e, "pass launch");
-  return SR_OK;
-}
 
 const float* sr_plan_s::theta_l(const Geo& g, int l) const { return theta + g.th_off + (int64_t)(l - 1) * g.m; }
 
@@ -614,6 +514,8 @@ sr_status sr_plan_create(sr_plan* out, const sr_problem* probs, int32_t nprob, c
     } else {
       if (i > 0 && (g.n != geo[0].n || g.m != geo[0].m))
         return fail(SR_E_SHAPE, "dense problems of one plan share one matrix and must have one shape");
+      if (g.n % 2 != 0) return fail(SR_E_UNSUPPORTED, "dense problems need an even signal length");
+      if (g.m > (1 << 30) / 2 || g.n > (1 << 28)) return fail(SR_E_UNSUPPORTED, "dense problem too large");
     }
   }
   if (kind == SR_STRUCTURED) {

@@ -1,5 +1,233 @@
-#include "plan.hpp"
+// Reverse-mode derivatives of the structured operator with respect to the
+// signal and to the phases theta_l of the diagonals D_l (section III, Eq. (5)),
+// in PyTorch's complex-gradient convention (dL/dRe + i dL/dIm).
+//
+// For z = A x with u_l = D_l w_{l-1}, w_l = F u_l (w_0 = U x):
+//   ubar_l = F^H wbar_l,  thetabar_l += Im(ubar_l conj(u_l)),
+//   wbar_{l-1} = D_l^* ubar_l,  xbar = U^H wbar_0 = A^H zbar.
+// For v = A^H r with t_l = F^H s_l, q_l = D_l^* t_l (s_L = r, s_{l-1} = q_l):
+//   qbar_1 = U vbar,  thetabar_l += Im(conj(qbar_l) q_l),
+//   qbar_{l+1} = F D_l qbar_l,  rbar = A vbar.
+// The intermediates u_l / q_l are recomputed inside the call (one grid buffer
+// per layer for the current problem) rather than kept from an earlier call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "fft_core.hpp"
+#include "fused1d.hpp"
+#include "schedule.hpp"
+
 namespace sr {
-sr_status vjp_forward(sr_plan_s*, const float2*, const float2*, float2*, float*) { return fail(SR_E_UNSUPPORTED, "not built yet"); }
-sr_status vjp_adjoint(sr_plan_s*, const float2*, const float2*, float2*, float*) { return fail(SR_E_UNSUPPORTED, "not built yet"); }
+
+namespace {
+
+// gth_1[support] += Im(conj(gv) v) for the adjoint derivative's first layer
+__global__ void gth_support_kernel(const float2* __restrict__ gv, const float2* __restrict__ v, float* gth, int N1,
+                                   int N2, int o1, int o2, long long M2) {
+  const long long n = (long long)N1 * N2;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / N2), j = (int)(e % N2);
+    const float2 a = gv[e], b = v[e];
+    gth[(long long)(o1 + i) * M2 + (o2 + j)] += a.x * b.y - a.y * b.x;
+  }
 }
+
+sr_status ensure_vjp_buf(sr_plan_s* p) {
+  size_t need = 0;
+  for (const Geo& g : p->geo)
+    if (g.ndim == 2) need = std::max(need, (size_t)std::max(g.L - 1, 1) * (size_t)g.m + (size_t)g.n);
+  if (need <= p->vjp_elems) return SR_OK;
+  if (p->vjp_buf) {
+    hipStreamSynchronize(p->stream);
+    hipFree(p->vjp_buf);
+    p->vjp_buf = nullptr;
+    p->vjp_elems = 0;
+  }
+  hipError_t e = hipMalloc(&p->vjp_buf, need * sizeof(float2));
+  if (e != hipSuccess) return fail(SR_E_NOMEM, "derivative workspace allocation failed");
+  p->vjp_elems = need;
+  return SR_OK;
+}
+
+// save buffer of layer k (k = 2..L) and an n-sized scratch after them
+float2* save_of(sr_plan_s* p, const Geo& g, int k) { return p->vjp_buf + (size_t)(k - 2) * g.m; }
+float2* nscratch(sr_plan_s* p, const Geo& g) { return p->vjp_buf + (size_t)std::max(g.L - 1, 1) * g.m; }
+
+float* gth_of(const sr_plan_s* p, const Geo& g, float* gtheta, int l) {
+  return gtheta + g.th_off + (int64_t)(l - 1) * g.m;
+}
+
+sr_status fused1d_vjp(sr_plan_s* p, const Geo& g, int op, Fused1DArgs a) {
+  a.n = g.N1;
+  a.m = g.M1;
+  a.L = g.L;
+  a.off = g.o1;
+  a.theta = p->theta_l(g, 1);
+  a.tw = p->twiddles(g.M1);
+  hipError_t e = launch_fused1d(g.M1, op, a, p->stream);
+  if (e != hipSuccess) return hip_fail(e, "fused 1D derivative launch");
+  return SR_OK;
+}
+
+#define VJ_CHECK(st)            \
+  do {                          \
+    sr_status s_ = (st);        \
+    if (s_ != SR_OK) return s_; \
+  } while (0)
+
+// Forward passes 1..L on x (saving u_k, k >= 2), or with phase cotangents
+// accumulated (kind_mid = PK_MID_FWD_GT).  Returns the result buffer.
+sr_status fwd_passes(sr_plan_s* p, const Geo& g, const float2* x, int kind_mid, float* gtheta, float2** cur_out) {
+  float2* bufs[2] = {p->bufA, p->bufB};
+  int which = 0;
+  {
+    PassArgs a = base_args(p, g, 1);
+    a.in = x;
+    a.in_ld = g.N2;
+    a.in_lo = g.o1;
+    a.in_hi = g.o1 + g.N1;
+    a.ntr = g.N2;
+    a.tr_lo = g.o2;
+    a.th_pre = p->theta_l(g, 1);
+    a.out = bufs[which];
+    a.out_ld = g.N2;
+    a.out_lo = 0;
+    a.out_hi = g.M1;
+    a.scale_out = 1.f / std::sqrt((float)g.M1);
+    VJ_CHECK(launch(p, g, 1, PK_FIRST_FWD, a));
+  }
+  for (int k = 2; k <= g.L; ++k) {
+    PassArgs a = base_args(p, g, k);
+    set_in(a, g, k, bufs[which]);
+    out_full(a, g, k, bufs[which ^ 1]);
+    a.th_mid = p->theta_l(g, k);
+    const float s = 1.f / std::sqrt((float)pass_len(g, k));
+    a.scale_mid = s;
+    a.scale_out = s;
+    a.save = save_of(p, g, k);
+    if (kind_mid == PK_MID_FWD_GT) a.gth = gth_of(p, g, gtheta, k);
+    VJ_CHECK(launch(p, g, k, kind_mid, a));
+    which ^= 1;
+  }
+  *cur_out = bufs[which];
+  return SR_OK;
+}
+
+// Adjoint passes from r (full grid): first [F^H], then mids of kind kind_mid
+// (save q_k or accumulate phase cotangents), then the last pass of kind
+// kind_last into x_out.
+sr_status adj_passes(sr_plan_s* p, const Geo& g, const float2* r, int kind_mid, int kind_last, float* gtheta,
+                     const float2* xin, float2* x_out) {
+  const int kt = g.L + 1;
+  float2* cur = p->bufA;
+  float2* other = p->bufB;
+  {
+    PassArgs a = base_args(p, g, kt);
+    in_full(a, g, kt, r);
+    set_out(a, g, kt, cur);
+    a.scale_out = 1.f / std::sqrt((float)pass_len(g, kt));
+    VJ_CHECK(launch(p, g, kt, PK_FIRST_ADJ, a));
+  }
+  for (int k = g.L; k >= 2; --k) {
+    PassArgs a = base_args(p, g, k);
+    in_full(a, g, k, cur);
+    set_out(a, g, k, other);
+    a.th_mid = p->theta_l(g, k);
+    const float s = 1.f / std::sqrt((float)pass_len(g, k));
+    a.scale_mid = s;
+    a.scale_out = s;
+    a.save = save_of(p, g, k);
+    if (kind_mid == PK_MID_ADJ_GT) a.gth = gth_of(p, g, gtheta, k);
+    VJ_CHECK(launch(p, g, k, kind_mid, a));
+    std::swap(cur, other);
+  }
+  PassArgs a = base_args(p, g, 1);
+  a.in = cur;
+  a.in_ld = g.N2;
+  a.in_lo = 0;
+  a.in_hi = g.M1;
+  a.ntr = g.N2;
+  a.tr_lo = g.o2;
+  a.out = x_out;
+  a.out_ld = g.N2;
+  a.out_lo = g.o1;
+  a.out_hi = g.o1 + g.N1;
+  a.th_post = p->theta_l(g, 1);
+  a.scale_out = 1.f / std::sqrt((float)g.M1);
+  if (kind_last == PK_LAST_ADJ_GT) {
+    a.gth = gth_of(p, g, gtheta, 1);
+    a.xin = xin;
+  }
+  return launch(p, g, 1, kind_last, a);
+}
+
+}  // namespace
+
+sr_status vjp_forward(sr_plan_s* p, const float2* x, const float2* gz, float2* gx, float* gtheta) {
+  VJ_CHECK(ensure_vjp_buf(p));
+  for (size_t i = 0; i < p->geo.size(); ++i) {
+    const Geo& g = p->geo[i];
+    const float2* xi = x + p->xoff[i];
+    const float2* gzi = gz + p->yoff[i];
+    if (g.ndim == 1) {
+      Fused1DArgs a{};
+      a.x_in = xi;
+      a.r_in = gzi;
+      a.x_out = gx ? gx + p->xoff[i] : nullptr;
+      a.gth = gtheta + g.th_off;
+      VJ_CHECK(fused1d_vjp(p, g, F1_FWD_VJP, a));
+      continue;
+    }
+    float2* gxi = gx ? gx + p->xoff[i] : nscratch(p, g);
+    float2* cur = nullptr;
+    if (g.L >= 2) VJ_CHECK(fwd_passes(p, g, xi, PK_MID_FWD_SAVE, gtheta, &cur));
+    VJ_CHECK(adj_passes(p, g, gzi, PK_MID_ADJ_GT, PK_LAST_ADJ_GT, gtheta, xi, gxi));
+  }
+  return SR_OK;
+}
+
+sr_status vjp_adjoint(sr_plan_s* p, const float2* r, const float2* gv, float2* gr, float* gtheta) {
+  VJ_CHECK(ensure_vjp_buf(p));
+  for (size_t i = 0; i < p->geo.size(); ++i) {
+    const Geo& g = p->geo[i];
+    const float2* ri = r + p->yoff[i];
+    const float2* gvi = gv + p->xoff[i];
+    if (g.ndim == 1) {
+      Fused1DArgs a{};
+      a.r_in = ri;
+      a.x_in = gvi;
+      a.z_out = gr ? gr + p->yoff[i] : nullptr;
+      a.gth = gtheta + g.th_off;
+      VJ_CHECK(fused1d_vjp(p, g, F1_ADJ_VJP, a));
+      continue;
+    }
+    // recompute q_k (k >= 2) and v = A^H r
+    float2* v = nscratch(p, g);
+    VJ_CHECK(adj_passes(p, g, ri, PK_MID_ADJ_SAVE, PK_LAST_ADJ, gtheta, nullptr, v));
+    // first layer: gth_1 += Im(conj(gv) v) on the support
+    {
+      const long long n = g.n;
+      const int groups = (int)std::min<long long>((n + 255) / 256, 1024);
+      hipLaunchKernelGGL(gth_support_kernel, dim3(groups), dim3(256), 0, p->stream, gvi, v, gth_of(p, g, gtheta, 1),
+                         g.N1, g.N2, g.o1, g.o2, (long long)g.M2);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return hip_fail(e, "gth_support");
+    }
+    // forward passes on gv with the cotangents of layers 2..L, then A gv
+    float2* cur = nullptr;
+    VJ_CHECK(fwd_passes(p, g, gvi, PK_MID_FWD_GT, gtheta, &cur));
+    if (gr != nullptr) {
+      const int k = g.L + 1;
+      PassArgs a = base_args(p, g, k);
+      set_in(a, g, k, cur);
+      a.scale_mid = 1.f / std::sqrt((float)pass_len(g, k));
+      a.z_out = gr + p->yoff[i];
+      VJ_CHECK(launch(p, g, k, PK_LAST_STORE, a));
+    }
+  }
+  return SR_OK;
+}
+
+}  // namespace sr

@@ -70,6 +70,7 @@ def _create(lib, probs, theta_len, theta=True, dense=None):
     ((16, 16), (32, 32), 2, 1000, -2),     # theta block out of range
     ((0, 16), (32, 32), 2, 2048, -2),      # empty signal
     ((40,), (100,), 1, 100, -3),           # 1D length 100 unsupported
+    ((4, 4), (8, 8), 1, 64, -3),           # 2D length 8 unsupported
     ((256,), (2048,), 4, 8192, -3),        # 1D needs L*m <= 4096
 ])
 def test_invalid_plans_are_rejected(lib, n, m, L, tlen, status):
