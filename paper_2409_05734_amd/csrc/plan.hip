@@ -132,5 +132,6 @@ sr_plan_s::~sr_plan_s() {
   for (auto& g : graphs) hipGraphExecDestroy(g.second);
   if (cap_stream) hipStreamDestroy(cap_stream);
   if (vjp_buf) hipFree(vjp_buf);
+  if (batch) sr::destroy_batch_state(batch);
   if (ws) hipFree(ws);
 }

@@ -28,6 +28,11 @@ sr_status hip_fail(hipError_t e, const char* what);
 
 }  // namespace sr
 
+namespace sr {
+struct BatchState;
+void destroy_batch_state(BatchState* s);
+}  // namespace sr
+
 struct sr_plan_s {
   std::vector<sr::Geo> geo;
   int kind = SR_STRUCTURED;
@@ -56,6 +61,7 @@ struct sr_plan_s {
   float* fscratch = nullptr;  // float scratch (dense solver scalars)
   unsigned* sync = nullptr;   // [0] grid-barrier counter, [1] barrier error flag
   float2* vjp_buf = nullptr;  // per-layer intermediates for derivatives (allocated on first use)
+  sr::BatchState* batch = nullptr;  // batched-schedule state (built on first batched solve)
   size_t vjp_elems = 0;
 
   int schedule = SR_SCHED_AUTO;
@@ -89,6 +95,10 @@ sr_status dense_forward(sr_plan_s* p, const float2* x, float2* z, float* y);
 sr_status dense_adjoint(sr_plan_s* p, const float2* r, float2* x);
 sr_status dense_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta, float* loss_trace);
 sr_status dense_spectral(sr_plan_s* p, const float* y, const float2* v0, int iters, float lam, float2* x0);
+
+// batched.hip (many problems advanced one pass level per launch)
+bool batched_supported(const sr_plan_s* p);
+sr_status batched_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta);
 
 // vjp.hip (reverse-mode derivatives of A and A^H)
 sr_status vjp_forward(sr_plan_s* p, const float2* x, const float2* gz, float2* gx, float* gtheta);

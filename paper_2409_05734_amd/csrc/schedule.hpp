@@ -4,7 +4,12 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdio>
+#include <cstdint>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "launch.hpp"
@@ -113,5 +118,75 @@ inline sr_status launch(sr_plan_s* p, const Geo& g, int k, int kind, const PassA
 }
 
 
+
+// ------------------------------------------------------------- graphs
+// Solver iterations are captured once into a hipGraph (on a private stream)
+// and replayed on the plan's stream: one graph launch per chunk of
+// iterations instead of 2L+1 kernel launches per iteration.  Graphs are
+// cached by the call's pointers and scalars; SR_GRAPH=0 disables them.
+
+constexpr int kGraphChunk = 50;  // iterations per captured graph (even)
+constexpr size_t kGraphCacheSize = 8;
+
+inline bool graphs_enabled(const sr_plan_s* p) {
+  if (p->schedule == SR_SCHED_LOOP) return false;
+  const char* e = std::getenv("SR_GRAPH");
+  return e == nullptr || std::atoi(e) != 0;
+}
+
+template <class F>
+sr_status launch_captured(sr_plan_s* p, const std::string& key, F&& enqueue) {
+  for (auto it = p->graphs.begin(); it != p->graphs.end(); ++it) {
+    if (it->first == key) {
+      hipGraphExec_t ex = it->second;
+      std::rotate(it, it + 1, p->graphs.end());  // most recent last
+      {
+        hipError_t le = hipGraphLaunch(ex, p->stream);
+        if (le != hipSuccess) return hip_fail(le, "hipGraphLaunch");
+      }
+      return SR_OK;
+    }
+  }
+  hipStream_t user = p->stream;
+  p->stream = p->cap_stream;
+  hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) {
+    p->stream = user;
+    return hip_fail(e, "hipStreamBeginCapture");
+  }
+  sr_status st = enqueue();
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(p->cap_stream, &graph);
+  p->stream = user;
+  if (st != SR_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  if (p->graphs.size() >= kGraphCacheSize) {
+    hipGraphExecDestroy(p->graphs.front().second);
+    p->graphs.erase(p->graphs.begin());
+  }
+  p->graphs.push_back({key, ex});
+  e = hipGraphLaunch(ex, p->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return SR_OK;
+}
+
+inline std::string ptr_key(const void* a) {
+  char buf[32];
+  std::snprintf(buf, sizeof(buf), "%p", a);
+  return buf;
+}
+
+inline std::string float_key(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return std::to_string(u);
+}
 
 }  // namespace sr

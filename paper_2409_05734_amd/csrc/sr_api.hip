@@ -205,6 +205,12 @@ static sr_status gd_iter_2d(sr_plan_s* p, const Geo& g, const float* y, float2* 
   return adjoint_body(p, g, back, PK_LAST_GD, x, step, 0.f, nullptr, 0, nullptr);
 }
 
+namespace sr {
+sr_status gd_iter_2d_public(sr_plan_s* p, const Geo& g, const float* y, float2* x, float step, float* loss_part) {
+  return gd_iter_2d(p, g, y, x, step, loss_part);
+}
+}  // namespace sr
+
 static sr_status spec_iter_2d(sr_plan_s* p, const Geo& g, const float* y, float2* u, float lam, float inv_mc,
                               const double* ysum, const float* part_in, int npart_in, float* part_out) {
   float2* cur = nullptr;
@@ -220,72 +226,6 @@ static int turn_groups(const sr_plan_s* p, const Geo& g) {
   const int ntr = (k == 2) ? g.M1 : (pass_col(k) ? g.M2 : g.M1);
   const int N = pass_len(g, k);
   return pass_groups(N, pass_col(k), p->tile(N, pass_col(k)), ntr);
-}
-
-// ------------------------------------------------------------- graphs
-// Solver iterations are captured once into a hipGraph (on a private stream)
-// and replayed on the plan's stream: one graph launch per chunk of
-// iterations instead of 2L+1 kernel launches per iteration.  Graphs are
-// cached by the call's pointers and scalars; SR_GRAPH=0 disables them.
-
-constexpr int kGraphChunk = 50;  // iterations per captured graph (even)
-constexpr size_t kGraphCacheSize = 8;
-
-static bool graphs_enabled(const sr_plan_s* p) {
-  if (p->schedule == SR_SCHED_LOOP) return false;
-  const char* e = std::getenv("SR_GRAPH");
-  return e == nullptr || std::atoi(e) != 0;
-}
-
-template <class F>
-static sr_status launch_captured(sr_plan_s* p, const std::string& key, F&& enqueue) {
-  for (auto it = p->graphs.begin(); it != p->graphs.end(); ++it) {
-    if (it->first == key) {
-      hipGraphExec_t ex = it->second;
-      std::rotate(it, it + 1, p->graphs.end());  // most recent last
-      SR_HIP(hipGraphLaunch(ex, p->stream));
-      return SR_OK;
-    }
-  }
-  hipStream_t user = p->stream;
-  p->stream = p->cap_stream;
-  hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed);
-  if (e != hipSuccess) {
-    p->stream = user;
-    return hip_fail(e, "hipStreamBeginCapture");
-  }
-  sr_status st = enqueue();
-  hipGraph_t graph = nullptr;
-  e = hipStreamEndCapture(p->cap_stream, &graph);
-  p->stream = user;
-  if (st != SR_OK) {
-    if (graph) hipGraphDestroy(graph);
-    return st;
-  }
-  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-  hipGraphExec_t ex = nullptr;
-  e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
-  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-  if (p->graphs.size() >= kGraphCacheSize) {
-    hipGraphExecDestroy(p->graphs.front().second);
-    p->graphs.erase(p->graphs.begin());
-  }
-  p->graphs.push_back({key, ex});
-  SR_HIP(hipGraphLaunch(ex, p->stream));
-  return SR_OK;
-}
-
-static std::string ptr_key(const void* a) {
-  char buf[32];
-  std::snprintf(buf, sizeof(buf), "%p", a);
-  return buf;
-}
-
-static std::string float_key(float f) {
-  uint32_t u;
-  std::memcpy(&u, &f, 4);
-  return std::to_string(u);
 }
 
 // ------------------------------------------------------------------ tuner
@@ -647,6 +587,8 @@ sr_status sr_gd_solve(sr_plan p, const float* y, void* x_inout, int32_t iters, c
   if (iters == 0) return SR_OK;
   float2* xs = (float2*)x_inout;
   if (p->kind == SR_DENSE) return dense_gd(p, y, xs, iters, eta_host, loss_trace);
+  const bool want_batched = p->schedule == SR_SCHED_BATCHED || (p->schedule == SR_SCHED_AUTO && p->geo.size() >= 8);
+  if (want_batched && loss_trace == nullptr && batched_supported(p)) return batched_gd(p, y, xs, iters, eta_host);
   for (size_t i = 0; i < p->geo.size(); ++i) {
     const Geo& g = p->geo[i];
     const float* yi = y + p->yoff[i];
