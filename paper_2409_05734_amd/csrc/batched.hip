@@ -55,6 +55,10 @@ __device__ __forceinline__ void run_kind(const PassArgs& a, int kind, int tile, 
       case PK_LAST_GD:
         pass_tile<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_GD>(a, tile, lds, red, nullptr, 0, nullptr);
         return;
+      case PK_LAST_GD_FWD:
+        pass_tile<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_GD_FWD>(a, tile, lds, red, nullptr, 0,
+                                                                                  nullptr);
+        return;
       default:
         break;
     }
@@ -122,18 +126,27 @@ int batch_tile_width(int N) {
 
 }  // namespace
 
-// Per-plan state of the batched schedule (device descriptors + item lists of
-// each level, private pass buffers), rebuilt when the call's pointers change.
-struct BatchState {
-  std::string key;
-  float2* bufs = nullptr;  // per problem: two full grids
+// Level lists of one recorded pass sequence (device descriptors and items).
+struct LevelSet {
   BatchDesc* d_descs = nullptr;
   BatchItem* d_items = nullptr;
   std::vector<int> level_off, level_cnt;  // item ranges per level
-  ~BatchState() {
-    if (bufs) hipFree(bufs);
+  ~LevelSet() {
     if (d_descs) hipFree(d_descs);
     if (d_items) hipFree(d_items);
+  }
+};
+
+// Per-plan state of the batched schedule, rebuilt when the call's pointers
+// change: private pass buffers and three level sets -- the first pass of
+// every problem, the steady iteration (ending with the update fused with the
+// next first pass), and the final iteration (plain update).
+struct BatchState {
+  std::string key;
+  float2* bufs = nullptr;  // per problem: two full grids
+  LevelSet first, steady, last;
+  ~BatchState() {
+    if (bufs) hipFree(bufs);
   }
 };
 
@@ -146,9 +159,53 @@ bool batched_supported(const sr_plan_s* p) {
   return true;
 }
 
-sr_status gd_iter_2d_public(sr_plan_s* p, const Geo& g, const float* y, float2* x, float step, float* loss_part);
+sr_status gd_first_pass_public(sr_plan_s* p, const Geo& g, const float2* x);
+sr_status gd_steady_public(sr_plan_s* p, const Geo& g, const float* y, float2* x, float step, bool last);
 
-// Build (or reuse) the level lists for GD on (y, x, eta).
+// Turn per-problem pass recordings into levels (level q = pass q of every
+// problem that has one) and upload them.
+static sr_status build_levels(sr_plan_s* p, const std::vector<std::vector<PassRecord>>& recs, LevelSet& ls) {
+  size_t max_levels = 0;
+  for (const auto& r : recs) max_levels = std::max(max_levels, r.size());
+  std::vector<BatchDesc> descs;
+  std::vector<BatchItem> items;
+  ls.level_off.assign(max_levels, 0);
+  ls.level_cnt.assign(max_levels, 0);
+  for (size_t q = 0; q < max_levels; ++q) {
+    ls.level_off[q] = (int)items.size();
+    for (size_t i = 0; i < recs.size(); ++i) {
+      if (q >= recs[i].size()) continue;
+      const PassRecord& r = recs[i][q];
+      const Geo& g = p->geo[i];
+      BatchDesc d;
+      std::memset(&d, 0, sizeof(d));
+      d.a = r.a;
+      d.N = pass_len(g, r.k);
+      d.col = pass_col(r.k);
+      d.kind = r.kind;
+      const int B = batch_tile_width(d.N);
+      const int di = (int)descs.size();
+      descs.push_back(d);
+      for (int t = 0; t * B < r.a.ntr; ++t) items.push_back({di, t});
+    }
+    ls.level_cnt[q] = (int)items.size() - ls.level_off[q];
+  }
+  if (ls.d_descs) hipFree(ls.d_descs);
+  if (ls.d_items) hipFree(ls.d_items);
+  ls.d_descs = nullptr;
+  ls.d_items = nullptr;
+  hipError_t e = hipMalloc(&ls.d_descs, std::max<size_t>(descs.size(), 1) * sizeof(BatchDesc));
+  if (e == hipSuccess) e = hipMalloc(&ls.d_items, std::max<size_t>(items.size(), 1) * sizeof(BatchItem));
+  if (e != hipSuccess) return fail(SR_E_NOMEM, "batched descriptor allocation failed");
+  e = hipMemcpyAsync(ls.d_descs, descs.data(), descs.size() * sizeof(BatchDesc), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ls.d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);  // the host vectors go out of scope
+  if (e != hipSuccess) return hip_fail(e, "batched descriptor upload");
+  return SR_OK;
+}
+
+// Build (or reuse) the level sets for GD on (y, x, eta).
 static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const float* eta, BatchState** out) {
   std::string key = std::to_string((uintptr_t)y) + ":" + std::to_string((uintptr_t)x);
   for (size_t i = 0; i < p->geo.size(); ++i) {
@@ -172,71 +229,45 @@ static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const fl
       return fail(SR_E_NOMEM, "batched workspace allocation failed");
     }
   }
-  st->key = key;
-  // record every problem's iteration with its private buffers
-  std::vector<std::vector<PassRecord>> recs(p->geo.size());
+  st->key.clear();
+  const size_t np = p->geo.size();
+  std::vector<std::vector<PassRecord>> rec_first(np), rec_steady(np), rec_last(np);
   float2* saveA = p->bufA;
   float2* saveB = p->bufB;
   size_t off = 0;
-  size_t max_levels = 0;
   sr_status status = SR_OK;
-  for (size_t i = 0; i < p->geo.size() && status == SR_OK; ++i) {
+  for (size_t i = 0; i < np && status == SR_OK; ++i) {
     const Geo& g = p->geo[i];
-    p->bufA = st->bufs + off;
+    p->bufA = st->bufs + off;  // each problem's private ping-pong buffers
     p->bufB = st->bufs + off + g.m;
     off += 2 * (size_t)g.m;
-    g_recording = &recs[i];
-    status = gd_iter_2d_public(p, g, y + p->yoff[i], x + p->xoff[i], eta[i] / (float)g.m, nullptr);
+    const float* yi = y + p->yoff[i];
+    float2* xi = x + p->xoff[i];
+    const float step = eta[i] / (float)g.m;
+    g_recording = &rec_first[i];
+    status = gd_first_pass_public(p, g, xi);
+    g_recording = &rec_steady[i];
+    if (status == SR_OK) status = gd_steady_public(p, g, yi, xi, step, false);
+    g_recording = &rec_last[i];
+    if (status == SR_OK) status = gd_steady_public(p, g, yi, xi, step, true);
     g_recording = nullptr;
-    max_levels = std::max(max_levels, recs[i].size());
   }
   p->bufA = saveA;
   p->bufB = saveB;
   if (status != SR_OK) return status;
-  std::vector<BatchDesc> descs;
-  std::vector<BatchItem> items;
-  st->level_off.assign(max_levels, 0);
-  st->level_cnt.assign(max_levels, 0);
-  for (size_t q = 0; q < max_levels; ++q) {
-    st->level_off[q] = (int)items.size();
-    for (size_t i = 0; i < recs.size(); ++i) {
-      if (q >= recs[i].size()) continue;
-      const PassRecord& r = recs[i][q];
-      const Geo& g = p->geo[i];
-      BatchDesc d;
-      std::memset(&d, 0, sizeof(d));
-      d.a = r.a;
-      d.N = pass_len(g, r.k);
-      d.col = pass_col(r.k);
-      d.kind = r.kind;
-      const int B = batch_tile_width(d.N);
-      const int di = (int)descs.size();
-      descs.push_back(d);
-      for (int t = 0; t * B < r.a.ntr; ++t) items.push_back({di, t});
-    }
-    st->level_cnt[q] = (int)items.size() - st->level_off[q];
-  }
-  if (st->d_descs) hipFree(st->d_descs);
-  if (st->d_items) hipFree(st->d_items);
-  st->d_descs = nullptr;
-  st->d_items = nullptr;
-  hipError_t e = hipMalloc(&st->d_descs, descs.size() * sizeof(BatchDesc));
-  if (e == hipSuccess) e = hipMalloc(&st->d_items, items.size() * sizeof(BatchItem));
-  if (e != hipSuccess) return fail(SR_E_NOMEM, "batched descriptor allocation failed");
-  e = hipMemcpyAsync(st->d_descs, descs.data(), descs.size() * sizeof(BatchDesc), hipMemcpyHostToDevice, p->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(st->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice, p->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);  // host vectors go out of scope
-  if (e != hipSuccess) return hip_fail(e, "batched descriptor upload");
+  if ((status = build_levels(p, rec_first, st->first)) != SR_OK) return status;
+  if ((status = build_levels(p, rec_steady, st->steady)) != SR_OK) return status;
+  if ((status = build_levels(p, rec_last, st->last)) != SR_OK) return status;
+  st->key = key;
   *out = st;
   return SR_OK;
 }
 
-static sr_status batch_iteration(sr_plan_s* p, BatchState* st) {
-  for (size_t q = 0; q < st->level_cnt.size(); ++q) {
-    if (st->level_cnt[q] == 0) continue;
-    hipLaunchKernelGGL(batched_level_kernel, dim3(st->level_cnt[q]), dim3(kBatchThreads), kBatchLds, p->stream,
-                       st->d_items + st->level_off[q], st->d_descs);
+static sr_status run_levels(sr_plan_s* p, const LevelSet& ls) {
+  for (size_t q = 0; q < ls.level_cnt.size(); ++q) {
+    if (ls.level_cnt[q] == 0) continue;
+    hipLaunchKernelGGL(batched_level_kernel, dim3(ls.level_cnt[q]), dim3(kBatchThreads), kBatchLds, p->stream,
+                       ls.d_items + ls.level_off[q], ls.d_descs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "batched level launch");
   }
@@ -248,13 +279,16 @@ sr_status batched_gd(sr_plan_s* p, const float* y, float2* x, int iters, const f
   sr_status s = batch_prepare(p, y, x, eta, &st);
   if (s != SR_OK) return s;
   constexpr int kChunk = 50;
+  if (iters <= 0) return SR_OK;
+  s = run_levels(p, st->first);
+  if (s != SR_OK) return s;
   int it = 0;
-  if (iters >= kChunk && graphs_enabled(p)) {
+  if (iters - 1 >= kChunk && graphs_enabled(p)) {
     const std::string gkey = "batch:" + st->key;
-    for (; it + kChunk <= iters; it += kChunk) {
+    for (; it + kChunk <= iters - 1; it += kChunk) {
       s = launch_captured(p, gkey, [&]() -> sr_status {
         for (int c = 0; c < kChunk; ++c) {
-          sr_status q = batch_iteration(p, st);
+          sr_status q = run_levels(p, st->steady);
           if (q != SR_OK) return q;
         }
         return SR_OK;
@@ -262,11 +296,11 @@ sr_status batched_gd(sr_plan_s* p, const float* y, float2* x, int iters, const f
       if (s != SR_OK) return s;
     }
   }
-  for (; it < iters; ++it) {
-    s = batch_iteration(p, st);
+  for (; it < iters - 1; ++it) {
+    s = run_levels(p, st->steady);
     if (s != SR_OK) return s;
   }
-  return SR_OK;
+  return run_levels(p, st->last);
 }
 
 }  // namespace sr

@@ -8,7 +8,7 @@ namespace sr {
 
 hipError_t launch_pass(int N, int kind, bool col, int B, const PassArgs& a, hipStream_t s) {
   if (B <= 0) B = default_tile(N, col);
-  const bool rev = kind >= PK_MID_FWD_SAVE;
+  const bool rev = kind >= PK_MID_FWD_SAVE && kind <= PK_LAST_ADJ_GT;
   switch (N) {
 #define SR_CASE(n) \
   case n:          \

@@ -20,12 +20,15 @@ enum PassKind : int {
   PK_LAST_GD = 8,     // ... then x <- x - step * g
   PK_LAST_SPEC = 9,   // ... then u <- step * g - 2 lambda u/||u|| (+ norm partials)
   // reverse mode (derivatives with respect to the phases)
-  PK_MID_FWD_SAVE = 10,  // [F_a, D_k (save u_k), F_a]
+  PK_MID_FWD_SAVE = 10,  // (kinds 10..14 live in the reverse-mode kernel set)  // [F_a, D_k (save u_k), F_a]
   PK_MID_ADJ_GT = 11,    // [F_a^H, gth_k += Im(u conj(u_k)), D_k^*, F_a^H]
   PK_MID_ADJ_SAVE = 12,  // [F_a^H, D_k^* (save q_k), F_a^H]
   PK_MID_FWD_GT = 13,    // [F_a, gth_k += Im(conj(q) q_k), D_k, F_a]
   PK_LAST_ADJ_GT = 14,   // [F_0^H, gth_1 += Im(u conj(D_1 U x)), D_1^*, U^H]
-  PK_COUNT = 15
+  // GD / spectral update fused with the next iteration's [U, D_1, F_0]
+  PK_LAST_GD_FWD = 15,
+  PK_LAST_SPEC_FWD = 16,
+  PK_COUNT = 17
 };
 
 // Tile widths: each length is compiled for a few tile widths (transforms per

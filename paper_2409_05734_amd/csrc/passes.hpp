@@ -37,9 +37,14 @@ enum MidOp : int {
 enum PostOp : int {
   POST_STORE = 0,
   POST_PHASE_CONJ_STORE = 1,
-  POST_GD = 2,
-  POST_SPEC = 3,
-  POST_PHASE_CONJ_GT = 4  // gth_1 += Im(v conj(D_1 U x)), then D_1^* and crop
+  POST_GD = 2,            // x <- x - step g
+  POST_SPEC = 3,          // u <- s (step g - 2 lambda u), s = 1/||u|| (deferred normalisation)
+  POST_PHASE_CONJ_GT = 4,  // gth_1 += Im(v conj(D_1 U x)), then D_1^* and crop
+  // the next iteration's first pass fused behind the update: the new iterate,
+  // still in registers, is padded, multiplied by D_1 and transformed along
+  // axis 0 into out2 (the compact buffer the next row pass reads)
+  POST_GD_FWD = 5,
+  POST_SPEC_FWD = 6
 };
 
 struct PassArgs {
@@ -82,6 +87,8 @@ struct PassArgs {
   float2* save;          // per-layer intermediate on the grid (written or read)
   float* gth;            // phase-cotangent accumulator of this pass's diagonal (grid layout)
   const float2* xin;     // POST_PHASE_CONJ_GT: the signal x (crop layout = output layout)
+  float2* out2;          // POST_*_FWD: compact output of the fused forward transform
+  long long out2_ld;
 };
 
 // Sum of previous-iterate partials, identical on every thread (fixed order).
@@ -108,7 +115,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   constexpr bool MID_SAVED = (MID == MID_PHASE_CONJ_GT || MID == MID_PHASE_GT);
   constexpr bool MID_Y = (MID == MID_GD || MID == MID_SPEC);
   constexpr bool POST_PH = (POST != POST_STORE);
-  constexpr bool POST_X = (POST == POST_GD || POST == POST_SPEC);
+  constexpr bool POST_X = (POST == POST_GD || POST == POST_SPEC || POST == POST_GD_FWD || POST == POST_SPEC_FWD);
+  constexpr bool POST_FWD = (POST == POST_GD_FWD || POST == POST_SPEC_FWD);
+  constexpr bool POST_IS_GD = (POST == POST_GD || POST == POST_GD_FWD);
+  constexpr bool POST_IS_SPEC = (POST == POST_SPEC || POST == POST_SPEC_FWD);
   const int t = T::thread_t();
   const int bl = T::thread_b();
   const int b = tile * B + bl;
@@ -264,26 +274,38 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int k = T::elem(t, j);
+      float2 val = make_float2(0.f, 0.f);
       if (out_win(k)) {
-        float2 val = cscale(v[j], a.scale_out);
+        val = cscale(v[j], a.scale_out);
         if constexpr (POST == POST_PHASE_CONJ_GT) {
           const float2 u1 = cmul(xo[j], dq[j]);  // u_1 = D_1 U x at this position
           a.gth[gidx(k)] = gt[j] + (val.y * u1.x - val.x * u1.y);
         }
         if constexpr (POST_PH) val = cmulc(val, dq[j]);
-        if constexpr (POST == POST_GD) {
+        if constexpr (POST_IS_GD) {
           val = make_float2(xo[j].x - a.step * val.x, xo[j].y - a.step * val.y);
-        } else if constexpr (POST == POST_SPEC) {
-          const float c = a.two_lam * s_prev;
-          val = make_float2(a.step * val.x - c * xo[j].x, a.step * val.y - c * xo[j].y);
+        } else if constexpr (POST_IS_SPEC) {
+          val = make_float2(s_prev * (a.step * val.x - a.two_lam * xo[j].x),
+                            s_prev * (a.step * val.y - a.two_lam * xo[j].y));
           acc += cabs2(val);
         }
         a.out[out_addr(k)] = val;
       }
+      if constexpr (POST_FWD) v[j] = cmul(val, dq[j]);  // zero outside the support window
     }
   }
 
-  if constexpr (MID == MID_GD || POST == POST_SPEC) {
+  if constexpr (POST_FWD) {
+    T::template fft<false>(v, lds, ph, w, t, bl);
+    const float s1 = a.scale_out;  // 1/sqrt(M1) for both transforms of this column pass
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int k = T::elem(t, j);
+      if (active) a.out2[(long long)k * a.out2_ld + b] = cscale(v[j], s1);
+    }
+  }
+
+  if constexpr (MID == MID_GD || POST_IS_SPEC) {
     if (part_out != nullptr) {
       float sum = block_sum<T::THREADS>(acc, red);
       if (threadIdx.x == 0) part_out[tile] = sum;

@@ -47,6 +47,10 @@ hipError_t dispatch(int kind, const PassArgs& a, hipStream_t s) {
         return go<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_GD>(a, s);
       case PK_LAST_SPEC:
         return go<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_SPEC>(a, s);
+      case PK_LAST_GD_FWD:
+        return go<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_GD_FWD>(a, s);
+      case PK_LAST_SPEC_FWD:
+        return go<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_SPEC_FWD>(a, s);
       default:
         break;
     }

@@ -127,7 +127,7 @@ __global__ void __launch_bounds__((Tile<N, B, true>::THREADS)) persistent_kernel
       const float* part_in = nullptr;
       float* part_out = nullptr;
       if constexpr (OP == PO_SPEC) {
-        if (kind == PK_FIRST_FWD || kind == PK_LAST_SPEC) part_in = pin;
+        if (kind == PK_LAST_SPEC) part_in = pin;  // normalisation is applied in the last pass
         if (kind == PK_LAST_SPEC) part_out = pout;
       } else {
         if (p == pa.loss_pass && pa.loss_trace != nullptr) part_out = pa.part_base;

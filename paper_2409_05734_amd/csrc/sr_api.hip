@@ -74,31 +74,33 @@ using namespace sr;
 
 const float* sr_plan_s::theta_l(const Geo& g, int l) const { return theta + g.th_off + (int64_t)(l - 1) * g.m; }
 
-// Forward passes 1..L (through D_L's first transform), starting from x.
-// Returns the buffer holding the result (compact if L == 1, else full).
-static sr_status forward_body(sr_plan_s* p, const Geo& g, const float2* x, float in_scale, const float* part_in,
-                              int npart, float2** cur_out) {
+// Pass 1, [U, D_1, F_0] on the support columns of x, into the compact bufA.
+static sr_status first_pass(sr_plan_s* p, const Geo& g, const float2* x, float in_scale, const float* part_in,
+                            int npart) {
+  PassArgs a = base_args(p, g, 1);
+  a.in = x;
+  a.in_ld = g.N2;
+  a.in_lo = g.o1;
+  a.in_hi = g.o1 + g.N1;
+  a.ntr = g.N2;
+  a.tr_lo = g.o2;
+  a.th_pre = p->theta_l(g, 1);
+  a.scale_pre = in_scale;
+  a.part_in = part_in;
+  a.npart = npart;
+  a.out = p->bufA;
+  a.out_ld = g.N2;
+  a.out_lo = 0;
+  a.out_hi = g.M1;
+  a.scale_out = 1.f / std::sqrt((float)g.M1);
+  return launch(p, g, 1, PK_FIRST_FWD, a);
+}
+
+// Passes 2..L from the compact bufA.  Returns the buffer holding the result
+// (compact bufA if L == 1, else a full grid).
+static sr_status forward_rest(sr_plan_s* p, const Geo& g, float2** cur_out) {
   float2* bufs[2] = {p->bufA, p->bufB};
   int which = 0;
-  {
-    PassArgs a = base_args(p, g, 1);
-    a.in = x;
-    a.in_ld = g.N2;
-    a.in_lo = g.o1;
-    a.in_hi = g.o1 + g.N1;
-    a.ntr = g.N2;
-    a.tr_lo = g.o2;
-    a.th_pre = p->theta_l(g, 1);
-    a.scale_pre = in_scale;
-    a.part_in = part_in;
-    a.npart = npart;
-    a.out = bufs[which];
-    a.out_ld = g.N2;
-    a.out_lo = 0;
-    a.out_hi = g.M1;
-    a.scale_out = 1.f / std::sqrt((float)g.M1);
-    SR_CHECK(launch(p, g, 1, PK_FIRST_FWD, a));
-  }
   for (int k = 2; k <= g.L; ++k) {
     PassArgs a = base_args(p, g, k);
     set_in(a, g, k, bufs[which]);
@@ -114,11 +116,19 @@ static sr_status forward_body(sr_plan_s* p, const Geo& g, const float2* x, float
   return SR_OK;
 }
 
+// Forward passes 1..L (through D_L's first transform), starting from x.
+static sr_status forward_body(sr_plan_s* p, const Geo& g, const float2* x, float in_scale, const float* part_in,
+                              int npart, float2** cur_out) {
+  SR_CHECK(first_pass(p, g, x, in_scale, part_in, npart));
+  return forward_rest(p, g, cur_out);
+}
+
 // Adjoint passes L..1 starting from `cur` (layout of the output of pass L+1's
 // mirror: compact if L == 1, full otherwise), ending with the column pass that
 // applies D_1^*, crops, and performs `last_kind` into x.
 static sr_status adjoint_body(sr_plan_s* p, const Geo& g, float2* cur, int last_kind, float2* x, float step,
-                              float two_lam, const float* part_in, int npart, float* part_out) {
+                              float two_lam, const float* part_in, int npart, float* part_out,
+                              float2* out2 = nullptr) {
   float2* other = (cur == p->bufA) ? p->bufB : p->bufA;
   for (int k = g.L; k >= 2; --k) {
     PassArgs a = base_args(p, g, k);
@@ -149,6 +159,8 @@ static sr_status adjoint_body(sr_plan_s* p, const Geo& g, float2* cur, int last_
   a.part_in = part_in;
   a.npart = npart;
   a.part_out = part_out;
+  a.out2 = out2;
+  a.out2_ld = g.N2;
   return launch(p, g, 1, last_kind, a);
 }
 
@@ -205,20 +217,50 @@ static sr_status gd_iter_2d(sr_plan_s* p, const Geo& g, const float* y, float2* 
   return adjoint_body(p, g, back, PK_LAST_GD, x, step, 0.f, nullptr, 0, nullptr);
 }
 
-namespace sr {
-sr_status gd_iter_2d_public(sr_plan_s* p, const Geo& g, const float* y, float2* x, float step, float* loss_part) {
-  return gd_iter_2d(p, g, y, x, step, loss_part);
-}
-}  // namespace sr
 
+// One power iteration with deferred normalisation: the passes run on the
+// unnormalised iterate u and the last pass scales by 1/||u|| (A is linear and
+// T(y) does not depend on the scale).
 static sr_status spec_iter_2d(sr_plan_s* p, const Geo& g, const float* y, float2* u, float lam, float inv_mc,
                               const double* ysum, const float* part_in, int npart_in, float* part_out) {
   float2* cur = nullptr;
-  SR_CHECK(forward_body(p, g, u, 1.f, part_in, npart_in, &cur));
+  SR_CHECK(forward_body(p, g, u, 1.f, nullptr, 0, &cur));
   float2* back = nullptr;
   SR_CHECK(turnaround(p, g, cur, PK_TURN_SPEC, y, lam, ysum, nullptr, &back));
   return adjoint_body(p, g, back, PK_LAST_SPEC, u, inv_mc, 2.f * lam, part_in, npart_in, part_out);
 }
+
+// Steady-state iterations: passes 2..L, the turnaround and the adjoint
+// passes, then the update fused with the next iteration's pass 1 (writing the
+// compact bufA the next pass 2 reads).  `last` selects the plain update for
+// the final iteration.  2L launches per iteration instead of 2L+1.
+static sr_status gd_steady(sr_plan_s* p, const Geo& g, const float* y, float2* x, float step, float* loss_part,
+                           bool last) {
+  float2* cur = nullptr;
+  SR_CHECK(forward_rest(p, g, &cur));
+  float2* back = nullptr;
+  SR_CHECK(turnaround(p, g, cur, PK_TURN_GD, y, 0.f, nullptr, loss_part, &back));
+  return adjoint_body(p, g, back, last ? PK_LAST_GD : PK_LAST_GD_FWD, x, step, 0.f, nullptr, 0, nullptr,
+                      last ? nullptr : p->bufA);
+}
+
+static sr_status spec_steady(sr_plan_s* p, const Geo& g, const float* y, float2* u, float lam, float inv_mc,
+                             const double* ysum, const float* part_in, int npart_in, float* part_out, bool last) {
+  float2* cur = nullptr;
+  SR_CHECK(forward_rest(p, g, &cur));
+  float2* back = nullptr;
+  SR_CHECK(turnaround(p, g, cur, PK_TURN_SPEC, y, lam, ysum, nullptr, &back));
+  return adjoint_body(p, g, back, last ? PK_LAST_SPEC : PK_LAST_SPEC_FWD, u, inv_mc, 2.f * lam, part_in, npart_in,
+                      part_out, last ? nullptr : p->bufA);
+}
+
+namespace sr {
+// Entry points for the batched schedule, which records these pass sequences.
+sr_status gd_first_pass_public(sr_plan_s* p, const Geo& g, const float2* x) { return first_pass(p, g, x, 1.f, nullptr, 0); }
+sr_status gd_steady_public(sr_plan_s* p, const Geo& g, const float* y, float2* x, float step, bool last) {
+  return gd_steady(p, g, y, x, step, nullptr, last);
+}
+}  // namespace sr
 
 static int last_pass_groups(const sr_plan_s* p, const Geo& g) { return pass_groups(g.M1, true, p->tile(g.M1, true), g.N2); }
 static int turn_groups(const sr_plan_s* p, const Geo& g) {
@@ -611,17 +653,18 @@ sr_status sr_gd_solve(sr_plan p, const float* y, void* x_inout, int32_t iters, c
       continue;
     }
     const int nparts = turn_groups(p, g);
+    SR_CHECK(first_pass(p, g, xi, 1.f, nullptr, 0));
     int it = 0;
-    if (lt == nullptr && graphs_enabled(p) && iters >= kGraphChunk) {
+    if (lt == nullptr && graphs_enabled(p) && iters - 1 >= kGraphChunk) {
       const std::string key = "gd:" + std::to_string(i) + ":" + ptr_key(yi) + ":" + ptr_key(xi) + ":" + float_key(step);
-      for (; it + kGraphChunk <= iters; it += kGraphChunk)
+      for (; it + kGraphChunk <= iters - 1; it += kGraphChunk)
         SR_CHECK(launch_captured(p, key, [&]() -> sr_status {
-          for (int c = 0; c < kGraphChunk; ++c) SR_CHECK(gd_iter_2d(p, g, yi, xi, step, nullptr));
+          for (int c = 0; c < kGraphChunk; ++c) SR_CHECK(gd_steady(p, g, yi, xi, step, nullptr, false));
           return SR_OK;
         }));
     }
     for (; it < iters; ++it) {
-      SR_CHECK(gd_iter_2d(p, g, yi, xi, step, lt ? p->part : nullptr));
+      SR_CHECK(gd_steady(p, g, yi, xi, step, lt ? p->part : nullptr, it == iters - 1));
       if (lt) SR_CHECK(reduce_partials(p, p->part, nparts, lt + it));
     }
   }
@@ -668,26 +711,29 @@ sr_status sr_spectral_init(sr_plan p, const float* y, const void* v0, int32_t it
     } else {
       const int nq = last_pass_groups(p, g);
       int it = 0;
-      if (iters > 0) {  // the first iteration reads the start vector's single partial
-        SR_CHECK(spec_iter_2d(p, g, yi, xi, lambda, inv_mc, p->ysum, parts[0], npart, parts[1]));
+      if (iters > 0) SR_CHECK(first_pass(p, g, xi, 1.f, nullptr, 0));
+      if (iters > 1) {  // the first iteration reads the start vector's single partial
+        SR_CHECK(spec_steady(p, g, yi, xi, lambda, inv_mc, p->ysum, parts[0], npart, parts[1], false));
         npart = nq;
         it = 1;
       }
-      if (graphs_enabled(p) && iters - it >= kGraphChunk) {
+      if (graphs_enabled(p) && iters - 1 - it >= kGraphChunk) {
         // chunks start at odd iterations, so every chunk has the same partial-buffer parity
         const std::string key = "spec:" + std::to_string(i) + ":" + ptr_key(yi) + ":" + ptr_key(xi) + ":" +
                                 float_key(lambda);
-        for (; it + kGraphChunk <= iters; it += kGraphChunk)
+        for (; it + kGraphChunk <= iters - 1; it += kGraphChunk)
           SR_CHECK(launch_captured(p, key, [&]() -> sr_status {
             for (int c = 0; c < kGraphChunk; ++c) {
               const int q = it + c;
-              SR_CHECK(spec_iter_2d(p, g, yi, xi, lambda, inv_mc, p->ysum, parts[q & 1], nq, parts[(q + 1) & 1]));
+              SR_CHECK(spec_steady(p, g, yi, xi, lambda, inv_mc, p->ysum, parts[q & 1], nq, parts[(q + 1) & 1],
+                                   false));
             }
             return SR_OK;
           }));
       }
       for (; it < iters; ++it) {
-        SR_CHECK(spec_iter_2d(p, g, yi, xi, lambda, inv_mc, p->ysum, parts[it & 1], npart, parts[(it + 1) & 1]));
+        SR_CHECK(spec_steady(p, g, yi, xi, lambda, inv_mc, p->ysum, parts[it & 1], npart, parts[(it + 1) & 1],
+                             it == iters - 1));
         npart = nq;
       }
     }

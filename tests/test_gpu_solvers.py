@@ -163,10 +163,10 @@ def test_zero_iterations_and_edge_inputs(gpu):
 @pytest.mark.parametrize("n_shape,m_shape,L", [((256, 256), (512, 512), 2), ((100, 120), (256, 256), 3),
                                                ((128, 128), (256, 256), 1)])
 def test_schedules_agree(gpu, monkeypatch, n_shape, m_shape, L):
-    """Graph-replayed chunks, one launch per pass, and the single-launch
-    persistent solver compute every transform identically: GD iterates agree
-    bit for bit; spectral iterates agree to rounding (partial norms are
-    grouped by tile)."""
+    """Graph-replayed chunks and direct launches run the same kernels: GD
+    iterates agree bit for bit.  The single-launch persistent solver runs the
+    unfused pass sequence and groups partial norms by its own tiles: it agrees
+    to rounding."""
     import paper_2409_05734_amd as srpr
     rng = np.random.default_rng(50 + L)
     th, xs = random_problem(rng, n_shape, m_shape, L)
@@ -188,7 +188,8 @@ def test_schedules_agree(gpu, monkeypatch, n_shape, m_shape, L):
     s_loop = _run_spec(plan, y, v0, 111, -1.0, gpu)
     srpr.sr_plan_sync(plan)
     assert np.array_equal(g_auto, g_loop) and np.array_equal(g_auto2, g_loop)
-    assert np.array_equal(g_pers, g_loop)
+    # the persistent solver runs the unfused pass sequence (separate first pass)
+    assert rel_l2(g_pers, g_loop) < 1e-5
     assert np.max(np.abs(l_pers - l_loop) / l_loop) < 1e-5
     assert rel_l2(s_auto, s_loop) < 1e-5 and rel_l2(s_pers, s_loop) < 1e-5
     assert rel_l2(s_auto.reshape(n_shape), oracle.spectral_init(op, y, v0, 111, -1.0)) <= TOL_IT
