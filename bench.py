@@ -1,18 +1,24 @@
-"""Benchmark: gradient-descent iterations per second of structured random phase
-retrieval on one MI355X, for the 2D image workload (256x256 complex image,
-zero-padded to 512x512 so alpha = 4, L = 2 random phase layers, Poisson noise
-at 1000 photons per pixel, complex64).
+"""Benchmark of structured random phase retrieval on one MI355X.
 
-One step = one GD solve of 500 iterations (Eq. (2)) started from the spectral
-estimate; the spectral initialisation (100 power iterations, Eq. (3)-(4)) and
-single A / A^H applications are timed in the same run and reported beside it.
-Inputs are synthetic and seeded and live in HBM before the timed region.
+Headline (the JSON line's `value`): gradient-descent iterations per second on
+the 2D image workload -- a 256x256 complex image zero-padded to 512x512
+(alpha = 4), L = 2 random phase layers, Poisson noise at 1000 photons per
+pixel, complex64.  One step = one GD solve of 500 iterations (Eq. (2)) from
+the spectral estimate (100 power iterations, Eq. (3)-(4), timed alongside).
+Inputs are synthetic, seeded, and resident in HBM before the timed region.
 
-Prints one JSON line.  `python bench.py --steps K --warmup W`.
+Beside it (skipped with --quick): the 1024^2 -> 2048^2, L = 3 operator and
+solver, the dense i.i.d. MFMA baseline (16384 x 4096 complex64 A, 32
+signals), 256 uneven problems batched vs the per-problem loop, the
+64-problem mask-gradient (autograd) step vs a per-problem loop, the tiny 1D
+problem, and the FP64 oracle timed on the host (`cpu_baseline`).
+
+Prints one JSON line.  `python bench.py [--steps K] [--warmup W] [--quick]`.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,12 +31,18 @@ if HERE not in sys.path:
     sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
 GD_ITERS = 500
 PI_ITERS = 100
 
 
+# --------------------------------------------------------------------------
+# Algorithmic byte model of the fused pass schedule (per unit of work)
+# --------------------------------------------------------------------------
+
 def schedule_bytes_gd(n_shape, m_shape, L):
-    """Algorithmic HBM bytes of one GD iteration under the fused pass schedule.
+    """Algorithmic HBM bytes of one GD iteration under the fused pass schedule
+    (2L+1 passes, each one read and one write of its buffer).
 
     Pass 1 reads x (8n) and the support part of theta_1 (4n), writes the
     compact M1 x N2 buffer; each later pass reads and writes its buffer
@@ -40,8 +52,7 @@ def schedule_bytes_gd(n_shape, m_shape, L):
     N1, N2 = n_shape
     M1, M2 = m_shape
     n, m, mc = N1 * N2, M1 * M2, M1 * N2
-    b = 0
-    b += 8 * n + 4 * n + 8 * mc                       # [U D1 F0]
+    b = 8 * n + 4 * n + 8 * mc                       # [U D1 F0]
     for k in range(2, L + 1):                          # [F D_k F]
         b += 8 * (mc if k == 2 else m) + 4 * m + 8 * m
     b += 8 * (mc if L == 1 else m) + 4 * m + 8 * (mc if L == 1 else m)  # turnaround (+ y)
@@ -52,7 +63,7 @@ def schedule_bytes_gd(n_shape, m_shape, L):
 
 
 def schedule_bytes_op(n_shape, m_shape, L):
-    """Algorithmic bytes of one A application (x in, z out)."""
+    """Algorithmic bytes of one A (or A^H) application (x in, z out)."""
     N1, N2 = n_shape
     M1, M2 = m_shape
     n, m, mc = N1 * N2, M1 * M2, M1 * N2
@@ -61,6 +72,50 @@ def schedule_bytes_op(n_shape, m_shape, L):
         b += 8 * (mc if k == 2 else m) + 4 * m + 8 * m
     b += 8 * (mc if L == 1 else m) + 8 * m
     return b
+
+
+def source_hash() -> str:
+    """Hash of the HIP sources, to tell whether stored counter data is stale."""
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "paper_2409_05734_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic():
+    """Measured HBM bytes per GD iteration from the committed counter summary,
+    if it was taken on the current kernels (else None)."""
+    path = os.path.join(HERE, "profiles", "gd_image_512_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        if d.get("source_hash") == source_hash():
+            return d.get("bytes_per_gd_iteration")
+    except Exception:
+        pass
+    return None
+
+
+# --------------------------------------------------------------------------
+# helpers
+# --------------------------------------------------------------------------
+
+def _events(torch, n):
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def _time_calls(torch, stream, fn, reps, warm=3):
+    for _ in range(warm):
+        fn()
+    a, b = _events(torch, 2)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps  # ms
 
 
 def cpu_baseline(d, y, x0, eta, budget_s=12.0):
@@ -83,7 +138,231 @@ def cpu_baseline(d, y, x0, eta, budget_s=12.0):
             break
     return {"value": it / el, "unit": "GD iters/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{it} GD iterations of the FP64 explicit-DFT oracle on the same 256^2 -> 512^2, L=2 "
-                      f"problem ({el:.1f} s)"}
+                      f"problem ({el:.1f} s, {threads} BLAS threads, {os.cpu_count()} host cores visible)"}
+
+
+def make_measurements(torch, srpr, plan, x_star, noise_rng, photons, dev):
+    """Noiseless intensities from the library's forward operator, then Poisson
+    photon noise drawn on the host (the noise model is an input, not the method)."""
+    import sr_inputs
+    m = plan.m_total
+    yclean = torch.empty(m, dtype=torch.float32, device=dev)
+    srpr.sr_forward(plan, torch.from_numpy(x_star.ravel()).to(dev), None, yclean)
+    torch.cuda.synchronize()
+    if noise_rng is None:
+        return yclean
+    return torch.from_numpy(sr_inputs.poisson_counts(noise_rng, yclean.cpu().numpy(), photons)).to(dev)
+
+
+# --------------------------------------------------------------------------
+# workloads
+# --------------------------------------------------------------------------
+
+def headline(torch, srpr, sr_inputs, dev, steps, warmup):
+    d = sr_inputs.image_2d(1)
+    n_shape, m_shape, L = d["n_shape"], d["m_shape"], d["layers"]
+    n, m = int(np.prod(n_shape)), int(np.prod(m_shape))
+    plan = srpr.Plan([srpr.Problem(n_shape, m_shape, L)], d["theta"])
+    stream = plan.stream
+    y = make_measurements(torch, srpr, plan, d["x_star"], d["noise_rng"], d["photons"], dev)
+    y_h = y.cpu().numpy()
+    v0 = torch.from_numpy(d["v0"].ravel()).to(dev)
+    x0 = torch.empty(n, dtype=torch.complex64, device=dev)
+    eta = float(d["mu"] * m / float(y_h.astype(np.float64).mean()))  # mu / (c mean(y)), c = 1/m
+
+    srpr.sr_spectral_init(plan, y, v0, PI_ITERS, d["lam"], x0)
+    pi_ms = _time_calls(torch, stream, lambda: srpr.sr_spectral_init(plan, y, v0, PI_ITERS, d["lam"], x0), 5)
+
+    x = torch.empty_like(x0)
+    for _ in range(warmup):
+        x.copy_(x0)
+        srpr.sr_gd_solve(plan, y, x, GD_ITERS, eta)
+    torch.cuda.synchronize()
+    ev = [_events(torch, 2) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        x.copy_(x0)
+        ev[i][0].record(stream)
+        srpr.sr_gd_solve(plan, y, x, GD_ITERS, eta)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    solve_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    xs = torch.from_numpy(d["x_star"].ravel()).to(dev)
+    z = torch.empty(m, dtype=torch.complex64, device=dev)
+    r = torch.randn(m, dtype=torch.complex64, device=dev)
+    xa = torch.empty(n, dtype=torch.complex64, device=dev)
+    fwd_ms = _time_calls(torch, stream, lambda: srpr.sr_forward(plan, xs, z, None), 200)
+    adj_ms = _time_calls(torch, stream, lambda: srpr.sr_adjoint(plan, r, xa), 200)
+    op_bytes = schedule_bytes_op(n_shape, m_shape, L)
+    gd_bytes = schedule_bytes_gd(n_shape, m_shape, L)
+
+    xh = x.cpu().numpy().astype(np.complex128)
+    xt = d["x_star"].ravel().astype(np.complex128)
+    cos = float(abs(np.vdot(xh, xt)) / (np.linalg.norm(xh) * np.linalg.norm(xt)))
+    it_us = solve_ms * 1e3 / GD_ITERS
+    achieved = gd_bytes / (it_us * 1e-6) / 1e9
+    traffic = stored_traffic()
+    return {
+        "value": GD_ITERS * steps / wall,
+        "ms_per_step": wall * 1e3 / steps,
+        "solve_ms_events": solve_ms,
+        "gd_iteration_us": it_us,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "one fused GD iteration (2L = 4 pass kernels in steady state, graph-replayed)",
+                     "bytes_per_unit": gd_bytes, "unit_of_work": "GD iteration"},
+        "operator": {"A_us": fwd_ms * 1e3, "AH_us": adj_ms * 1e3,
+                     "A_GBps": op_bytes / (fwd_ms * 1e-3) / 1e9, "AH_GBps": op_bytes / (adj_ms * 1e-3) / 1e9,
+                     "bytes_per_application": op_bytes},
+        "spectral_init": {"iters": PI_ITERS, "ms": pi_ms, "iters_per_s": PI_ITERS / (pi_ms * 1e-3)},
+        "cosine_similarity": cos,
+        "_cpu": (d, y_h.reshape(m_shape), x0.cpu().numpy().reshape(n_shape), eta),
+    }
+
+
+def large_2d(torch, srpr, sr_inputs, dev):
+    d = sr_inputs.large_2d(4)
+    n_shape, m_shape, L = d["n_shape"], d["m_shape"], d["layers"]
+    n, m = int(np.prod(n_shape)), int(np.prod(m_shape))
+    plan = srpr.Plan([srpr.Problem(n_shape, m_shape, L)], d["theta"])
+    s = plan.stream
+    y = make_measurements(torch, srpr, plan, d["x_star"], d["noise_rng"], d["photons"], dev)
+    v0 = torch.from_numpy(d["v0"].ravel()).to(dev)
+    x = torch.empty(n, dtype=torch.complex64, device=dev)
+    pi_ms = _time_calls(torch, s, lambda: srpr.sr_spectral_init(plan, y, v0, d["pi_iters"], d["lam"], x), 2, warm=1)
+    eta = float(d["mu"] * m / float(y.double().mean().item()))
+    x0 = x.clone()
+
+    def solve():
+        x.copy_(x0)
+        srpr.sr_gd_solve(plan, y, x, d["gd_iters"], eta)
+    gd_ms = _time_calls(torch, s, solve, 3, warm=1)
+    xs = torch.from_numpy(d["x_star"].ravel()).to(dev)
+    z = torch.empty(m, dtype=torch.complex64, device=dev)
+    fwd_ms = _time_calls(torch, s, lambda: srpr.sr_forward(plan, xs, z, None), 20)
+    adj_ms = _time_calls(torch, s, lambda: srpr.sr_adjoint(plan, z, x), 20)
+    op_bytes = schedule_bytes_op(n_shape, m_shape, L)
+    gd_bytes = schedule_bytes_gd(n_shape, m_shape, L)
+    it_us = gd_ms * 1e3 / d["gd_iters"]
+    return {"workload": "1024^2 -> 2048^2 (alpha=4), L=3, Poisson 1000 photons",
+            "gd_iters_per_s": d["gd_iters"] / (gd_ms * 1e-3), "gd_iteration_us": it_us,
+            "gd_GBps": gd_bytes / (it_us * 1e-6) / 1e9, "gd_frac_hbm": gd_bytes / (it_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "bytes_per_gd_iteration": gd_bytes,
+            "spectral_iters_per_s": d["pi_iters"] / (pi_ms * 1e-3),
+            "A_us": fwd_ms * 1e3, "AH_us": adj_ms * 1e3,
+            "A_GBps": op_bytes / (fwd_ms * 1e-3) / 1e9, "AH_GBps": op_bytes / (adj_ms * 1e-3) / 1e9}
+
+
+def dense(torch, srpr, sr_inputs, dev):
+    db = sr_inputs.dense_batch(4)
+    A = torch.from_numpy(db["dense_A"]).to(dev)
+    X = torch.from_numpy(db["X"].ravel()).to(dev)
+    R = torch.from_numpy(db["R"].ravel()).to(dev)
+    del db
+    m, n, nb = 16384, 4096, 32
+    plan = srpr.Plan([srpr.Problem((n,), (m,), 1, kind=srpr.SR_DENSE) for _ in range(nb)], None, dense_A=A)
+    s = plan.stream
+    Z = torch.empty(nb * m, dtype=torch.complex64, device=dev)
+    V = torch.empty(nb * n, dtype=torch.complex64, device=dev)
+    fwd_ms = _time_calls(torch, s, lambda: srpr.sr_forward(plan, X, Z, None), 20)
+    adj_ms = _time_calls(torch, s, lambda: srpr.sr_adjoint(plan, R, V), 20)
+    flops = 8.0 * m * n * nb
+    bytes_ = 8.0 * m * n + 8.0 * nb * (m + n)
+    return {"workload": "dense i.i.d. CN(0,1) A 16384 x 4096 complex64 (512 MiB), 32 signals, FP32 MFMA",
+            "A_us": fwd_ms * 1e3, "AH_us": adj_ms * 1e3,
+            "A_TFLOPs": flops / (fwd_ms * 1e-3) / 1e12, "AH_TFLOPs": flops / (adj_ms * 1e-3) / 1e12,
+            "A_frac_mfma": flops / (fwd_ms * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS,
+            "AH_frac_mfma": flops / (adj_ms * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS,
+            "A_GBps": bytes_ / (fwd_ms * 1e-3) / 1e9}
+
+
+def batched(torch, srpr, sr_inputs, dev, iters=300):
+    probs = sr_inputs.batched_mixed(2, 256)
+    plan = srpr.Plan([srpr.Problem(p["n_shape"], p["m_shape"], p["layers"]) for p in probs],
+                     np.concatenate([p["theta"].ravel() for p in probs]))
+    s = plan.stream
+    xs = np.concatenate([p["x_star"].ravel() for p in probs])
+    y = torch.empty(plan.m_total, dtype=torch.float32, device=dev)
+    srpr.sr_forward(plan, torch.from_numpy(xs).to(dev), None, y)
+    yh = y.cpu().numpy()
+    eta = np.array([p["mu"] * int(np.prod(p["m_shape"])) / float(np.mean(yh[plan.y_off[i]:plan.y_off[i + 1]]))
+                    for i, p in enumerate(probs)], dtype=np.float32)
+    x0 = torch.from_numpy(np.concatenate([p["x0"].ravel() for p in probs])).to(dev)
+    x = torch.empty_like(x0)
+
+    def run():
+        x.copy_(x0)
+        srpr.sr_gd_solve(plan, y, x, iters, eta)
+    srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_BATCHED)
+    b_ms = _time_calls(torch, s, run, 3, warm=1)
+    xb = x.clone()
+    srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_LOOP)
+    l_ms = _time_calls(torch, s, run, 1, warm=1)
+    rel = float(((xb - x).abs().pow(2).sum() / x.abs().pow(2).sum()).sqrt().item())
+    byt = sum(schedule_bytes_gd(p["n_shape"], p["m_shape"], p["layers"]) for p in probs)
+    return {"workload": "256 problems, N in {32,64,96,128}^2, alpha in {2,4,8}, L in {1,2,3}, 300 GD steps",
+            "batched_ms": b_ms, "loop_ms": l_ms, "speedup_vs_loop": l_ms / b_ms,
+            "batched_gd_iters_per_s": iters / (b_ms * 1e-3),
+            "batched_GBps": byt * iters / (b_ms * 1e-3) / 1e9, "bytes_per_batched_iteration": byt,
+            "batched_vs_loop_rel_diff": rel}
+
+
+def autograd(torch, srpr, sr_inputs, dev):
+    from paper_2409_05734_amd.autograd import unrolled_gd_loss
+    d = sr_inputs.mask_design(3)
+    B, L = d["x_star"].shape[0], d["layers"]
+    n_shape, m_shape = d["n_shape"], d["m_shape"]
+    th = torch.from_numpy(d["theta"].ravel()).to(dev)
+    xs = torch.from_numpy(d["x_star"].reshape(B, -1)).to(dev)
+    x0 = torch.from_numpy(d["x0"].reshape(B, -1)).to(dev)
+    plan = srpr.Plan([srpr.Problem(n_shape, m_shape, L, theta_offset=0) for _ in range(B)], d["theta"])
+    singles = [srpr.Plan([srpr.Problem(n_shape, m_shape, L, theta_offset=0)], d["theta"]) for _ in range(1)]
+    s = plan.stream
+
+    def batch_step():
+        t = th.clone().requires_grad_(True)
+        loss = unrolled_gd_loss(plan, t, xs, x0, d["steps"], d["mu"])
+        loss.backward()
+        return t.grad
+
+    def loop_step():
+        t = th.clone().requires_grad_(True)
+        tot = 0.0
+        for b in range(B):
+            tot = tot + unrolled_gd_loss(singles[0], t, xs[b:b + 1], x0[b:b + 1], d["steps"], d["mu"]) / B
+        tot.backward()
+        return t.grad
+
+    g1 = batch_step()
+    g2 = loop_step()
+    rel = float(((g1 - g2).norm() / g2.norm()).item())
+    b_ms = _time_calls(torch, s, batch_step, 2, warm=1)
+    l_ms = _time_calls(torch, s, loop_step, 1, warm=0)
+    return {"workload": "64 problems 128^2 -> 256^2, L=2, loss after 20 unrolled GD steps, d loss / d theta",
+            "batched_plan_ms": b_ms, "per_problem_loop_ms": l_ms, "speedup_vs_loop": l_ms / b_ms,
+            "grad_rel_diff_vs_loop": rel}
+
+
+def tiny_1d(torch, srpr, sr_inputs, dev):
+    d = sr_inputs.tiny_1d(0)
+    plan = srpr.Plan([srpr.Problem(d["n_shape"], d["m_shape"], d["layers"])], d["theta"])
+    s = plan.stream
+    y = make_measurements(torch, srpr, plan, d["x_star"], None, 0, dev)
+    v0 = torch.from_numpy(d["v0"]).to(dev)
+    x = torch.empty(64, dtype=torch.complex64, device=dev)
+    eta = float(d["mu"] * 256 / float(y.double().mean().item()))
+
+    def solve():
+        srpr.sr_spectral_init(plan, y, v0, d["pi_iters"], d["lam"], x)
+        srpr.sr_gd_solve(plan, y, x, d["gd_iters"], eta)
+    ms = _time_calls(torch, s, solve, 20)
+    xh = x.cpu().numpy().astype(np.complex128)
+    xt = d["x_star"].astype(np.complex128)
+    cos = float(abs(np.vdot(xh, xt)) / (np.linalg.norm(xh) * np.linalg.norm(xt)))
+    return {"workload": "1D n=64, m=256, L=2: 50 power iterations + 200 GD (one workgroup, LDS-resident)",
+            "solve_us": ms * 1e3, "gd_plus_pi_iters_per_s": 250 / (ms * 1e-3), "cosine_similarity": cos}
 
 
 def main():
@@ -91,6 +370,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--quick", action="store_true", help="headline only (no side workloads, no CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -102,111 +382,45 @@ def main():
     import sr_inputs
 
     dev = torch.device("cuda:0")
-    d = sr_inputs.image_2d(1)
-    n_shape, m_shape, L = d["n_shape"], d["m_shape"], d["layers"]
-    n, m = int(np.prod(n_shape)), int(np.prod(m_shape))
-    plan = srpr.Plan([srpr.Problem(n_shape, m_shape, L)], d["theta"])
-    stream = plan.stream
-
-    # measurements: noiseless intensities from the library's own forward
-    # operator, then Poisson photon noise drawn on the host
-    xs = torch.from_numpy(d["x_star"].ravel()).to(dev)
-    yclean = torch.empty(m, dtype=torch.float32, device=dev)
-    srpr.sr_forward(plan, xs, None, yclean)
-    torch.cuda.synchronize()
-    y_h = sr_inputs.poisson_counts(d["noise_rng"], yclean.cpu().numpy(), d["photons"])
-    y = torch.from_numpy(y_h).to(dev)
-    v0 = torch.from_numpy(d["v0"].ravel()).to(dev)
-    x0 = torch.empty(n, dtype=torch.complex64, device=dev)
-    eta = float(d["mu"] * m / float(y_h.astype(np.float64).mean()))  # mu / (c * mean(y)), c = 1/m
-
-    # spectral initialisation (timed separately)
-    srpr.sr_spectral_init(plan, y, v0, PI_ITERS, d["lam"], x0)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    srpr.sr_spectral_init(plan, y, v0, PI_ITERS, d["lam"], x0)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    pi_ms = e0.elapsed_time(e1)
-
-    x = torch.empty_like(x0)
-    for _ in range(args.warmup):
-        x.copy_(x0)
-        srpr.sr_gd_solve(plan, y, x, GD_ITERS, eta)
-    torch.cuda.synchronize()
-
-    # timed region: K GD solves of 500 iterations each (x reset between solves
-    # by a 2 MB device copy, included)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        x.copy_(x0)
-        ev[i][0].record(stream)
-        srpr.sr_gd_solve(plan, y, x, GD_ITERS, eta)
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    solve_ms = [a.elapsed_time(b) for a, b in ev]
-    ms_per_step = wall * 1e3 / args.steps
-    gd_rate = GD_ITERS * args.steps / wall
-
-    # single-operator timing
-    z = torch.empty(m, dtype=torch.complex64, device=dev)
-    r = torch.randn(m, dtype=torch.complex64, device=dev)
-    xa = torch.empty(n, dtype=torch.complex64, device=dev)
-    reps = 200
-    for _ in range(10):
-        srpr.sr_forward(plan, xs, z, None)
-    a0, a1, a2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-    a0.record(stream)
-    for _ in range(reps):
-        srpr.sr_forward(plan, xs, z, None)
-    a1.record(stream)
-    for _ in range(reps):
-        srpr.sr_adjoint(plan, r, xa)
-    a2.record(stream)
-    torch.cuda.synchronize()
-    fwd_us = a0.elapsed_time(a1) * 1e3 / reps
-    adj_us = a1.elapsed_time(a2) * 1e3 / reps
-    op_bytes = schedule_bytes_op(n_shape, m_shape, L)
-
-    # quality check of the solve just timed
-    xh = x.cpu().numpy().astype(np.complex128)
-    xt = d["x_star"].ravel().astype(np.complex128)
-    cos = float(abs(np.vdot(xh, xt)) / (np.linalg.norm(xh) * np.linalg.norm(xt)))
-
-    gd_bytes = schedule_bytes_gd(n_shape, m_shape, L)
-    solve_avg_ms = float(np.mean(solve_ms))
-    achieved = gd_bytes * GD_ITERS / (solve_avg_ms * 1e-3) / 1e9
+    h = headline(torch, srpr, sr_inputs, dev, args.steps, args.warmup)
+    cpu_args = h.pop("_cpu")
     out = {
         "metric": "GD iters/s (n=256^2, alpha=4, L=2)",
-        "value": gd_rate,
+        "value": h["value"],
         "unit": "GD iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": h["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "c64",
         "data": "synthetic",
         "config": {"workload": "2D image 256x256 -> 512x512 (alpha=4), L=2, Poisson 1000 photons, "
-                               "GD solve of 500 iterations per step", "n": n, "m": m, "layers": L,
+                               "one GD solve of 500 iterations per step", "n": 65536, "m": 262144, "layers": 2,
                    "gd_iters_per_step": GD_ITERS},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "GD iteration (fused passes)", "bytes_per_unit": gd_bytes},
-        "operator": {"A_us": fwd_us, "AH_us": adj_us, "A_GBps": op_bytes / (fwd_us * 1e-6) / 1e9,
-                     "AH_GBps": op_bytes / (adj_us * 1e-6) / 1e9, "bytes_per_application": op_bytes},
-        "spectral_init": {"iters": PI_ITERS, "ms": pi_ms, "iters_per_s": PI_ITERS / (pi_ms * 1e-3)},
-        "cosine_similarity": cos,
+        "roofline": h["roofline"],
+        "operator": h["operator"],
+        "spectral_init": h["spectral_init"],
+        "gd_iteration_us": h["gd_iteration_us"],
+        "cosine_similarity": h["cosine_similarity"],
     }
-    if not args.no_cpu_baseline:
-        xr = x0.cpu().numpy().reshape(n_shape)
-        out["cpu_baseline"] = cpu_baseline(d, y_h.reshape(m_shape), xr, eta)
+    if not args.quick:
+        extras = {}
+        for name, fn in (("large_2d", large_2d), ("dense_baseline", dense), ("batched", batched),
+                         ("autograd", autograd), ("tiny_1d", tiny_1d)):
+            t0 = time.perf_counter()
+            try:
+                extras[name] = fn(torch, srpr, sr_inputs, dev)
+            except Exception as e:  # report, do not hide: the headline stays valid
+                extras[name] = {"error": f"{type(e).__name__}: {e}"}
+            extras[name]["wall_s"] = round(time.perf_counter() - t0, 2)
+            torch.cuda.empty_cache()
+        out["extras"] = extras
+    if not args.quick and not args.no_cpu_baseline:
+        d, y_h, x0_h, eta = cpu_args
+        out["cpu_baseline"] = cpu_baseline(d, y_h, x0_h, eta)
     print(json.dumps(out))
 
 
