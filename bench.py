@@ -87,12 +87,16 @@ def source_hash() -> str:
 def stored_traffic():
     """Measured HBM bytes per GD iteration from the committed counter summary,
     if it was taken on the current kernels (else None)."""
-    path = os.path.join(HERE, "profiles", "gd_image_512_traffic.json")
+    path = os.path.join(HERE, "profiles", "gd_image_512_traffic.txt")
     try:
+        d = {}
         with open(path) as f:
-            d = json.load(f)
+            for line in f:
+                parts = line.split()
+                if len(parts) == 2 and not line.startswith("#"):
+                    d[parts[0]] = parts[1]
         if d.get("source_hash") == source_hash():
-            return d.get("bytes_per_gd_iteration")
+            return float(d["bytes_per_gd_iteration"])
     except Exception:
         pass
     return None
@@ -372,6 +376,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="headline only (no side workloads, no CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="first run one 256 MiB device copy (reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU build: the benchmark runs on one GPU only; use --gpus 1"}))
@@ -382,6 +388,13 @@ def main():
     import sr_inputs
 
     dev = torch.device("cuda:0")
+    if args.calibration_copy:
+        # one elementwise kernel that reads 256 MiB and writes 256 MiB
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     h = headline(torch, srpr, sr_inputs, dev, args.steps, args.warmup)
     cpu_args = h.pop("_cpu")
     out = {

@@ -80,9 +80,12 @@ __device__ __forceinline__ void run_kind(const PassArgs& a, int kind, int tile, 
   }
 }
 
+constexpr size_t kBatchLds = 2 * sizeof(float2) * kBatchThreads * 12;  // covers 2 * B * NP elements for E <= 12
+
 template <int N>
 __device__ __forceinline__ void run_len(const BatchDesc& d, int tile, float2* lds, float* red) {
   static_assert(Tile<N, batch_b<N>(), true>::THREADS == kBatchThreads, "batched tiles are 256 threads");
+  static_assert(2 * sizeof(float2) * Tile<N, batch_b<N>(), true>::BUF <= kBatchLds, "batched LDS budget");
   if (d.col) run_kind<N, true>(d.a, d.kind, tile, lds, red);
   else run_kind<N, false>(d.a, d.kind, tile, lds, red);
 }
@@ -91,7 +94,7 @@ __global__ void __launch_bounds__(kBatchThreads) batched_level_kernel(const Batc
                                                                       const BatchDesc* __restrict__ descs) {
   extern __shared__ float2 lds[];
   __shared__ float red[kBatchThreads];
-  const BatchItem it = items[blockIdx.x];
+  const BatchItem it = items[xcd_tile(blockIdx.x, gridDim.x)];
   const BatchDesc& d = descs[it.desc];
   switch (d.N) {
     case 16: run_len<16>(d, it.tile, lds, red); break;
@@ -106,8 +109,6 @@ __global__ void __launch_bounds__(kBatchThreads) batched_level_kernel(const Batc
     default: break;
   }
 }
-
-constexpr size_t kBatchLds = 2 * sizeof(float2) * kBatchThreads * 12;  // 2 * B * N elements, E <= 12
 
 int batch_tile_width(int N) {
   switch (N) {

@@ -35,13 +35,17 @@ int tile_options(int N, bool col, int* out, int max_out) {
 // Default tile: the widest column tile (longest contiguous segments) and the
 // four-wave row tile.
 int default_tile(int N, bool col) {
-  int opts[8];
-  const int n = tile_options(N, col, opts, 8);
-  return n > 0 ? opts[n - 1] : 1;
+  int opts[16];
+  const int n = tile_options(N, col, opts, 16);
+  int best = 1;
+  for (int i = 0; i < n; ++i)
+    if (opts[i] < 256 && opts[i] > best) best = opts[i];  // widest double-buffered tile
+  return n > 0 ? best : 1;
 }
 
 int pass_groups(int N, bool col, int B, int ntr) {
   if (B <= 0) B = default_tile(N, col);
+  B &= 255;
   return (ntr + B - 1) / B;
 }
 

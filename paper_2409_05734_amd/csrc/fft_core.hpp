@@ -63,6 +63,17 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
   return r;
 }
 
+// Workgroup index -> tile index such that consecutive tiles run on the same
+// XCD.  Workgroups are dispatched to the 8 XCDs round-robin (bid mod 8), each
+// with its own L2; tiles that share cache lines (adjacent column tiles) then
+// hit the same L2 instead of each XCD fetching the full line.  Bijective on
+// [0, G) for any G.
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_tile(int bid, int G) {
+  const int q = G / kNumXcd, r = G % kNumXcd, x = bid % kNumXcd, l = bid / kNumXcd;
+  return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
 // --------------------------------------------------------------- butterflies
 // In-place R-point DFT, y_k = sum_j u_j w^(jk), w = exp(-2 pi i/R) (forward)
 // or exp(+2 pi i/R) (INV).  No scaling.
@@ -171,19 +182,26 @@ template <> struct FftShape<768>  { static constexpr int E = 12; using R = Radix
 // A tile of B transforms of length N.  COL selects the thread mapping used for
 // column-mode tiles: lane = t*B + b (consecutive lanes walk the batch, which is
 // the contiguous direction in memory) with LDS layout [k][b]; otherwise
-// lane = b*TPT + t with LDS layout [b][k + pad].
-template <int N, int B, bool COL, int E_ = FftShape<N>::E, class RL = typename FftShape<N>::R>
+// lane = b*TPT + t with LDS layout [b][k + pad].  DB: ping-pong LDS buffers
+// (one barrier per stage) or a single buffer (half the LDS, two barriers per
+// stage) -- the single buffer lets two large column tiles share a CU.
+template <int N, int B, bool COL, bool DB = true, int E_ = FftShape<N>::E, class RL = typename FftShape<N>::R>
 struct Tile {
   static constexpr int E = E_;
   static constexpr int TPT = N / E;
   static constexpr int THREADS = TPT * B;
-  static constexpr int PAD = COL ? 0 : 0;
-  static constexpr int LD = N + PAD;          // row-mode LDS stride
-  static constexpr int BUF = B * LD;          // complex elements per LDS buffer
+  // One pad slot every 8 elements for radix-8-first lengths: the stage-0
+  // scatter (stride 8) would otherwise put 8 lanes on one LDS bank pair.
+  static constexpr int PADSHIFT = RL::values[0] == 8 ? 3 : 0;
+  static constexpr int NP = PADSHIFT ? N + (N >> PADSHIFT) : N;  // padded transform length
+  static constexpr int LD = NP;               // row-mode LDS stride
+  static constexpr int BUF = B * NP;          // complex elements per LDS buffer
+  static constexpr int NBUF = DB ? 2 : 1;     // LDS buffers (elements: NBUF * BUF)
   static_assert(N % E == 0, "E must divide N");
   static_assert(RL::product() == N, "radix list must multiply to N");
 
-  __device__ __forceinline__ static int lidx(int b, int k) { return COL ? (k * B + b) : (b * LD + k); }
+  __device__ __forceinline__ static int padk(int k) { return PADSHIFT ? k + (k >> PADSHIFT) : k; }
+  __device__ __forceinline__ static int lidx(int b, int k) { return COL ? (padk(k) * B + b) : (b * LD + padk(k)); }
   __device__ __forceinline__ static int thread_t() { return COL ? (int)(threadIdx.x / B) : (int)(threadIdx.x % TPT); }
   __device__ __forceinline__ static int thread_b() { return COL ? (int)(threadIdx.x % B) : (int)(threadIdx.x / TPT); }
   __device__ __forceinline__ static int elem(int t, int j) { return t + j * TPT; }
@@ -243,7 +261,7 @@ struct Tile {
       if constexpr (S > 0) {
         // inputs of this stage: canonical positions in the buffer written last
         __syncthreads();
-        float2* src = lds + (phase ^ 1) * BUF;
+        float2* src = DB ? lds + (phase ^ 1) * BUF : lds;
 #pragma unroll
         for (int j = 0; j < E; ++j) v[j] = src[lidx(b, elem(t, j))];
       }
@@ -263,7 +281,12 @@ struct Tile {
         }
         Dft<R, INV>::run(u);
         if constexpr (S + 1 < RL::count) {
-          float2* dst = lds + phase * BUF;
+          if constexpr (!DB) {
+            // single buffer: every thread must be done reading it (this stage's
+            // loads, or an earlier transform's) before anyone overwrites it
+            if (q == 0) __syncthreads();
+          }
+          float2* dst = DB ? lds + phase * BUF : lds;
           const int base = (i / P) * P * R + k;
 #pragma unroll
           for (int r = 0; r < R; ++r) dst[lidx(b, base + r * P)] = u[r];

@@ -40,16 +40,22 @@ template <int N>
 struct TileCfg {
   static constexpr int E = FftShape<N>::E;
   static constexpr int TPT = N / E;
-  static constexpr int lds_bytes(int b) { return 2 * b * N * 8; }
-  static constexpr bool col_ok(int b) {
-    return b * TPT <= 1024 && (lds_bytes(b) <= 65536 || (b == 4 && lds_bytes(b) <= 131072));
-  }
+  static constexpr int NP = Tile<N, 1, true>::NP;  // padded length in LDS
+  static constexpr int lds_bytes(int b) { return 2 * b * NP * 8; }  // double-buffered tile
+  static constexpr int kMaxLds = 152 * 1024;  // dynamic LDS per workgroup (160 KB minus static)
+  static constexpr bool col_ok(int b) { return b * TPT <= 1024 && lds_bytes(b) <= kMaxLds; }
   static constexpr bool row_ok(int b) { return b >= 1 && b * TPT <= 1024 && lds_bytes(b) <= 65536; }
+  // single-buffered column tiles: offered where the double-buffered tile of
+  // the same width would not let two workgroups share a CU
+  static constexpr bool col_sb_ok(int b) {
+    return b * TPT <= 1024 && lds_bytes(b) > kMaxLds / 2 && lds_bytes(b) / 2 <= kMaxLds;
+  }
   static constexpr int ROW_SMALL = TPT >= 64 ? 1 : 64 / TPT;   // one wave
   static constexpr int ROW_BIG = TPT >= 256 ? 1 : 256 / TPT;   // four waves
 };
 
-// Tile widths available for a length and mode (ascending), and the default.
+// Tile widths available for a length and mode, and the default.  Column
+// widths with bit 256 set are single-buffered variants.
 int tile_options(int N, bool col, int* out, int max_out);
 int default_tile(int N, bool col);
 

@@ -106,10 +106,10 @@ __device__ __forceinline__ float inv_norm_from_partials(const float* part, int n
 // Every global load the tile needs (input, phases, measurements, twiddles,
 // the previous iterate) is issued up front, so a pass costs one memory
 // round trip plus its arithmetic, not one round trip per stage.
-template <int N, int B, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST>
+template <int N, int B, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST, bool DB = true>
 __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* lds, float* red, const float* part_in,
                                           int npart, float* part_out) {
-  using T = Tile<N, B, COL>;
+  using T = Tile<N, B, COL, DB>;
   constexpr int E = T::E;
   constexpr bool MID_PH = (MID == MID_PHASE || MID == MID_PHASE_CONJ || MID >= MID_PHASE_SAVE);
   constexpr bool MID_SAVED = (MID == MID_PHASE_CONJ_GT || MID == MID_PHASE_GT);
@@ -313,11 +313,12 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   }
 }
 
-template <int N, int B, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST>
-__global__ void __launch_bounds__((Tile<N, B, COL>::THREADS)) pass_kernel(const PassArgs a) {
+template <int N, int B, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST, bool DB = true>
+__global__ void __launch_bounds__((Tile<N, B, COL, DB>::THREADS)) pass_kernel(const PassArgs a) {
   extern __shared__ float2 lds[];
-  __shared__ float red[Tile<N, B, COL>::THREADS];
-  pass_tile<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST>(a, blockIdx.x, lds, red, a.part_in, a.npart, a.part_out);
+  __shared__ float red[Tile<N, B, COL, DB>::THREADS];
+  pass_tile<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, DB>(a, xcd_tile(blockIdx.x, gridDim.x), lds, red, a.part_in,
+                                                              a.npart, a.part_out);
 }
 
 }  // namespace sr

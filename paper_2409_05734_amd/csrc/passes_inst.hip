@@ -15,11 +15,16 @@ namespace sr {
 
 namespace {
 
-template <int N, int B, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST>
+// Tile widths are encoded as B | kSingleBuffer for single-buffered tiles.
+constexpr int kSingleBuffer = 256;
+
+template <int N, int BE, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST>
 hipError_t go(const PassArgs& a, hipStream_t s) {
-  using T = Tile<N, B, COL>;
-  auto kern = pass_kernel<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST>;
-  const size_t lds = 2 * sizeof(float2) * (size_t)T::BUF;
+  constexpr int B = BE & (kSingleBuffer - 1);
+  constexpr bool DB = (BE & kSingleBuffer) == 0;
+  using T = Tile<N, B, COL, DB>;
+  auto kern = pass_kernel<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, DB>;
+  const size_t lds = T::NBUF * sizeof(float2) * (size_t)T::BUF;
   if (lds > 65536) {
     static bool raised = false;  // once per instantiation
     if (!raised) {
@@ -34,7 +39,7 @@ hipError_t go(const PassArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int N, bool COL, int B>
+template <int N, bool COL, int B>  // B: encoded tile width
 hipError_t dispatch(int kind, const PassArgs& a, hipStream_t s) {
 #if SR_PASS_SET == 0
   if constexpr (COL) {
@@ -94,27 +99,30 @@ hipError_t dispatch(int kind, const PassArgs& a, hipStream_t s) {
 using Cfg = TileCfg<SR_FFT_N>;
 constexpr int kColOpts[4] = {2, 4, 8, 16};
 
-hipError_t by_tile(int kind, bool col, int B, const PassArgs& a, hipStream_t s) {
+template <int B>
+hipError_t col_tile(int kind, bool single, const PassArgs& a, hipStream_t s) {
+  constexpr int N = SR_FFT_N;
+  if (single) {
+    if constexpr (Cfg::col_sb_ok(B)) return dispatch<N, true, B | kSingleBuffer>(kind, a, s);
+  } else {
+    if constexpr (Cfg::col_ok(B)) return dispatch<N, true, B>(kind, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t by_tile(int kind, bool col, int Benc, const PassArgs& a, hipStream_t s) {
   constexpr int N = SR_FFT_N;
   if (col) {
-    switch (B) {
-      case 2:
-        if constexpr (Cfg::col_ok(2)) return dispatch<N, true, 2>(kind, a, s);
-        break;
-      case 4:
-        if constexpr (Cfg::col_ok(4)) return dispatch<N, true, 4>(kind, a, s);
-        break;
-      case 8:
-        if constexpr (Cfg::col_ok(8)) return dispatch<N, true, 8>(kind, a, s);
-        break;
-      case 16:
-        if constexpr (Cfg::col_ok(16)) return dispatch<N, true, 16>(kind, a, s);
-        break;
-      default:
-        break;
+    const bool single = (Benc & kSingleBuffer) != 0;
+    switch (Benc & (kSingleBuffer - 1)) {
+      case 2: return col_tile<2>(kind, single, a, s);
+      case 4: return col_tile<4>(kind, single, a, s);
+      case 8: return col_tile<8>(kind, single, a, s);
+      case 16: return col_tile<16>(kind, single, a, s);
+      default: return hipErrorInvalidValue;
     }
-    return hipErrorInvalidValue;
   }
+  const int B = Benc;
   if (B == Cfg::ROW_SMALL) return dispatch<N, false, Cfg::ROW_SMALL>(kind, a, s);
   if constexpr (Cfg::ROW_BIG != Cfg::ROW_SMALL) {
     if (B == Cfg::ROW_BIG) return dispatch<N, false, Cfg::ROW_BIG>(kind, a, s);
@@ -131,6 +139,8 @@ int tile_options_n<SR_FFT_N>(bool col, int* out, int max_out) {
   if (col) {
     for (int b : kColOpts)
       if (Cfg::col_ok(b) && n < max_out) out[n++] = b;
+    for (int b : kColOpts)
+      if (Cfg::col_sb_ok(b) && n < max_out) out[n++] = b | kSingleBuffer;
   } else {
     if (n < max_out) out[n++] = Cfg::ROW_SMALL;
     if (Cfg::ROW_BIG != Cfg::ROW_SMALL && n < max_out) out[n++] = Cfg::ROW_BIG;

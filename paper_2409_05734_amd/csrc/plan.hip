@@ -60,8 +60,9 @@ sr_status sr_plan_s::init(const float* theta_host) {
   size_t b_ysum = align256(sizeof(double) * (np + 8));
   size_t b_fs = align256(sizeof(float) * (8 * np + 64));
   size_t b_sync = 256;
+  size_t b_red = align256(sizeof(double) * 1024);
   int ngrid = (kind == SR_DENSE) ? 2 : 4;
-  ws_bytes = b_theta + b_eph + b_tw + ngrid * b_grid + b_part + b_ysum + b_fs + b_sync;
+  ws_bytes = b_theta + b_eph + b_tw + ngrid * b_grid + b_part + b_ysum + b_fs + b_sync + b_red;
   hipError_t e = hipMalloc(&ws, ws_bytes);
   if (e != hipSuccess) {
     ws = nullptr;
@@ -91,6 +92,8 @@ sr_status sr_plan_s::init(const float* theta_host) {
   fscratch = (float*)c;
   c += b_fs;
   sync = (unsigned*)c;
+  c += b_sync;
+  red_ws = (double*)c;
 
   size_t o = 0;
   for (int N : lens) {

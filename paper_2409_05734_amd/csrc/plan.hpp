@@ -60,6 +60,7 @@ struct sr_plan_s {
   double* ysum = nullptr;  // sum(y) scratch (per problem)
   float* fscratch = nullptr;  // float scratch (dense solver scalars)
   unsigned* sync = nullptr;   // [0] grid-barrier counter, [1] barrier error flag
+  double* red_ws = nullptr;   // per-workgroup partials of the two-stage reductions (kRedGroups)
   float2* vjp_buf = nullptr;  // per-layer intermediates for derivatives (allocated on first use)
   sr::BatchState* batch = nullptr;  // batched-schedule state (built on first batched solve)
   size_t vjp_elems = 0;

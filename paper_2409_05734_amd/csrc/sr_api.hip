@@ -308,7 +308,31 @@ static void tune_cache_store(const char* path, const std::string& key, int cb, i
   std::fclose(f);
 }
 
+// SR_TUNE_FORCE="c,r,t" pins the column tile, row tile and phase-table
+// choice for every shape (options a length does not offer fall back to its
+// default); used to exercise every compiled variant.
+static bool tile_offered(int N, bool col, int b) {
+  int o[16];
+  const int n = tile_options(N, col, o, 16);
+  for (int i = 0; i < n; ++i)
+    if (o[i] == b) return true;
+  return false;
+}
+
 static sr_status tune_plan(sr_plan_s* p) {
+  const char* force = std::getenv("SR_TUNE_FORCE");
+  if (force != nullptr) {
+    int c = 0, r = 0, t = 0;
+    if (std::sscanf(force, "%d,%d,%d", &c, &r, &t) == 3) {
+      for (const Geo& g : p->geo) {
+        if (g.ndim != 2) continue;
+        p->tiles[{g.M1, 1}] = tile_offered(g.M1, true, c) ? c : default_tile(g.M1, true);
+        p->tiles[{g.M2, 0}] = tile_offered(g.M2, false, r) ? r : default_tile(g.M2, false);
+      }
+      p->use_table = t != 0;
+      return SR_OK;
+    }
+  }
   const char* env = std::getenv("SR_TUNE");
   if (env != nullptr && std::atoi(env) == 0) return SR_OK;
   const char* cache = std::getenv("SR_TUNE_CACHE");
@@ -321,9 +345,9 @@ static sr_status tune_plan(sr_plan_s* p) {
     if (p->tiles.count({g.M1, 1}) && p->tiles.count({g.M2, 0})) continue;  // decided by an earlier shape
     int cb = 0, rb = 0, tb = 0;
     if (!tune_cache_lookup(cache, key, &cb, &rb, &tb)) {
-      int copt[8], ropt[8];
-      const int nc = tile_options(g.M1, true, copt, 8);
-      const int nr = tile_options(g.M2, false, ropt, 8);
+      int copt[16], ropt[16];
+      const int nc = tile_options(g.M1, true, copt, 16);
+      const int nr = tile_options(g.M2, false, ropt, 16);
       float best = 1e30f;
       hipEvent_t e0, e1;
       SR_HIP(hipEventCreate(&e0));

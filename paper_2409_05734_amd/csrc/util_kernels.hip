@@ -10,8 +10,6 @@ namespace sr {
 
 namespace {
 
-constexpr int kRedThreads = 1024;
-
 template <int NT>
 __device__ double block_sum_d(double v, double* red) {
   red[threadIdx.x] = v;
@@ -35,25 +33,51 @@ __global__ void reduce_partials_kernel(const float* __restrict__ part, int n, fl
   }
 }
 
-// out = sum(y) with one workgroup (fixed strided order + fixed tree)
-__global__ void __launch_bounds__(kRedThreads) sum_floats_kernel(const float* __restrict__ y, long long n,
-                                                                 double* out) {
-  __shared__ double red[kRedThreads];
+// Two-stage deterministic reductions: stage 1 gives workgroup g the
+// contiguous chunk [g*chunk, (g+1)*chunk) (fixed strided order + fixed tree),
+// stage 2 sums the per-workgroup partials in index order.
+constexpr int kRedGroups = 1024;
+constexpr int kRedStage1 = 256;
+
+__global__ void __launch_bounds__(kRedStage1) sum_floats_stage1(const float* __restrict__ y, long long n,
+                                                                long long chunk, double* part) {
+  __shared__ double red[kRedStage1];
+  const long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
   double acc = 0.0;
-  for (long long i = threadIdx.x; i < n; i += kRedThreads) acc += (double)y[i];
-  const double s = block_sum_d<kRedThreads>(acc, red);
-  if (threadIdx.x == 0) *out = s;
+  for (long long i = lo + threadIdx.x; i < hi; i += kRedStage1) acc += (double)y[i];
+  const double s = block_sum_d<kRedStage1>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-__global__ void __launch_bounds__(kRedThreads) norm2_kernel(const float2* __restrict__ x, long long n, float* out) {
-  __shared__ double red[kRedThreads];
+__global__ void __launch_bounds__(kRedStage1) norm2_stage1(const float2* __restrict__ x, long long n, long long chunk,
+                                                           double* part) {
+  __shared__ double red[kRedStage1];
+  const long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
   double acc = 0.0;
-  for (long long i = threadIdx.x; i < n; i += kRedThreads) {
+  for (long long i = lo + threadIdx.x; i < hi; i += kRedStage1) {
     const float2 v = x[i];
     acc += (double)v.x * v.x + (double)v.y * v.y;
   }
-  const double s = block_sum_d<kRedThreads>(acc, red);
-  if (threadIdx.x == 0) *out = (float)s;
+  const double s = block_sum_d<kRedStage1>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// stage 2: out = sum of part[0..g) in index order; as double or as float
+__global__ void reduce_stage2(const double* __restrict__ part, int g, double* out_d, float* out_f) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double acc = 0.0;
+    for (int i = 0; i < g; ++i) acc += part[i];
+    if (out_d) *out_d = acc;
+    if (out_f) *out_f = (float)acc;
+  }
+}
+
+void red_shape(long long n, int* groups, long long* chunk) {
+  long long g = (n + 4095) / 4096;
+  if (g > kRedGroups) g = kRedGroups;
+  if (g < 1) g = 1;
+  *groups = (int)g;
+  *chunk = (n + g - 1) / g;
 }
 
 // x *= sqrt(sum(y) * inv_mc) / ||x||, ||x||^2 = sum of the partials
@@ -90,13 +114,21 @@ sr_status reduce_partials(sr_plan_s* p, const float* part, int n, float* out) {
 }
 
 sr_status sum_floats(sr_plan_s* p, const float* y, int64_t n, double* out) {
-  hipLaunchKernelGGL(sum_floats_kernel, dim3(1), dim3(kRedThreads), 0, p->stream, y, (long long)n, out);
+  int g;
+  long long chunk;
+  red_shape(n, &g, &chunk);
+  hipLaunchKernelGGL(sum_floats_stage1, dim3(g), dim3(kRedStage1), 0, p->stream, y, (long long)n, chunk, p->red_ws);
+  hipLaunchKernelGGL(reduce_stage2, dim3(1), dim3(64), 0, p->stream, p->red_ws, g, out, (float*)nullptr);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SR_OK : hip_fail(e, "sum_floats");
 }
 
 sr_status norm2_partial(sr_plan_s* p, const float2* x, int64_t n, float* out) {
-  hipLaunchKernelGGL(norm2_kernel, dim3(1), dim3(kRedThreads), 0, p->stream, x, (long long)n, out);
+  int g;
+  long long chunk;
+  red_shape(n, &g, &chunk);
+  hipLaunchKernelGGL(norm2_stage1, dim3(g), dim3(kRedStage1), 0, p->stream, x, (long long)n, chunk, p->red_ws);
+  hipLaunchKernelGGL(reduce_stage2, dim3(1), dim3(64), 0, p->stream, p->red_ws, g, (double*)nullptr, out);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SR_OK : hip_fail(e, "norm2");
 }

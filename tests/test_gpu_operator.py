@@ -148,3 +148,28 @@ def test_sampled_outputs_at_large_size(gpu):
     for k1 in (0, 1, 1023, 2047):
         row = F2[k1] @ W  # axis-0 transform, row k1 only
         assert rel_l2(z[k1], row) <= TOL_OP
+
+
+@pytest.mark.parametrize("n_shape,m_shape,L", [((256, 256), (512, 512), 2), ((600, 300), (2048, 512), 3),
+                                               ((300, 700), (768, 2048), 2), ((40, 50), (96, 128), 3)])
+@pytest.mark.parametrize("col_tile", [2, 4, 8, 16, 2 | 256, 4 | 256, 8 | 256, 16 | 256])
+def test_every_tile_variant(gpu, monkeypatch, n_shape, m_shape, L, col_tile):
+    """Every compiled column tile (double- and single-buffered LDS) and both
+    row tiles, with and without the exp(i theta) table, against the oracle."""
+    import torch
+    import paper_2409_05734_amd as srpr
+    rng = np.random.default_rng(col_tile + L)
+    th, x = random_problem(rng, n_shape, m_shape, L)
+    z_ref = oracle.forward(x, th)
+    r = z_ref.astype(np.complex64)
+    v_ref = oracle.adjoint(r, th, n_shape)
+    for row_tile, table in ((1, 0), (4, 1), (64, 1)):
+        monkeypatch.setenv("SR_TUNE_FORCE", f"{col_tile},{row_tile},{table}")
+        plan = make_plan([(n_shape, m_shape, L)], [th], gpu)
+        zd = torch.empty(int(np.prod(m_shape)), dtype=torch.complex64, device=gpu)
+        vd = torch.empty(int(np.prod(n_shape)), dtype=torch.complex64, device=gpu)
+        srpr.sr_forward(plan, to_dev(x.ravel(), gpu), zd, None)
+        srpr.sr_adjoint(plan, to_dev(r.ravel(), gpu), vd)
+        torch.cuda.synchronize()
+        assert rel_l2(to_host(zd).reshape(m_shape), z_ref) <= TOL_OP
+        assert rel_l2(to_host(vd).reshape(n_shape), v_ref) <= TOL_OP
