@@ -49,14 +49,14 @@ __device__ __forceinline__ void run_kind(const PassArgs& a, int kind, int tile, 
   if constexpr (COL) {
     switch (kind) {
       case PK_FIRST_FWD:
-        pass_tile<N, B, COL, PRE_PHASE, MID_NONE, false, false, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
+        pass_tile_rt<N, B, COL, PRE_PHASE, MID_NONE, false, false, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
                                                                                    nullptr);
         return;
       case PK_LAST_GD:
-        pass_tile<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_GD>(a, tile, lds, red, nullptr, 0, nullptr);
+        pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_GD>(a, tile, lds, red, nullptr, 0, nullptr);
         return;
       case PK_LAST_GD_FWD:
-        pass_tile<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_GD_FWD>(a, tile, lds, red, nullptr, 0,
+        pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_GD_FWD>(a, tile, lds, red, nullptr, 0,
                                                                                   nullptr);
         return;
       default:
@@ -65,14 +65,14 @@ __device__ __forceinline__ void run_kind(const PassArgs& a, int kind, int tile, 
   }
   switch (kind) {
     case PK_MID_FWD:
-      pass_tile<N, B, COL, PRE_NONE, MID_PHASE, true, false, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE, true, false, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
                                                                                 nullptr);
       return;
     case PK_TURN_GD:
-      pass_tile<N, B, COL, PRE_NONE, MID_GD, true, false, true, POST_STORE>(a, tile, lds, red, nullptr, 0, nullptr);
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_GD, true, false, true, POST_STORE>(a, tile, lds, red, nullptr, 0, nullptr);
       return;
     case PK_MID_ADJ:
-      pass_tile<N, B, COL, PRE_NONE, MID_PHASE_CONJ, true, true, true, POST_STORE>(a, tile, lds, red, nullptr, 0,
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE_CONJ, true, true, true, POST_STORE>(a, tile, lds, red, nullptr, 0,
                                                                                    nullptr);
       return;
     default:

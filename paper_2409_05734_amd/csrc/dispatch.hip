@@ -7,8 +7,9 @@ namespace sr {
 #define SR_FOR_EACH_2D_LEN(X) X(16) X(32) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(2048)
 
 hipError_t launch_pass(int N, int kind, bool col, int B, const PassArgs& a, hipStream_t s) {
-  if (B <= 0) B = default_tile(N, col);
   const bool rev = kind >= PK_MID_FWD_SAVE && kind <= PK_LAST_ADJ_GT;
+  // the reverse-mode passes are built for the default thread shape only
+  if (B <= 0 || (rev && (B & kNarrow))) B = default_tile(N, col);
   switch (N) {
 #define SR_CASE(n) \
   case n:          \
@@ -45,7 +46,7 @@ int default_tile(int N, bool col) {
 
 int pass_groups(int N, bool col, int B, int ntr) {
   if (B <= 0) B = default_tile(N, col);
-  B &= 255;
+  B &= kSingleBuffer - 1;
   return (ntr + B - 1) / B;
 }
 

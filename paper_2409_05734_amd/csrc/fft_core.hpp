@@ -74,6 +74,37 @@ __device__ __forceinline__ int xcd_tile(int bid, int G) {
   return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
 }
 
+// ------------------------------------------------------- buffer memory ops
+// Global loads and stores through buffer resources.  A lane whose element
+// lies outside its window passes an offset past the resource's range, so the
+// hardware returns zero (loads) or drops the write (stores) without a branch;
+// offsets are 32-bit byte offsets from a wave-uniform base (every buffer a
+// pass touches spans well under 2 GiB).
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr unsigned kOob = 0x80000000u;  // byte offset past every resource
+__device__ __forceinline__ Rsrc rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 0x7fffffff, 0x00020000);
+}
+__device__ __forceinline__ unsigned off8(bool ok, int e) { return ok ? (unsigned)e * 8u : kOob; }
+__device__ __forceinline__ unsigned off4(bool ok, int e) { return ok ? (unsigned)e * 4u : kOob; }
+__device__ __forceinline__ float2 ld2(Rsrc r, unsigned off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  return make_float2(__builtin_bit_cast(float, (unsigned)v[0]), __builtin_bit_cast(float, (unsigned)v[1]));
+}
+__device__ __forceinline__ float ld1(Rsrc r, unsigned off) {
+  return __builtin_bit_cast(float, (unsigned)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void st2(Rsrc r, unsigned off, float2 x) {
+  typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+  u32x2 v;
+  v[0] = __builtin_bit_cast(unsigned, x.x);
+  v[1] = __builtin_bit_cast(unsigned, x.y);
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+}
+__device__ __forceinline__ void st1(Rsrc r, unsigned off, float x) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, off, 0, 0);
+}
+
 // --------------------------------------------------------------- butterflies
 // In-place R-point DFT, y_k = sum_j u_j w^(jk), w = exp(-2 pi i/R) (forward)
 // or exp(+2 pi i/R) (INV).  No scaling.
@@ -178,6 +209,25 @@ template <> struct FftShape<192>  { static constexpr int E = 12; using R = Radix
 template <> struct FftShape<384>  { static constexpr int E = 12; using R = RadixList<3, 4, 4, 4, 2>; };
 template <> struct FftShape<768>  { static constexpr int E = 12; using R = RadixList<3, 4, 4, 4, 4>; };
 
+// Narrow variant of the power-of-two lengths: four elements per thread
+// (radix-4 stages, one radix-2 stage for odd powers), i.e. twice the threads
+// per transform.  It costs more LDS exchanges but halves each wave's serial
+// arithmetic, which pays when a pass has too few transforms to give every
+// SIMD of the chip a wave of the default shape.
+template <int N>
+struct FftNarrow;
+template <> struct FftNarrow<64>   { using R = RadixList<4, 4, 4>; };
+template <> struct FftNarrow<128>  { using R = RadixList<4, 4, 4, 2>; };
+template <> struct FftNarrow<256>  { using R = RadixList<4, 4, 4, 4>; };
+template <> struct FftNarrow<512>  { using R = RadixList<4, 4, 4, 4, 2>; };
+template <> struct FftNarrow<1024> { using R = RadixList<4, 4, 4, 4, 4>; };
+template <int N> struct HasNarrow { static constexpr bool value = false; };
+template <> struct HasNarrow<64> { static constexpr bool value = true; };
+template <> struct HasNarrow<128> { static constexpr bool value = true; };
+template <> struct HasNarrow<256> { static constexpr bool value = true; };
+template <> struct HasNarrow<512> { static constexpr bool value = true; };
+template <> struct HasNarrow<1024> { static constexpr bool value = true; };
+
 // ------------------------------------------------------------------- tile
 // A tile of B transforms of length N.  COL selects the thread mapping used for
 // column-mode tiles: lane = t*B + b (consecutive lanes walk the batch, which is
@@ -190,9 +240,10 @@ struct Tile {
   static constexpr int E = E_;
   static constexpr int TPT = N / E;
   static constexpr int THREADS = TPT * B;
-  // One pad slot every 8 elements for radix-8-first lengths: the stage-0
-  // scatter (stride 8) would otherwise put 8 lanes on one LDS bank pair.
-  static constexpr int PADSHIFT = RL::values[0] == 8 ? 3 : 0;
+  // One pad slot every R0 elements for radix-8- or radix-4-first lengths:
+  // the stage-0 scatter (stride R0) would otherwise put lanes on one LDS
+  // bank pair.
+  static constexpr int PADSHIFT = RL::values[0] == 8 ? 3 : (RL::values[0] == 4 && E_ == 4) ? 2 : 0;
   static constexpr int NP = PADSHIFT ? N + (N >> PADSHIFT) : N;  // padded transform length
   static constexpr int LD = NP;               // row-mode LDS stride
   static constexpr int BUF = B * NP;          // complex elements per LDS buffer
@@ -300,5 +351,17 @@ struct Tile {
     }
   }
 };
+
+// Tile of shape variant EV: 0 = the length's default shape, 1 = narrow.
+template <int N, int B, bool COL, bool DB, int EV>
+struct TileSel {
+  using type = Tile<N, B, COL, DB>;
+};
+template <int N, int B, bool COL, bool DB>
+struct TileSel<N, B, COL, DB, 1> {
+  using type = Tile<N, B, COL, DB, 4, typename FftNarrow<N>::R>;
+};
+template <int N, int B, bool COL, bool DB = true, int EV = 0>
+using TileV = typename TileSel<N, B, COL, DB, EV>::type;
 
 }  // namespace sr

@@ -32,15 +32,15 @@ enum PassKind : int {
 };
 
 // Tile widths: each length is compiled for a few tile widths (transforms per
-// workgroup) in each mode; the plan's tuner picks one per (length, mode).
+// workgroup) and, for power-of-two lengths 64..1024, two thread shapes in
+// each mode; the plan's tuner picks one per (length, mode).
 // Row mode: 1 wave or 4 waves per workgroup.  Column mode: 2, 4, 8 or 16
 // adjacent columns (16- to 128-byte row segments), within 1024 threads and
 // the LDS budget (double-buffered tiles).
-template <int N>
+template <int N, int EV = 0>
 struct TileCfg {
-  static constexpr int E = FftShape<N>::E;
-  static constexpr int TPT = N / E;
-  static constexpr int NP = Tile<N, 1, true>::NP;  // padded length in LDS
+  static constexpr int TPT = TileV<N, 1, true, true, EV>::TPT;
+  static constexpr int NP = TileV<N, 1, true, true, EV>::NP;  // padded length in LDS
   static constexpr int lds_bytes(int b) { return 2 * b * NP * 8; }  // double-buffered tile
   static constexpr int kMaxLds = 152 * 1024;  // dynamic LDS per workgroup (160 KB minus static)
   static constexpr bool col_ok(int b) { return b * TPT <= 1024 && lds_bytes(b) <= kMaxLds; }
@@ -55,9 +55,13 @@ struct TileCfg {
 };
 
 // Tile widths available for a length and mode, and the default.  Column
-// widths with bit 256 set are single-buffered variants.
+// widths with bit 256 set are single-buffered variants; widths with bit 512
+// set use the narrow shape (four elements per thread).
 int tile_options(int N, bool col, int* out, int max_out);
 int default_tile(int N, bool col);
+
+constexpr int kSingleBuffer = 256;
+constexpr int kNarrow = 512;
 
 // Number of workgroups a pass of this length/mode/tile launches.
 int pass_groups(int N, bool col, int B, int ntr);

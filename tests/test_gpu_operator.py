@@ -150,12 +150,19 @@ def test_sampled_outputs_at_large_size(gpu):
         assert rel_l2(z[k1], row) <= TOL_OP
 
 
+NARROW = 512  # tile-width flag of the four-elements-per-thread shape
+
+
 @pytest.mark.parametrize("n_shape,m_shape,L", [((256, 256), (512, 512), 2), ((600, 300), (2048, 512), 3),
-                                               ((300, 700), (768, 2048), 2), ((40, 50), (96, 128), 3)])
-@pytest.mark.parametrize("col_tile", [2, 4, 8, 16, 2 | 256, 4 | 256, 8 | 256, 16 | 256])
+                                               ((300, 700), (768, 2048), 2), ((40, 50), (96, 128), 3),
+                                               ((100, 30), (256, 64), 2), ((500, 200), (1024, 256), 3)])
+@pytest.mark.parametrize("col_tile", [2, 4, 8, 16, 2 | 256, 4 | 256, 8 | 256, 16 | 256,
+                                      2 | NARROW, 4 | NARROW, 8 | NARROW])
 def test_every_tile_variant(gpu, monkeypatch, n_shape, m_shape, L, col_tile):
-    """Every compiled column tile (double- and single-buffered LDS) and both
-    row tiles, with and without the exp(i theta) table, against the oracle."""
+    """Every compiled column tile (double- and single-buffered LDS, default and
+    narrow thread shape) and the row tiles of both shapes, with and without
+    the exp(i theta) table, against the oracle.  Widths a length does not
+    offer fall back to its default tile."""
     import torch
     import paper_2409_05734_amd as srpr
     rng = np.random.default_rng(col_tile + L)
@@ -163,7 +170,7 @@ def test_every_tile_variant(gpu, monkeypatch, n_shape, m_shape, L, col_tile):
     z_ref = oracle.forward(x, th)
     r = z_ref.astype(np.complex64)
     v_ref = oracle.adjoint(r, th, n_shape)
-    for row_tile, table in ((1, 0), (4, 1), (64, 1)):
+    for row_tile, table in ((1, 0), (4, 1), (64, 1), (1 | NARROW, 1), (2 | NARROW, 0), (4 | NARROW, 1)):
         monkeypatch.setenv("SR_TUNE_FORCE", f"{col_tile},{row_tile},{table}")
         plan = make_plan([(n_shape, m_shape, L)], [th], gpu)
         zd = torch.empty(int(np.prod(m_shape)), dtype=torch.complex64, device=gpu)

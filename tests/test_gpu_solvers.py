@@ -61,6 +61,48 @@ def test_gd_iterates(gpu, n_shape, m_shape, L):
         assert aligned(xg.reshape(n_shape), xr) <= TOL_IT, k
 
 
+@pytest.mark.parametrize("force", ["8,1,1", "2,4,0", "16,1,1", "2|n,1|n,1", "8|n,2|n,0", "4|n,1,1"])
+def test_gd_iterates_every_pass_shape(gpu, monkeypatch, force):
+    """The fused solver passes (turnaround with the residual, the update fused
+    with the next first pass) on pinned tile shapes, default and narrow,
+    against the oracle's GD iterates on a 512 x 512 grid and a 128 x 256 grid."""
+    c, r, t = (int(v.replace("|n", "")) | (512 if "|n" in v else 0) for v in force.split(","))
+    monkeypatch.setenv("SR_TUNE_FORCE", f"{c},{r},{t}")
+    for n_shape, m_shape, L in (((200, 180), (512, 512), 2), ((60, 100), (128, 256), 3)):
+        rng = np.random.default_rng(77 + L)
+        th, xs = random_problem(rng, n_shape, m_shape, L)
+        op = oracle.StructuredOperator(th, n_shape)
+        y = (np.abs(op.A(xs)) ** 2).astype(np.float32)
+        x0 = (xs + 0.5 * sr_inputs.complex_gaussian(rng, n_shape)).astype(np.complex64)
+        eta = np.float32(oracle.default_step(op, y, 0.2))
+        plan = make_plan([(n_shape, m_shape, L)], [th], gpu)
+        for k in (1, 20):
+            xg, _ = _run_gd(plan, y, x0, k, eta, gpu)
+            xr = oracle.gd_solve(op, y, x0, k, float(eta))
+            assert aligned(xg.reshape(n_shape), xr) <= TOL_IT, (n_shape, k)
+
+
+@pytest.mark.parametrize("n_shape,m_shape,L", [((64, 64), (128, 64), 1), ((128, 128), (256, 128), 1),
+                                               ((64,), (128,), 1)])
+def test_gd_steps_along_unstable_trajectory(gpu, n_shape, m_shape, L):
+    """alpha = 2, L = 1 from a random start: GD amplifies rounding along the
+    trajectory, so whole trajectories of any two FP32 implementations drift
+    apart.  The arithmetic is checked step by step instead: from each oracle
+    iterate x_k (k = 0..50), one GPU step must reproduce the oracle's x_{k+1}."""
+    rng = np.random.default_rng(91 + len(n_shape))
+    th, xs = random_problem(rng, n_shape, m_shape, L)
+    op = oracle.StructuredOperator(th, n_shape)
+    y = (np.abs(op.A(xs)) ** 2).astype(np.float32)
+    x = sr_inputs.scaled_start(rng, n_shape, float(np.sum(y))).astype(np.complex128)
+    eta = np.float32(oracle.default_step(op, y, 0.2))
+    plan = make_plan([(n_shape, m_shape, L)], [th], gpu)
+    for k in range(51):
+        xr = oracle.gd_solve(op, y, x, 1, float(eta))
+        xg, _ = _run_gd(plan, y, x.astype(np.complex64), 1, eta, gpu)
+        assert rel_l2(xg.reshape(n_shape), xr) <= 2e-5, k
+        x = xr
+
+
 def test_gd_loss_trace(gpu):
     rng = np.random.default_rng(21)
     for n_shape, m_shape, L in [((64,), (256,), 2), ((24, 24), (64, 64), 2)]:
