@@ -47,20 +47,33 @@ __device__ __forceinline__ float2 phase(float theta, float s) {
   return make_float2(cs * s, CONJ ? -sn * s : sn * s);
 }
 
-// Deterministic workgroup sum (fixed tree order); every thread gets the
-// result.  NTHREADS must be a power of two and equal blockDim.x.
+// Deterministic workgroup sum: a fixed shuffle tree inside each wave, lane
+// 0's total broadcast to the wave, then the wave totals added in wave order.
+// Every thread gets the same value.  NTHREADS must be a power of two and
+// equal blockDim.x; `red` holds at least NTHREADS / 64 values.
+template <int NTHREADS, class V>
+__device__ __forceinline__ V block_sum_t(V v, V* red) {
+  constexpr int W = NTHREADS < 64 ? NTHREADS : 64;
+  constexpr int NW = NTHREADS / W;
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_down(v, o, W);
+  v = __shfl(v, 0, W);
+  if constexpr (NW == 1) {
+    return v;
+  } else {
+    __syncthreads();  // `red` may still be read by an earlier call
+    if ((threadIdx.x & (W - 1)) == 0) red[threadIdx.x / W] = v;
+    __syncthreads();
+    V s = red[0];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) s += red[i];
+    return s;
+  }
+}
+
 template <int NTHREADS>
 __device__ __forceinline__ float block_sum(float v, float* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-#pragma unroll
-  for (int s = NTHREADS / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  const float r = red[0];
-  __syncthreads();
-  return r;
+  return block_sum_t<NTHREADS, float>(v, red);
 }
 
 // Workgroup index -> tile index such that consecutive tiles run on the same

@@ -91,11 +91,15 @@ struct PassArgs {
   long long out2_ld;
 };
 
-// Sum of previous-iterate partials, identical on every thread (fixed order).
+// 1/sqrt of the sum of the previous iterate's squared-norm partials: strided
+// per-thread sums, then a fixed-order workgroup reduction in float64, so
+// every thread (and every workgroup of the pass) gets the same value.
+template <int NTHREADS>
 __device__ __forceinline__ float inv_norm_from_partials(const float* part, int n) {
+  __shared__ double redd[NTHREADS / 64 > 0 ? NTHREADS / 64 : 1];
   double acc = 0.0;
-  for (int i = 0; i < n; ++i) acc += (double)part[i];
-  return (float)(1.0 / sqrt(acc));
+  for (int i = (int)threadIdx.x; i < n; i += NTHREADS) acc += (double)part[i];
+  return (float)(1.0 / sqrt(block_sum_t<NTHREADS, double>(acc, redd)));
 }
 
 // One tile (B transforms) of a fused pass.  `lds` holds 2*B*N complex
@@ -202,7 +206,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   float s_pre = a.scale_pre;
   float s_prev = 1.f;  // 1/||u_prev|| for the spectral update
   if (part_in != nullptr) {
-    s_prev = inv_norm_from_partials(part_in, npart);
+    s_prev = inv_norm_from_partials<T::THREADS>(part_in, npart);
     if (PRE == PRE_PHASE) s_pre *= s_prev;
   }
 
