@@ -74,11 +74,17 @@ def schedule_bytes_op(n_shape, m_shape, L):
     return b
 
 
+# the sources the 2D pass kernels and their schedule are compiled from
+PASS_SOURCES = ("fft_core.hpp", "passes.hpp", "launch.hpp", "passes_inst.hip", "dispatch.hip", "schedule.hpp",
+                "sr_api.hip", "plan.hpp", "plan.hip")
+
+
 def source_hash() -> str:
-    """Hash of the HIP sources, to tell whether stored counter data is stale."""
+    """Hash of the pass-kernel sources, to tell whether stored counter data
+    for the GD iteration is stale."""
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "paper_2409_05734_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in PASS_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]

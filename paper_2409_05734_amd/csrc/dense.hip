@@ -31,55 +31,71 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64;   // output rows per workgroup
-constexpr int BN = 64;   // output columns per workgroup (32 signals, re/im)
-constexpr int BK = 64;   // reduction chunk
+// Both products are skinny GEMMs (N = 2 nb <= 64 real columns per tile)
+// whose reduction runs over the long dimension of A.  The reduction is split
+// over S workgroups (S chosen so that a launch has about four workgroups per
+// CU); each writes its 64 x 64 partial tile, and an epilogue kernel sums the S
+// partials in a fixed order and applies the solver arithmetic.  A is read in
+// its natural row-major layout in both products: in A X it is the MFMA's
+// first operand (rows i, reduction along 2n), in A^H R the second one
+// (reduction along m, columns 2n), computing P^T = Br^T At.
+constexpr int BT = 64;    // tile rows and columns
+constexpr int BK = 64;    // reduction chunk
 constexpr int PADK = BK + 4;
-constexpr int NT = 256;  // 4 waves, 2 x 2 wave tiles of 32 x 32
+constexpr int NT = 256;   // 4 waves, 2 x 2 wave tiles of 32 x 32
+constexpr int kTargetGroups = 1024;
 
-enum AMode : int { A_ROWS = 0, A_TRANS = 1 };
 enum Epi : int {
-  E1_STORE = 0,  // GEMM 1: z and/or |z|^2
-  E1_GD = 1,     // GEMM 1: r = (|z|^2 - y) z, loss partials
-  E1_SPEC = 2,   // GEMM 1: r = T(y/mean(y)) z
-  E2_STORE = 3,  // GEMM 2: x_out = A^H r * scale
-  E2_GD = 4,     // GEMM 2: x <- x - step * A^H r
-  E2_SPEC = 5    // GEMM 2: u <- step * A^H r - 2 lambda u / ||u||, norm partials
+  E1_STORE = 0,  // after A X: z and/or |z|^2
+  E1_GD = 1,     // after A X: r = (|z|^2 - y) z, loss partials
+  E1_SPEC = 2,   // after A X: r = T(y/mean(y)) z
+  E2_STORE = 3,  // after A^H R: x_out = A^H r * scale
+  E2_GD = 4,     // after A^H R: x <- x - step * A^H r
+  E2_SPEC = 5    // after A^H R: u <- step * A^H r - 2 lambda u / ||u||, norm partials
 };
 
 struct DenseArgs {
   const float* A;          // m x 2n floats
   int m, n, nb;
-  const float2* src;       // GEMM 1: X (nb x n); GEMM 2: R (nb x m)
+  const float2* src;       // A X: X (nb x n); A^H R: R (nb x m)
   const float* src_scale;  // per-signal scale of src (spectral 1/||u||), nullable
-  float2* z_out;           // GEMM 1 store / residual out (nb x m)
-  float* y_out;            // GEMM 1 store: |z|^2 (nb x m)
+  float2* z_out;           // A X store / residual out (nb x m)
+  float* y_out;            // A X store: |z|^2 (nb x m)
   const float* y;          // measurements (nb x m)
   const double* ysum;      // per-signal sum(y) (spectral)
   float lam;
-  float2* x;               // GEMM 2: output / iterate (nb x n)
+  float2* x;               // A^H R: output / iterate (nb x n)
   float step;
   float* part;             // partial sums [signal][row tile]
   int part_ld;             // row tiles
-  const float* prev_scale; // GEMM 2 spectral: 1/||u_p|| of the previous iterate
+  const float* prev_scale; // A^H R spectral: 1/||u_p|| of the previous iterate
+  // split reduction
+  float* split;            // S partial products
+  int S;                   // reduction splits
+  int kchunk;              // reduction length per split (multiple of BK)
+  int q_ld;                // 2 * (signals rounded up to 32): row length of the partials of A X
 };
 
 __device__ __forceinline__ f4 ld4(const float* p) { return *reinterpret_cast<const f4*>(p); }
 
-template <int AM, int EPI>
-__global__ void __launch_bounds__(NT) dense_gemm_kernel(const DenseArgs a) {
-  constexpr bool G1 = (AM == A_ROWS);
-  // GEMM 1: M = m, K = 2n; GEMM 2: M = 2n, K = m
-  const int M = G1 ? a.m : 2 * a.n;
-  const int K = G1 ? 2 * a.n : a.m;
+// Split-reduction GEMM.  G = 1: C (m x 2nb) = At . Bx over k in [0, 2n);
+// partial s stored at split[(s * m + i) * q_ld + q].  G = 2: C^T (2nb x 2n) =
+// Br^T . At over i in [0, m); partial s stored at split[(s * q_ld + q) * 2n + j].
+// grid.x = tiles * S (split index fastest), grid.y = signal tiles of 32.
+template <int G>
+__global__ void __launch_bounds__(NT) dense_mm_kernel(const DenseArgs a) {
+  const int M = G == 1 ? a.m : 2 * a.n;   // the big matrix's output extent
+  const int K = G == 1 ? 2 * a.n : a.m;
   const int lda = 2 * a.n;
-  const int i0 = blockIdx.x * BM;
-  const int p0 = blockIdx.y * (BN / 2);  // first signal of this column tile
+  const int s = blockIdx.x % a.S;
+  const int i0 = (blockIdx.x / a.S) * BT;       // first output row (G1) / column (G2) of A
+  const int p0 = blockIdx.y * (BT / 2);         // first signal of this tile
+  const int kbeg = s * a.kchunk;
+  const int kend = min(K, kbeg + a.kchunk);
 
-  __shared__ __attribute__((aligned(16))) float As[BM][PADK];
-  __shared__ __attribute__((aligned(16))) float Bs[BN][PADK];
-  __shared__ float Cs[BM][BN + 1];
-  __shared__ float red[NT];
+  // G1: As[i][k] (from A), Bs[q][k] (from X).  G2: As[q][k] (from R), Bs[k][j] (from A).
+  __shared__ __attribute__((aligned(16))) float As[BT][PADK];
+  __shared__ __attribute__((aligned(16))) float Bs[BT][PADK];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -96,70 +112,67 @@ __global__ void __launch_bounds__(NT) dense_gemm_kernel(const DenseArgs a) {
 
   // Per-thread staging of one chunk (register prefetch of the next chunk
   // overlaps its global loads with the MFMAs of the current one).
-  f4 ar[4];   // A: 16 floats
-  f4 br[4];   // B: 16 floats (two rows of the tile)
-  const int pl = tid >> 3;  // signal within the column tile (0..31)
+  f4 ar[4];   // 16 floats of A
+  f4 br[4];   // 16 floats of the small operand (two rows of the tile)
+  const int pl = tid >> 3;  // signal within the tile (0..31)
   const int p_ld = p0 + pl;
   const float sc = (a.src_scale != nullptr && p_ld < a.nb) ? a.src_scale[p_ld] : 1.f;
 
   auto load_chunk = [&](int k0) {
-    if constexpr (AM == A_ROWS) {
-      // row tid/4, k' = k0 + 16*(tid&3) .. +16
+    if constexpr (G == 1) {
+      // A row i0 + tid/4, k = k0 + 16*(tid&3) .. +16
       const int gi = i0 + (tid >> 2);
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
         const int gk = k0 + (tid & 3) * 16 + 4 * h;
         f4 v = f4{0.f, 0.f, 0.f, 0.f};
         if (gi < M) {
-          if (gk + 3 < K) {
+          if (gk + 3 < kend) {
             v = ld4(a.A + (long long)gi * lda + gk);
           } else {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-              if (gk + q < K) v[q] = a.A[(long long)gi * lda + gk + q];
+              if (gk + q < kend) v[q] = a.A[(long long)gi * lda + gk + q];
           }
         }
         ar[h] = v;
       }
-    } else {
-      // k = k0 + tid/4 (an A row), i = i0 + 16*(tid&3) .. +16
-      const int gk = k0 + (tid >> 2);
-#pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const int gi = i0 + (tid & 3) * 16 + 4 * h;
-        f4 v = f4{0.f, 0.f, 0.f, 0.f};
-        if (gk < K) {
-          if (gi + 3 < M) {
-            v = ld4(a.A + (long long)gk * lda + gi);
-          } else {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              if (gi + q < M) v[q] = a.A[(long long)gk * lda + gi + q];
-          }
-        }
-        ar[h] = v;
-      }
-    }
-    if constexpr (G1) {
       // 4 complex entries of x_p: k' = k0 + 8*(tid&7) .. +8
       const int kc = (k0 + (tid & 7) * 8) / 2;
       float2 xv[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         xv[q] = make_float2(0.f, 0.f);
-        if (p_ld < a.nb && kc + q < a.n) xv[q] = cscale(a.src[(long long)p_ld * a.n + kc + q], sc);
+        if (p_ld < a.nb && 2 * (kc + q) < kend) xv[q] = cscale(a.src[(long long)p_ld * a.n + kc + q], sc);
       }
       br[0] = f4{xv[0].x, -xv[0].y, xv[1].x, -xv[1].y};
       br[1] = f4{xv[2].x, -xv[2].y, xv[3].x, -xv[3].y};
       br[2] = f4{xv[0].y, xv[0].x, xv[1].y, xv[1].x};
       br[3] = f4{xv[2].y, xv[2].x, xv[3].y, xv[3].x};
     } else {
+      // A row k = k0 + tid/4 (an m index), columns j = i0 + 16*(tid&3) .. +16
+      const int gk = k0 + (tid >> 2);
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const int gj = i0 + (tid & 3) * 16 + 4 * h;
+        f4 v = f4{0.f, 0.f, 0.f, 0.f};
+        if (gk < kend) {
+          if (gj + 3 < M) {
+            v = ld4(a.A + (long long)gk * lda + gj);
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              if (gj + q < M) v[q] = a.A[(long long)gk * lda + gj + q];
+          }
+        }
+        ar[h] = v;
+      }
       // 8 complex entries of r_p: i = k0 + 8*(tid&7) .. +8
       const int ib = k0 + (tid & 7) * 8;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         float2 r = make_float2(0.f, 0.f);
-        if (p_ld < a.nb && ib + q < a.m) r = cscale(a.src[(long long)p_ld * a.m + ib + q], sc);
+        if (p_ld < a.nb && ib + q < kend) r = cscale(a.src[(long long)p_ld * a.m + ib + q], sc);
         br[q >> 2][q & 3] = r.x;
         br[2 + (q >> 2)][q & 3] = r.y;
       }
@@ -167,123 +180,192 @@ __global__ void __launch_bounds__(NT) dense_gemm_kernel(const DenseArgs a) {
   };
 
   auto store_chunk = [&]() {
-    if constexpr (AM == A_ROWS) {
+    // A: natural layout in both products (rows tid/4, 16 consecutive floats)
 #pragma unroll
-      for (int h = 0; h < 4; ++h) *reinterpret_cast<f4*>(&As[tid >> 2][(tid & 3) * 16 + 4 * h]) = ar[h];
-    } else {
-#pragma unroll
-      for (int h = 0; h < 4; ++h)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) As[(tid & 3) * 16 + 4 * h + q][tid >> 2] = ar[h][q];
+    for (int h = 0; h < 4; ++h) {
+      float* dst = G == 1 ? &As[tid >> 2][(tid & 3) * 16 + 4 * h] : &Bs[tid >> 2][(tid & 3) * 16 + 4 * h];
+      *reinterpret_cast<f4*>(dst) = ar[h];
     }
+    float(*S2)[PADK] = G == 1 ? Bs : As;
     const int kq = (tid & 7) * 8;
-    *reinterpret_cast<f4*>(&Bs[2 * pl][kq]) = br[0];
-    *reinterpret_cast<f4*>(&Bs[2 * pl][kq + 4]) = br[1];
-    *reinterpret_cast<f4*>(&Bs[2 * pl + 1][kq]) = br[2];
-    *reinterpret_cast<f4*>(&Bs[2 * pl + 1][kq + 4]) = br[3];
+    *reinterpret_cast<f4*>(&S2[2 * pl][kq]) = br[0];
+    *reinterpret_cast<f4*>(&S2[2 * pl][kq + 4]) = br[1];
+    *reinterpret_cast<f4*>(&S2[2 * pl + 1][kq]) = br[2];
+    *reinterpret_cast<f4*>(&S2[2 * pl + 1][kq + 4]) = br[3];
   };
 
-  load_chunk(0);
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    store_chunk();
-    __syncthreads();
-    if (k0 + BK < K) load_chunk(k0 + BK);
-    // MFMA over the chunk: blocks of 16 k; lane group g owns k = 16 kb + 4 g + kk
+  if (kbeg < kend) {
+    load_chunk(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+      store_chunk();
+      __syncthreads();
+      if (k0 + BK < kend) load_chunk(k0 + BK);
+      // blocks of 16 k; lane group g owns k = 16 kb + 4 g + kk
 #pragma unroll
-    for (int kb = 0; kb < BK / 16; ++kb) {
-      f4 av[2], bv[2];
+      for (int kb = 0; kb < BK / 16; ++kb) {
+        f4 av[2], bv[2];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        av[t] = *reinterpret_cast<const f4*>(&As[32 * wr + 16 * t + l16][16 * kb + 4 * g]);
-        bv[t] = *reinterpret_cast<const f4*>(&Bs[32 * wc + 16 * t + l16][16 * kb + 4 * g]);
+        for (int t = 0; t < 2; ++t) {
+          av[t] = *reinterpret_cast<const f4*>(&As[32 * wr + 16 * t + l16][16 * kb + 4 * g]);
+          if constexpr (G == 1) {
+            bv[t] = *reinterpret_cast<const f4*>(&Bs[32 * wc + 16 * t + l16][16 * kb + 4 * g]);
+          } else {
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) bv[t][kk] = Bs[16 * kb + 4 * g + kk][32 * wc + 16 * t + l16];
+          }
+        }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+          for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj)
+              acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ti][kk], bv[tj][kk], acc[ti][tj], 0, 0, 0);
       }
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-        for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-          for (int tj = 0; tj < 2; ++tj)
-            acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ti][kk], bv[tj][kk], acc[ti][tj], 0, 0, 0);
+      __syncthreads();
     }
-    __syncthreads();
   }
 
-  // ---- accumulators -> Cs (D[4*(lane/16)+r][lane%16] per 16x16 tile)
+  // ---- partial tile out: D[4*(lane/16)+r][lane%16] of each 16 x 16 block
+  const int q0 = 2 * p0;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Cs[32 * wr + 16 * ti + 4 * g + r][32 * wc + 16 * tj + l16] = acc[ti][tj][r];
-  __syncthreads();
-
-  float part = 0.f;
-  const int p = p_ld;
-  if constexpr (G1) {
-    // rows i0 + 8*(tid&7) .. +8 of signal p
-    const int ib = (tid & 7) * 8;
-    float ybar = 0.f;
-    if constexpr (EPI == E1_SPEC) ybar = p < a.nb ? (float)(a.ysum[p] / (double)a.m) : 0.f;
-    if (p < a.nb) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int il = ib + q;
-        const int gi = i0 + il;
-        if (gi >= a.m) break;
-        const float2 z = make_float2(Cs[il][2 * pl], Cs[il][2 * pl + 1]);
-        const long long o = (long long)p * a.m + gi;
-        if constexpr (EPI == E1_STORE) {
-          if (a.z_out) a.z_out[o] = z;
-          if (a.y_out) a.y_out[o] = cabs2(z);
-        } else if constexpr (EPI == E1_GD) {
-          const float d = cabs2(z) - a.y[o];
-          part += d * d;
-          a.z_out[o] = cscale(z, d);
+      for (int r = 0; r < 4; ++r) {
+        const int row = 32 * wr + 16 * ti + 4 * g + r;
+        const int col = 32 * wc + 16 * tj + l16;
+        if constexpr (G == 1) {
+          if (i0 + row < M) a.split[((long long)s * a.m + i0 + row) * a.q_ld + q0 + col] = acc[ti][tj][r];
         } else {
-          const float yy = a.y[o];
-          float w = a.lam;
-          if (yy > 0.f) w = fmaxf(1.f - ybar / yy, a.lam);
-          a.z_out[o] = cscale(z, w);
+          if (i0 + col < M) a.split[((long long)s * a.q_ld + q0 + row) * M + i0 + col] = acc[ti][tj][r];
         }
       }
-    }
-  } else {
-    // entries k0 + 4*(tid&7) .. +4 of signal p (rows 2k, 2k+1 of the tile)
-    const int kb = (tid & 7) * 4;
-    if (p < a.nb) {
+}
+
+// Epilogue after A X: z_pi = sum_s C_s[i][2p] + i C_s[i][2p+1] for 64 rows and
+// 32 signals, then the E1 arithmetic.  grid (row tiles, signal tiles).
+template <int EPI>
+__global__ void __launch_bounds__(NT) dense_epi1_kernel(const DenseArgs a) {
+  __shared__ float2 zs[BT][33];
+  __shared__ float red[NT];
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.x * BT;
+  const int p0 = blockIdx.y * 32;
+  {
+    // gather: thread (row il = tid/32 + 8u, signal pl = tid%32): coalesced over signals
+    const int pl = tid & 31;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int kl = kb + q;
-        const int gk = i0 / 2 + kl;
-        if (gk >= a.n) break;
-        const float2 gv = make_float2(Cs[2 * kl][2 * pl] + Cs[2 * kl + 1][2 * pl + 1],
-                                      Cs[2 * kl][2 * pl + 1] - Cs[2 * kl + 1][2 * pl]);
-        const long long o = (long long)p * a.n + gk;
-        if constexpr (EPI == E2_STORE) {
-          a.x[o] = cscale(gv, a.step);
-        } else if constexpr (EPI == E2_GD) {
-          const float2 xo = a.x[o];
-          a.x[o] = make_float2(xo.x - a.step * gv.x, xo.y - a.step * gv.y);
-        } else {
-          // u_new = step * M v - 2 lambda v, v = u / ||u|| (the 1/||u|| was applied to R's source in GEMM 1)
-          const float2 uo = a.x[o];
-          const float c = 2.f * a.lam * a.prev_scale[p];
-          const float2 nu = make_float2(a.step * gv.x - c * uo.x, a.step * gv.y - c * uo.y);
-          a.x[o] = nu;
-          part += cabs2(nu);
+    for (int u = 0; u < 8; ++u) {
+      const int il = (tid >> 5) + 8 * u;
+      const int gi = i0 + il;
+      float2 z = make_float2(0.f, 0.f);
+      if (gi < a.m) {
+        for (int s = 0; s < a.S; ++s) {
+          const float2 c = *reinterpret_cast<const float2*>(&a.split[((long long)s * a.m + gi) * a.q_ld + 2 * (p0 + pl)]);
+          z.x += c.x;
+          z.y += c.y;
         }
+      }
+      zs[il][pl] = z;
+    }
+  }
+  __syncthreads();
+  // apply: thread (signal pl = tid/8, rows 8*(tid&7) .. +8): coalesced over rows
+  const int pl = tid >> 3;
+  const int p = p0 + pl;
+  const int ib = (tid & 7) * 8;
+  float part = 0.f;
+  float ybar = 0.f;
+  if constexpr (EPI == E1_SPEC) ybar = p < a.nb ? (float)(a.ysum[p] / (double)a.m) : 0.f;
+  if (p < a.nb) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int il = ib + q;
+      const int gi = i0 + il;
+      if (gi >= a.m) break;
+      const float2 z = zs[il][pl];
+      const long long o = (long long)p * a.m + gi;
+      if constexpr (EPI == E1_STORE) {
+        if (a.z_out) a.z_out[o] = z;
+        if (a.y_out) a.y_out[o] = cabs2(z);
+      } else if constexpr (EPI == E1_GD) {
+        const float d = cabs2(z) - a.y[o];
+        part += d * d;
+        a.z_out[o] = cscale(z, d);
+      } else {
+        const float yy = a.y[o];
+        float w = a.lam;
+        if (yy > 0.f) w = fmaxf(1.f - ybar / yy, a.lam);
+        a.z_out[o] = cscale(z, w);
       }
     }
   }
-  if constexpr (EPI == E1_GD || EPI == E2_SPEC) {
+  if constexpr (EPI == E1_GD) {
     // per-signal partials: the 8 threads of signal pl are consecutive
     red[tid] = part;
     __syncthreads();
     if ((tid & 7) == 0 && p < a.nb) {
-      float s = 0.f;
+      float t = 0.f;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) s += red[tid + q];
-      a.part[(long long)p * a.part_ld + blockIdx.x] = s;
+      for (int q = 0; q < 8; ++q) t += red[tid + q];
+      a.part[(long long)p * a.part_ld + blockIdx.x] = t;
+    }
+  }
+}
+
+// Epilogue after A^H R: g_pk = (P[2k][2p] + P[2k+1][2p+1]) + i (P[2k][2p+1] -
+// P[2k+1][2p]), P = sum_s P_s, for 32 entries k and 32 signals, then the E2
+// arithmetic.  grid (k tiles of 32, signal tiles).
+template <int EPI>
+__global__ void __launch_bounds__(NT) dense_epi2_kernel(const DenseArgs a) {
+  __shared__ float red[NT];
+  const int tid = threadIdx.x;
+  const int pl = tid >> 3;
+  const int p = blockIdx.y * 32 + pl;
+  const int kb = blockIdx.x * 32 + (tid & 7) * 4;
+  const int J = 2 * a.n;
+  float part = 0.f;
+  if (p < a.nb) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int gk = kb + q;
+      if (gk >= a.n) break;
+      float2 re = make_float2(0.f, 0.f), im = make_float2(0.f, 0.f);  // (P[2k][2p], P[2k+1][2p]), (.., 2p+1)
+      for (int s = 0; s < a.S; ++s) {
+        const float2 u = *reinterpret_cast<const float2*>(&a.split[((long long)s * a.q_ld + 2 * p) * J + 2 * gk]);
+        const float2 v = *reinterpret_cast<const float2*>(&a.split[((long long)s * a.q_ld + 2 * p + 1) * J + 2 * gk]);
+        re.x += u.x;
+        re.y += u.y;
+        im.x += v.x;
+        im.y += v.y;
+      }
+      const float2 gv = make_float2(re.x + im.y, im.x - re.y);
+      const long long o = (long long)p * a.n + gk;
+      if constexpr (EPI == E2_STORE) {
+        a.x[o] = cscale(gv, a.step);
+      } else if constexpr (EPI == E2_GD) {
+        const float2 xo = a.x[o];
+        a.x[o] = make_float2(xo.x - a.step * gv.x, xo.y - a.step * gv.y);
+      } else {
+        // u_new = step * M v - 2 lambda v, v = u / ||u|| (the 1/||u|| was applied to R's source in A X)
+        const float2 uo = a.x[o];
+        const float c = 2.f * a.lam * a.prev_scale[p];
+        const float2 nu = make_float2(a.step * gv.x - c * uo.x, a.step * gv.y - c * uo.y);
+        a.x[o] = nu;
+        part += cabs2(nu);
+      }
+    }
+  }
+  if constexpr (EPI == E2_SPEC) {
+    red[tid] = part;
+    __syncthreads();
+    if ((tid & 7) == 0 && p < a.nb) {
+      float t = 0.f;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t += red[tid + q];
+      a.part[(long long)p * a.part_ld + blockIdx.x] = t;
     }
   }
 }
@@ -350,11 +432,34 @@ __global__ void dense_final_scale_kernel(float2* x, int n, int nb, const double*
   }
 }
 
-template <int AM, int EPI>
-hipError_t gemm(const DenseArgs& a, hipStream_t s) {
-  const int M = AM == A_ROWS ? a.m : 2 * a.n;
-  dim3 grid((M + BM - 1) / BM, (a.nb + BN / 2 - 1) / (BN / 2));
-  hipLaunchKernelGGL((dense_gemm_kernel<AM, EPI>), grid, dim3(NT), 0, s, a);
+// Reduction splits of one product: about kTargetGroups workgroups, every
+// split a whole number of BK chunks.
+void plan_split(int tiles, int K, int* S, int* kchunk) {
+  const int chunks = (K + BK - 1) / BK;
+  int want = std::max(1, std::min(chunks, (kTargetGroups + tiles - 1) / tiles));
+  const int per = (chunks + want - 1) / want;
+  *kchunk = per * BK;
+  *S = (chunks + per - 1) / per;
+}
+
+int signal_tiles(const DenseArgs& a) { return (a.nb + 31) / 32; }
+
+template <int G, int EPI>
+hipError_t gemm(DenseArgs a, float* split, hipStream_t st) {
+  const int M = G == 1 ? a.m : 2 * a.n;
+  const int K = G == 1 ? 2 * a.n : a.m;
+  const int tiles = (M + BT - 1) / BT;
+  plan_split(tiles * signal_tiles(a), K, &a.S, &a.kchunk);
+  a.split = split;
+  a.q_ld = 64 * signal_tiles(a);
+  hipLaunchKernelGGL((dense_mm_kernel<G>), dim3(tiles * a.S, signal_tiles(a)), dim3(NT), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if constexpr (G == 1) {
+    hipLaunchKernelGGL((dense_epi1_kernel<EPI>), dim3(tiles, signal_tiles(a)), dim3(NT), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((dense_epi2_kernel<EPI>), dim3((a.n + 31) / 32, signal_tiles(a)), dim3(NT), 0, st, a);
+  }
   return hipGetLastError();
 }
 
@@ -367,8 +472,8 @@ DenseArgs base(const sr_plan_s* p) {
   return a;
 }
 
-int row_tiles_g1(const DenseArgs& a) { return (a.m + BM - 1) / BM; }
-int row_tiles_g2(const DenseArgs& a) { return (2 * a.n + BM - 1) / BM; }
+int row_tiles_g1(const DenseArgs& a) { return (a.m + BT - 1) / BT; }
+int row_tiles_g2(const DenseArgs& a) { return (a.n + 31) / 32; }
 
 #define DN_HIP(x)                                     \
   do {                                                \
@@ -378,6 +483,22 @@ int row_tiles_g2(const DenseArgs& a) { return (2 * a.n + BM - 1) / BM; }
 
 }  // namespace
 
+// Floats of split-reduction partials a dense plan of this shape needs: the
+// larger of the two products' S x (rows) x (64 per signal tile).
+size_t dense_split_floats(int m, int n, int nb) {
+  DenseArgs a{};
+  a.m = m;
+  a.n = n;
+  a.nb = nb;
+  const int st = signal_tiles(a);
+  int S1, S2, kc;
+  plan_split(((m + BT - 1) / BT) * st, 2 * n, &S1, &kc);
+  plan_split(((2 * n + BT - 1) / BT) * st, m, &S2, &kc);
+  const size_t f1 = (size_t)S1 * m * 64 * st;
+  const size_t f2 = (size_t)S2 * 2 * n * 64 * st;
+  return std::max(f1, f2);
+}
+
 // Scratch layout for dense plans: bufA holds R (nb x m complex); fscratch
 // holds per-signal scalars; part holds per-signal partials.
 sr_status dense_forward(sr_plan_s* p, const float2* x, float2* z, float* y) {
@@ -385,7 +506,7 @@ sr_status dense_forward(sr_plan_s* p, const float2* x, float2* z, float* y) {
   a.src = x;
   a.z_out = z;
   a.y_out = y;
-  DN_HIP((gemm<A_ROWS, E1_STORE>(a, p->stream)));
+  DN_HIP((gemm<1, E1_STORE>(a, p->dsplit, p->stream)));
   return SR_OK;
 }
 
@@ -394,7 +515,7 @@ sr_status dense_adjoint(sr_plan_s* p, const float2* r, float2* x) {
   a.src = r;
   a.x = x;
   a.step = 1.f;
-  DN_HIP((gemm<A_TRANS, E2_STORE>(a, p->stream)));
+  DN_HIP((gemm<2, E2_STORE>(a, p->dsplit, p->stream)));
   return SR_OK;
 }
 
@@ -411,7 +532,7 @@ sr_status dense_gd(sr_plan_s* p, const float* y, float2* x, int iters, const flo
     g1.z_out = p->bufA;
     g1.part = p->part;
     g1.part_ld = t1;
-    DN_HIP((gemm<A_ROWS, E1_GD>(g1, p->stream)));
+    DN_HIP((gemm<1, E1_GD>(g1, p->dsplit, p->stream)));
     if (loss_trace) {
       hipLaunchKernelGGL(sum_rows_kernel, dim3((a.nb + 63) / 64), dim3(64), 0, p->stream, p->part, t1, t1, a.nb,
                          loss_trace + it, iters);
@@ -421,7 +542,7 @@ sr_status dense_gd(sr_plan_s* p, const float* y, float2* x, int iters, const flo
     g2.src = p->bufA;
     g2.x = x;
     g2.step = eta[0] / (float)a.m;
-    DN_HIP((gemm<A_TRANS, E2_GD>(g2, p->stream)));
+    DN_HIP((gemm<2, E2_GD>(g2, p->dsplit, p->stream)));
   }
   return SR_OK;
 }
@@ -449,7 +570,7 @@ sr_status dense_spectral(sr_plan_s* p, const float* y, const float2* v0, int ite
     g1.ysum = ysum;
     g1.lam = lam;
     g1.z_out = p->bufA;
-    DN_HIP((gemm<A_ROWS, E1_SPEC>(g1, p->stream)));
+    DN_HIP((gemm<1, E1_SPEC>(g1, p->dsplit, p->stream)));
     DenseArgs g2 = a;  // u <- A^H r / (m c) - 2 lambda u / ||u||
     g2.src = p->bufA;
     g2.x = x0;
@@ -458,7 +579,7 @@ sr_status dense_spectral(sr_plan_s* p, const float* y, const float2* v0, int ite
     g2.prev_scale = inv;
     g2.part = p->part;
     g2.part_ld = t2;
-    DN_HIP((gemm<A_TRANS, E2_SPEC>(g2, p->stream)));
+    DN_HIP((gemm<2, E2_SPEC>(g2, p->dsplit, p->stream)));
     cnt = t2;
   }
   hipLaunchKernelGGL(inv_norms_kernel, dim3((a.nb + 63) / 64), dim3(64), 0, p->stream, p->part, t2, cnt, a.nb, inv);

@@ -36,7 +36,8 @@ enum PassKind : int {
 // each mode; the plan's tuner picks one per (length, mode).
 // Row mode: 1 wave or 4 waves per workgroup.  Column mode: 2, 4, 8 or 16
 // adjacent columns (16- to 128-byte row segments), within 1024 threads and
-// the LDS budget (double-buffered tiles).
+// the LDS budget (double-buffered tiles, and single-buffered ones where they
+// raise occupancy).
 template <int N, int EV = 0>
 struct TileCfg {
   static constexpr int TPT = TileV<N, 1, true, true, EV>::TPT;
@@ -45,11 +46,12 @@ struct TileCfg {
   static constexpr int kMaxLds = 152 * 1024;  // dynamic LDS per workgroup (160 KB minus static)
   static constexpr bool col_ok(int b) { return b * TPT <= 1024 && lds_bytes(b) <= kMaxLds; }
   static constexpr bool row_ok(int b) { return b >= 1 && b * TPT <= 1024 && lds_bytes(b) <= 65536; }
-  // single-buffered column tiles: offered where the double-buffered tile of
-  // the same width would not let two workgroups share a CU
-  static constexpr bool col_sb_ok(int b) {
-    return b * TPT <= 1024 && lds_bytes(b) > kMaxLds / 2 && lds_bytes(b) / 2 <= kMaxLds;
-  }
+  // single-buffered tiles (half the LDS, two barriers per stage): offered
+  // where the double-buffered tile of the same width needs 32 KB or more, so
+  // that halving it raises the number of workgroups a CU holds
+  static constexpr bool sb_ok(int b) { return b * TPT <= 1024 && lds_bytes(b) >= 32768 && lds_bytes(b) / 2 <= kMaxLds; }
+  static constexpr bool col_sb_ok(int b) { return sb_ok(b); }
+  static constexpr bool row_sb_ok(int b) { return sb_ok(b); }
   static constexpr int ROW_SMALL = TPT >= 64 ? 1 : 64 / TPT;   // one wave
   static constexpr int ROW_BIG = TPT >= 256 ? 1 : 256 / TPT;   // four waves
 };

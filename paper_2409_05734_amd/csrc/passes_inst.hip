@@ -150,6 +150,16 @@ hipError_t by_tile(int kind, bool col, int Benc, const PassArgs& a, hipStream_t 
     }
     return hipErrorInvalidValue;
   }
+  if (Benc & kSingleBuffer) {
+    const int B = Benc & ~kSingleBuffer;
+    if constexpr (Cfg::row_sb_ok(Cfg::ROW_SMALL)) {
+      if (B == Cfg::ROW_SMALL) return dispatch<N, false, Cfg::ROW_SMALL | kSingleBuffer>(kind, a, s);
+    }
+    if constexpr (Cfg::ROW_BIG != Cfg::ROW_SMALL && Cfg::row_sb_ok(Cfg::ROW_BIG)) {
+      if (B == Cfg::ROW_BIG) return dispatch<N, false, Cfg::ROW_BIG | kSingleBuffer>(kind, a, s);
+    }
+    return hipErrorInvalidValue;
+  }
   const int B = Benc;
   if (B == Cfg::ROW_SMALL) return dispatch<N, false, Cfg::ROW_SMALL>(kind, a, s);
   if constexpr (Cfg::ROW_BIG != Cfg::ROW_SMALL) {
@@ -175,6 +185,9 @@ int tile_options_n<SR_FFT_N>(bool col, int* out, int max_out) {
   } else {
     if (n < max_out) out[n++] = Cfg::ROW_SMALL;
     if (Cfg::ROW_BIG != Cfg::ROW_SMALL && n < max_out) out[n++] = Cfg::ROW_BIG;
+    if (Cfg::row_sb_ok(Cfg::ROW_SMALL) && n < max_out) out[n++] = Cfg::ROW_SMALL | kSingleBuffer;
+    if (Cfg::ROW_BIG != Cfg::ROW_SMALL && Cfg::row_sb_ok(Cfg::ROW_BIG) && n < max_out)
+      out[n++] = Cfg::ROW_BIG | kSingleBuffer;
     if (kHasNarrow) {
       if (n < max_out) out[n++] = CfgN::ROW_SMALL | kNarrow;
       if (CfgN::ROW_BIG != CfgN::ROW_SMALL && n < max_out) out[n++] = CfgN::ROW_BIG | kNarrow;

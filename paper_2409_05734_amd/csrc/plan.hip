@@ -62,7 +62,10 @@ sr_status sr_plan_s::init(const float* theta_host) {
   size_t b_sync = 256;
   size_t b_red = align256(sizeof(double) * 1024);
   int ngrid = (kind == SR_DENSE) ? 2 : 4;
-  ws_bytes = b_theta + b_eph + b_tw + ngrid * b_grid + b_part + b_ysum + b_fs + b_sync + b_red;
+  size_t b_dsplit = 0;
+  if (kind == SR_DENSE)
+    b_dsplit = align256(sizeof(float) * sr::dense_split_floats((int)geo[0].m, (int)geo[0].n, (int)np));
+  ws_bytes = b_theta + b_eph + b_tw + ngrid * b_grid + b_part + b_ysum + b_fs + b_sync + b_red + b_dsplit;
   hipError_t e = hipMalloc(&ws, ws_bytes);
   if (e != hipSuccess) {
     ws = nullptr;
@@ -94,6 +97,8 @@ sr_status sr_plan_s::init(const float* theta_host) {
   sync = (unsigned*)c;
   c += b_sync;
   red_ws = (double*)c;
+  c += b_red;
+  if (b_dsplit) dsplit = (float*)c;
 
   size_t o = 0;
   for (int N : lens) {

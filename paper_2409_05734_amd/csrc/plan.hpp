@@ -59,6 +59,7 @@ struct sr_plan_s {
   int part_cap = 0;
   double* ysum = nullptr;  // sum(y) scratch (per problem)
   float* fscratch = nullptr;  // float scratch (dense solver scalars)
+  float* dsplit = nullptr;    // dense plans: split-reduction partial products
   unsigned* sync = nullptr;   // [0] grid-barrier counter, [1] barrier error flag
   double* red_ws = nullptr;   // per-workgroup partials of the two-stage reductions (kRedGroups)
   float2* vjp_buf = nullptr;  // per-layer intermediates for derivatives (allocated on first use)
@@ -92,6 +93,7 @@ sr_status final_scale(sr_plan_s* p, float2* x, int64_t n, const float* part, int
 sr_status fill_phase_table(sr_plan_s* p);
 
 // dense.hip (i.i.d. complex Gaussian baseline)
+size_t dense_split_floats(int m, int n, int nb);
 sr_status dense_forward(sr_plan_s* p, const float2* x, float2* z, float* y);
 sr_status dense_adjoint(sr_plan_s* p, const float2* r, float2* x);
 sr_status dense_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta, float* loss_trace);
