@@ -331,7 +331,9 @@ def batched(torch, srpr, sr_inputs, dev, iters=300):
             "recovered_batched": int((eb < 1e-3).sum()), "recovered_loop": int((el < 1e-3).sum()),
             "nonfinite_batched": int(np.isinf(eb).sum()), "nonfinite_loop": int(np.isinf(el).sum()),
             "max_err_recovered_batched": float(eb[both].max()) if both.any() else None,
-            "max_err_recovered_loop": float(el[both].max()) if both.any() else None}
+            "max_err_recovered_loop": float(el[both].max()) if both.any() else None,
+            "median_err_batched": float(np.median(eb)), "median_err_loop": float(np.median(el)),
+            "max_err_gap_finite": float(np.max(np.abs(eb - el)[np.isfinite(eb) & np.isfinite(el)]))}
 
 
 def autograd(torch, srpr, sr_inputs, dev):
