@@ -333,7 +333,7 @@ def batched(torch, srpr, sr_inputs, dev, iters=300):
             "max_err_recovered_batched": float(eb[both].max()) if both.any() else None,
             "max_err_recovered_loop": float(el[both].max()) if both.any() else None,
             "median_err_batched": float(np.median(eb)), "median_err_loop": float(np.median(el)),
-            "max_err_gap_finite": float(np.max(np.abs(eb - el)[np.isfinite(eb) & np.isfinite(el)]))}
+            "max_err_gap_finite": float(np.max(np.abs((eb - el)[np.isfinite(eb) & np.isfinite(el)])))}
 
 
 def autograd(torch, srpr, sr_inputs, dev):

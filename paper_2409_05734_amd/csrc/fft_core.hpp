@@ -281,9 +281,21 @@ struct Tile {
   static constexpr int NTW = tw_offset(RL::count) > 0 ? tw_offset(RL::count) : 1;
   using Twiddles = float2[NTW];
 
-  // tw: table exp(-2 pi i e/N), e = 0..N-1, rounded from float64.
+  // tw: this shape's thread-order twiddle table, entry i * TPT + t = twiddle
+  // slot i of thread t (so each load instruction reads consecutive entries),
+  // values exp(-2 pi i e/N) rounded from float64 (see for_each_twiddle).
   __device__ __forceinline__ static void load_twiddles(Twiddles& w, const float2* __restrict__ tw, int t) {
-    load_tw_stage<1>(w, tw, t);
+#pragma unroll
+    for (int i = 0; i < NTW; ++i) w[i] = tw[i * TPT + t];
+  }
+
+  // Host: calls f(slot, t, e) for every twiddle slot of every thread, where
+  // slot i of thread t holds exp(-2 pi i e/N).  Stage S >= 1 (span P, radix R)
+  // multiplies input r of butterfly q by w^(r k), k = (t + q TPT) mod P,
+  // w = exp(-2 pi i/(P R)), i.e. e = r k N/(P R).
+  template <class F>
+  static void for_each_twiddle(F&& f) {
+    twiddle_stage<1>(f);
   }
 
   // Forward (INV=false) or inverse (INV=true) unscaled DFT of the B transforms.
@@ -297,20 +309,19 @@ struct Tile {
   }
 
  private:
-  template <int S>
-  __device__ __forceinline__ static void load_tw_stage(Twiddles& w, const float2* __restrict__ tw, int t) {
+  template <int S, class F>
+  static void twiddle_stage(F& f) {
     if constexpr (S < RL::count) {
       constexpr int R = RL::values[S];
       constexpr int P = RL::span(S);
       constexpr int Q = E / R;
       constexpr int STRIDE = N / (P * R);
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int k = (t + q * TPT) % P;
-#pragma unroll
-        for (int r = 1; r < R; ++r) w[tw_offset(S) + q * (R - 1) + (r - 1)] = tw[r * k * STRIDE];
-      }
-      load_tw_stage<S + 1>(w, tw, t);
+      for (int t = 0; t < TPT; ++t)
+        for (int q = 0; q < Q; ++q) {
+          const int k = (t + q * TPT) % P;
+          for (int r = 1; r < R; ++r) f(tw_offset(S) + q * (R - 1) + (r - 1), t, r * k * STRIDE);
+        }
+      twiddle_stage<S + 1>(f);
     }
   }
 

@@ -60,7 +60,8 @@ struct PassArgs {
   int ntr;            // number of transforms (rows or columns) in this pass
   int tr_lo;          // grid coordinate of transform 0 on the other axis
   long long grid_ld;  // M2, row stride of the full measurement grid
-  const float2* tw;   // exp(-2 pi i e/N), e = 0..N-1
+  const float2* tw;   // thread-order twiddle table of the default thread shape
+  const float2* tw_n; // ... of the narrow thread shape (lengths that have one)
   const float* th_pre;
   const float* th_mid;
   const float* th_post;
@@ -152,7 +153,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   float2 sv[E];   // saved intermediate
   float gt[E];    // phase-cotangent accumulator
   typename T::Twiddles w;
-  T::load_twiddles(w, a.tw, t);
+  T::load_twiddles(w, EV ? a.tw_n : a.tw, t);
   const Rsrc r_in = rsrc(a.in);
   const Rsrc r_out = rsrc(a.out);
   const Rsrc r_pre = TAB ? rsrc(a.ep_pre) : rsrc(a.th_pre);

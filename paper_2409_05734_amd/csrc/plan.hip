@@ -13,6 +13,46 @@ using sr::Geo;
 
 namespace {
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Thread-order twiddle table of one tile shape (see Tile::load_twiddles):
+// slot i of thread t at i * TPT + t, exp(-2 pi i e/N) evaluated in float64
+// and rounded once.
+template <int N, int EV>
+void fill_twiddles(std::vector<float2>& out) {
+  using T = sr::TileV<N, 1, false, true, EV>;
+  out.assign((size_t)T::NTW * T::TPT, make_float2(1.f, 0.f));
+  T::for_each_twiddle([&](int slot, int t, int e) {
+    const double ang = -2.0 * M_PI * (double)e / (double)N;
+    out[(size_t)slot * T::TPT + t] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  });
+}
+
+template <int N>
+bool twiddles_for(int shape, std::vector<float2>& out) {
+  if (shape == 0) {
+    fill_twiddles<N, 0>(out);
+    return true;
+  }
+  if constexpr (sr::HasNarrow<N>::value) {
+    fill_twiddles<N, 1>(out);
+    return true;
+  }
+  return false;
+}
+
+// false if the length has no such shape
+bool thread_twiddles(int N, int shape, std::vector<float2>& out) {
+  switch (N) {
+#define SR_TW(n) \
+  case n:        \
+    return twiddles_for<n>(shape, out);
+    SR_TW(16) SR_TW(32) SR_TW(64) SR_TW(96) SR_TW(128) SR_TW(192) SR_TW(256) SR_TW(384) SR_TW(512) SR_TW(768)
+    SR_TW(1024) SR_TW(2048) SR_TW(4096)
+#undef SR_TW
+    default:
+      return false;
+  }
+}
 }  // namespace
 
 sr_status sr_plan_s::init(const float* theta_host) {
@@ -24,7 +64,7 @@ sr_status sr_plan_s::init(const float* theta_host) {
     yoff[i + 1] = yoff[i] + geo[i].m;
   }
 
-  // twiddle tables exp(-2 pi i e/N), evaluated in float64 and rounded once
+  // twiddle tables of every FFT length (and thread shape) the plan uses
   std::set<int> lens;
   int64_t max_m = 0;
   int cap = 1;
@@ -34,19 +74,17 @@ sr_status sr_plan_s::init(const float* theta_host) {
     lens.insert(g.M1);
     if (g.ndim == 2) lens.insert(g.M2);
   }
-  size_t tw_elems = 0;
-  for (int N : lens) tw_elems += N;
-  std::vector<float2> host_tw(tw_elems);
-  {
-    size_t o = 0;
-    for (int N : lens) {
-      for (int e = 0; e < N; ++e) {
-        const double ang = -2.0 * M_PI * (double)e / (double)N;
-        host_tw[o + e] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-      }
-      o += N;
+  std::vector<float2> host_tw;
+  std::vector<std::pair<std::pair<int, int>, size_t>> tw_at;  // ((length, shape), offset)
+  for (int N : lens)
+    for (int shape = 0; shape < 2; ++shape) {
+      std::vector<float2> t;
+      if (!thread_twiddles(N, shape, t)) continue;
+      tw_at.push_back({{N, shape}, host_tw.size()});
+      host_tw.insert(host_tw.end(), t.begin(), t.end());
+      host_tw.resize((host_tw.size() + 31) / 32 * 32, make_float2(0.f, 0.f));  // 256-byte aligned tables
     }
-  }
+  const size_t tw_elems = host_tw.size();
 
   // partial sums: one per workgroup of any pass (at most one per transform)
   for (const Geo& g : geo) cap = std::max<int>(cap, (int)std::max(g.M1, g.M2) + 1);
@@ -100,11 +138,7 @@ sr_status sr_plan_s::init(const float* theta_host) {
   c += b_red;
   if (b_dsplit) dsplit = (float*)c;
 
-  size_t o = 0;
-  for (int N : lens) {
-    tw[N] = twbuf + o;
-    o += N;
-  }
+  for (const auto& ta : tw_at) tw[ta.first] = twbuf + ta.second;
   if (tw_elems) {
     e = hipMemcpy(twbuf, host_tw.data(), sizeof(float2) * tw_elems, hipMemcpyHostToDevice);
     if (e != hipSuccess) return sr::hip_fail(e, "twiddle upload");
@@ -131,8 +165,8 @@ sr_status sr_plan_s::init(const float* theta_host) {
   return SR_OK;
 }
 
-const float2* sr_plan_s::twiddles(int N) const {
-  auto it = tw.find(N);
+const float2* sr_plan_s::twiddles(int N, int shape) const {
+  auto it = tw.find({N, shape});
   return it == tw.end() ? nullptr : it->second;
 }
 

@@ -45,7 +45,7 @@ struct sr_plan_s {
   int64_t theta_len = 0;
   const float2* dense_A = nullptr;  // caller-owned dense matrix (SR_DENSE)
 
-  std::map<int, float2*> tw;  // FFT length -> device twiddle table
+  std::map<std::pair<int, int>, float2*> tw;  // (FFT length, thread shape) -> device twiddle table
   float2* twbuf = nullptr;
 
   // workspace carved out of one allocation
@@ -77,7 +77,7 @@ struct sr_plan_s {
   }
 
   sr_status init(const float* theta_host);
-  const float2* twiddles(int N) const;
+  const float2* twiddles(int N, int shape = 0) const;
   const float* theta_l(const sr::Geo& g, int l) const;
   ~sr_plan_s();
 };

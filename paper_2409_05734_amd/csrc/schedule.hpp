@@ -25,7 +25,8 @@ inline PassArgs base_args(const sr_plan_s* p, const Geo& g, int k) {
   PassArgs a;
   std::memset(&a, 0, sizeof(a));
   a.grid_ld = g.M2;
-  a.tw = p->twiddles(pass_len(g, k));
+  a.tw = p->twiddles(pass_len(g, k), 0);
+  a.tw_n = p->twiddles(pass_len(g, k), 1);
   a.scale_pre = 1.f;
   a.scale_mid = 1.f;
   a.scale_out = 1.f;
