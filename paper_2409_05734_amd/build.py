@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsrpr.so")
 
 FFT_LENGTHS = (16, 32, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 2048)
-SOURCES = ("sr_api.hip", "plan.hip", "dispatch.hip", "util_kernels.hip", "dense.hip", "vjp.hip", "persist.hip", "batched.hip")
+SOURCES = ("sr_api.hip", "plan.hip", "dispatch.hip", "util_kernels.hip", "dense.hip", "vjp.hip", "persist.hip", "batched.hip", "fused2d.hip")
 
 ARCH = os.environ.get("SR_OFFLOAD_ARCH", "gfx950")
 

@@ -153,10 +153,15 @@ struct BatchState {
 
 void destroy_batch_state(BatchState* s) { delete s; }
 
+// Problems whose whole grid fits one workgroup's LDS run in the LDS-resident
+// solver (one launch for the whole solve); the others run as level launches.
+static bool lds_resident(const Geo& g) { return fused2d_enabled() && fused2d_supported(g); }
+
 bool batched_supported(const sr_plan_s* p) {
   if (p->kind != SR_STRUCTURED || p->geo.size() < 2) return false;
   for (const Geo& g : p->geo)
-    if (g.ndim != 2 || batch_tile_width(g.M1) == 0 || batch_tile_width(g.M2) == 0) return false;
+    if (g.ndim != 2 || (!lds_resident(g) && (batch_tile_width(g.M1) == 0 || batch_tile_width(g.M2) == 0)))
+      return false;
   return true;
 }
 
@@ -242,6 +247,7 @@ static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const fl
     p->bufA = st->bufs + off;  // each problem's private ping-pong buffers
     p->bufB = st->bufs + off + g.m;
     off += 2 * (size_t)g.m;
+    if (lds_resident(g)) continue;  // solved by the LDS-resident kernel
     const float* yi = y + p->yoff[i];
     float2* xi = x + p->xoff[i];
     const float step = eta[i] / (float)g.m;
@@ -275,12 +281,33 @@ static sr_status run_levels(sr_plan_s* p, const LevelSet& ls) {
   return SR_OK;
 }
 
+static sr_status batched_levels_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta);
+
 sr_status batched_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta) {
+  if (iters <= 0) return SR_OK;
+  std::vector<int> small, rest;
+  for (size_t i = 0; i < p->geo.size(); ++i) (lds_resident(p->geo[i]) ? small : rest).push_back((int)i);
+  if (rest.empty()) return fused2d_gd(p, small, y, x, iters, eta, p->stream);
+  sr_status s = SR_OK;
+  if (!small.empty()) {
+    // the LDS-resident solves run on the auxiliary stream beside the levels
+    if ((s = aux_fork(p)) != SR_OK) return s;
+    if ((s = fused2d_gd(p, small, y, x, iters, eta, p->aux_stream)) != SR_OK) return s;
+  }
+  s = batched_levels_gd(p, y, x, iters, eta);
+  if (!small.empty()) {
+    sr_status j = aux_join(p);
+    if (s == SR_OK) s = j;
+  }
+  return s;
+}
+
+// GD of the problems that are not LDS-resident, one launch per pass level.
+static sr_status batched_levels_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta) {
   BatchState* st = nullptr;
   sr_status s = batch_prepare(p, y, x, eta, &st);
   if (s != SR_OK) return s;
   constexpr int kChunk = 50;
-  if (iters <= 0) return SR_OK;
   s = run_levels(p, st->first);
   if (s != SR_OK) return s;
   int it = 0;

@@ -170,8 +170,36 @@ const float2* sr_plan_s::twiddles(int N, int shape) const {
   return it == tw.end() ? nullptr : it->second;
 }
 
+sr_status sr::aux_fork(sr_plan_s* p) {
+  hipError_t e = hipSuccess;
+  if (p->aux_stream == nullptr) {
+    e = hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) return sr::hip_fail(e, "auxiliary stream");
+  }
+  e = hipEventRecord(p->ev_fork, p->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(p->aux_stream, p->ev_fork, 0);
+  if (e != hipSuccess) return sr::hip_fail(e, "stream fork");
+  return SR_OK;
+}
+
+sr_status sr::aux_join(sr_plan_s* p) {
+  hipError_t e = hipEventRecord(p->ev_join, p->aux_stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(p->stream, p->ev_join, 0);
+  if (e != hipSuccess) return sr::hip_fail(e, "stream join");
+  return SR_OK;
+}
+
 sr_plan_s::~sr_plan_s() {
   for (auto& g : graphs) hipGraphExecDestroy(g.second);
+  if (aux_stream) {
+    hipStreamSynchronize(aux_stream);
+    hipStreamDestroy(aux_stream);
+  }
+  if (ev_fork) hipEventDestroy(ev_fork);
+  if (ev_join) hipEventDestroy(ev_join);
+  if (f2_descs) hipFree(f2_descs);
   if (cap_stream) hipStreamDestroy(cap_stream);
   if (vjp_buf) hipFree(vjp_buf);
   if (batch) sr::destroy_batch_state(batch);

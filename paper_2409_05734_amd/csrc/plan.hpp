@@ -66,6 +66,15 @@ struct sr_plan_s {
   sr::BatchState* batch = nullptr;  // batched-schedule state (built on first batched solve)
   size_t vjp_elems = 0;
 
+  // LDS-resident small-problem solver (fused2d.hip): device descriptors, their
+  // host staging copy, and a second stream (with fork/join events) so that it
+  // runs beside the batched level launches of the larger problems
+  void* f2_descs = nullptr;
+  size_t f2_desc_cap = 0;
+  std::vector<unsigned char> f2_host;
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
   int schedule = SR_SCHED_AUTO;
   hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
   std::vector<std::pair<std::string, hipGraphExec_t>> graphs;  // captured solver chunks (most recent last)
@@ -98,6 +107,17 @@ sr_status dense_forward(sr_plan_s* p, const float2* x, float2* z, float* y);
 sr_status dense_adjoint(sr_plan_s* p, const float2* r, float2* x);
 sr_status dense_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta, float* loss_trace);
 sr_status dense_spectral(sr_plan_s* p, const float* y, const float2* v0, int iters, float lam, float2* x0);
+
+// fused2d.hip (LDS-resident solves of small 2D problems, one workgroup each)
+bool fused2d_enabled();
+bool fused2d_supported(const Geo& g);
+sr_status fused2d_gd(sr_plan_s* p, const std::vector<int>& which, const float* y, float2* x, int iters,
+                     const float* eta, hipStream_t s);
+sr_status fused2d_spectral(sr_plan_s* p, const std::vector<int>& which, const float* y, const float2* v0, int iters,
+                           float lam, float2* x0, hipStream_t s);
+// fork the aux stream off the plan stream / join it back
+sr_status aux_fork(sr_plan_s* p);
+sr_status aux_join(sr_plan_s* p);
 
 // batched.hip (many problems advanced one pass level per launch)
 bool batched_supported(const sr_plan_s* p);

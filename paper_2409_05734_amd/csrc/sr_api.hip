@@ -703,7 +703,28 @@ sr_status sr_spectral_init(sr_plan p, const float* y, const void* v0, int32_t it
   const float2* vs = (const float2*)v0;
   float2* xs = (float2*)x0_out;
   if (p->kind == SR_DENSE) return dense_spectral(p, y, vs, iters, lambda, xs);
+  // batched plans: problems whose grid fits one workgroup's LDS run their
+  // whole iteration in the LDS-resident solver, beside the others' passes
+  const bool want_batched = p->schedule == SR_SCHED_BATCHED || (p->schedule == SR_SCHED_AUTO && p->geo.size() >= 8);
+  std::vector<char> resident(p->geo.size(), 0);
+  std::vector<int> small;
+  if (want_batched && p->geo.size() >= 2)
+    for (size_t i = 0; i < p->geo.size(); ++i)
+      if (fused2d_enabled() && fused2d_supported(p->geo[i])) {
+        resident[i] = 1;
+        small.push_back((int)i);
+      }
+  const bool forked = !small.empty() && small.size() < p->geo.size();
+  if (!small.empty()) {
+    hipStream_t s2 = p->stream;
+    if (forked) {
+      SR_CHECK(aux_fork(p));
+      s2 = p->aux_stream;
+    }
+    SR_CHECK(fused2d_spectral(p, small, y, vs, iters, lambda, xs, s2));
+  }
   for (size_t i = 0; i < p->geo.size(); ++i) {
+    if (resident[i]) continue;
     const Geo& g = p->geo[i];
     const float* yi = y + p->yoff[i];
     const float2* vi = vs + p->xoff[i];
@@ -764,6 +785,7 @@ sr_status sr_spectral_init(sr_plan p, const float* y, const void* v0, int32_t it
     // x0 = sqrt(sum(y)/(m c)) u / ||u||
     SR_CHECK(final_scale(p, xi, g.n, parts[iters & 1], npart, p->ysum, inv_mc));
   }
+  if (forked) SR_CHECK(aux_join(p));
   return SR_OK;
 }
 
