@@ -372,6 +372,39 @@ def autograd(torch, srpr, sr_inputs, dev):
             "grad_rel_diff_vs_loop": rel}
 
 
+def lds_resident(torch, srpr, sr_inputs, dev, count=512, iters=300):
+    """Many small 2D problems (64^2 grids, L = 2): the LDS-resident solver (one
+    workgroup per problem for the whole solve) against the level launches."""
+    rng = np.random.default_rng(7)
+    n_shape, m_shape, L = (32, 32), (64, 64), 2
+    probs = [srpr.Problem(n_shape, m_shape, L) for _ in range(count)]
+    theta = rng.uniform(0, 2 * np.pi, (count, L) + m_shape).astype(np.float32)
+    plan = srpr.Plan(probs, theta.ravel())
+    srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_BATCHED)
+    xs = torch.from_numpy(np.concatenate([sr_inputs.complex_gaussian(rng, n_shape).ravel() for _ in range(count)]))
+    xs = xs.to(dev)
+    y = torch.empty(plan.m_total, dtype=torch.float32, device=dev)
+    srpr.sr_forward(plan, xs, None, y)
+    x0 = (xs + 0.5 * torch.randn_like(xs)).contiguous()
+    eta = np.full(count, 0.2 * int(np.prod(m_shape)) / float(y.double().mean().item()), np.float32)
+    x = torch.empty_like(x0)
+    out = {"workload": f"{count} problems 32^2 -> 64^2, L=2, {iters} GD steps from x* + CN(0, 1/4)"}
+    finals = {}
+    for key, env in (("lds_resident_ms", "1"), ("levels_ms", "0")):
+        os.environ["SR_LDS_RESIDENT"] = env
+
+        def run():
+            x.copy_(x0)
+            srpr.sr_gd_solve(plan, y, x, iters, eta)
+        out[key] = _time_calls(torch, plan.stream, run, 3, warm=1)
+        finals[key] = x.clone()
+    os.environ.pop("SR_LDS_RESIDENT", None)
+    a, b = finals["lds_resident_ms"], finals["levels_ms"]
+    out["rel_diff_between_schedules"] = float(((a - b).abs().pow(2).sum() / b.abs().pow(2).sum()).sqrt())
+    out["speedup_vs_levels"] = out["levels_ms"] / out["lds_resident_ms"]
+    return out
+
+
 def tiny_1d(torch, srpr, sr_inputs, dev):
     d = sr_inputs.tiny_1d(0)
     plan = srpr.Plan([srpr.Problem(d["n_shape"], d["m_shape"], d["layers"])], d["theta"])
@@ -445,7 +478,7 @@ def main():
     if not args.quick:
         extras = {}
         for name, fn in (("large_2d", large_2d), ("dense_baseline", dense), ("batched", batched),
-                         ("autograd", autograd), ("tiny_1d", tiny_1d)):
+                         ("autograd", autograd), ("lds_resident_2d", lds_resident), ("tiny_1d", tiny_1d)):
             t0 = time.perf_counter()
             try:
                 extras[name] = fn(torch, srpr, sr_inputs, dev)
