@@ -405,6 +405,37 @@ def lds_resident(torch, srpr, sr_inputs, dev, count=512, iters=300):
     return out
 
 
+def forward_time_sweep(torch, srpr, sr_inputs, dev):
+    """Forward time per application at oversampling ratio 1 against image size,
+    structured (L = 2) and dense i.i.d. (the shape of the paper's forward-time
+    comparison; the dense matrix is drawn on the device)."""
+    rng = np.random.default_rng(11)
+    out = {"workload": "alpha = 1, one image per application; structured L = 2, dense i.i.d. CN(0,1)",
+           "structured": [], "dense": []}
+    for side in (32, 64, 128, 256, 512, 1024, 2048):
+        shape = (side, side)
+        theta = rng.uniform(0, 2 * np.pi, (2,) + shape).astype(np.float32)
+        plan = srpr.Plan([srpr.Problem(shape, shape, 2)], theta)
+        x = torch.from_numpy(sr_inputs.complex_gaussian(rng, shape).ravel()).to(dev)
+        z = torch.empty(side * side, dtype=torch.complex64, device=dev)
+        ms = _time_calls(torch, plan.stream, lambda: srpr.sr_forward(plan, x, z, None), 50)
+        out["structured"].append({"pixels": side * side, "forward_us": ms * 1e3})
+        del plan
+    g = torch.Generator(device=dev)
+    g.manual_seed(12)
+    for side in (32, 64, 128, 240):
+        n = side * side
+        A = torch.randn((n, n), dtype=torch.complex64, device=dev, generator=g)
+        plan = srpr.Plan([srpr.Problem((n,), (n,), 1, kind=srpr.SR_DENSE)], None, dense_A=A)
+        x = torch.randn(n, dtype=torch.complex64, device=dev, generator=g)
+        z = torch.empty(n, dtype=torch.complex64, device=dev)
+        ms = _time_calls(torch, plan.stream, lambda: srpr.sr_forward(plan, x, z, None), 5 if side >= 240 else 20)
+        out["dense"].append({"pixels": n, "forward_us": ms * 1e3, "matrix_GB": n * n * 8 / 1e9})
+        del plan, A
+        torch.cuda.empty_cache()
+    return out
+
+
 def tiny_1d(torch, srpr, sr_inputs, dev):
     d = sr_inputs.tiny_1d(0)
     plan = srpr.Plan([srpr.Problem(d["n_shape"], d["m_shape"], d["layers"])], d["theta"])
@@ -478,7 +509,8 @@ def main():
     if not args.quick:
         extras = {}
         for name, fn in (("large_2d", large_2d), ("dense_baseline", dense), ("batched", batched),
-                         ("autograd", autograd), ("lds_resident_2d", lds_resident), ("tiny_1d", tiny_1d)):
+                         ("autograd", autograd), ("lds_resident_2d", lds_resident), ("forward_time_sweep", forward_time_sweep),
+                         ("tiny_1d", tiny_1d)):
             t0 = time.perf_counter()
             try:
                 extras[name] = fn(torch, srpr, sr_inputs, dev)

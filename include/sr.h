@@ -3,14 +3,17 @@
  *
  * The library applies the structured sensing operator of Hu, Tachella, Unser
  * and Dong, "Structured Random Model for Fast and Robust Phase Retrieval"
- * (arXiv 2409.05734), section III, Eq. (5), oversampled case:
+ * (arXiv 2409.05734), section III, Eq. (5):
  *
- *     A = F D_L ... F D_1 U,      y = |A x|^2                       (Eq. (1))
+ *     A = S F D_L ... F D_1 U,    y = |A x|^2                       (Eq. (1))
  *
- * U zero-pads the signal (n = N1*N2 entries) into the centred window of an
- * m = M1*M2 grid (offset floor((M-N)/2) per axis), D_l = diag(exp(i theta_l))
- * are the random phase diagonals and F is the unitary DFT (1D, or the
- * separable 2D DFT for images).  On top of A and A^H it runs the paper's two
+ * The transforms run on a grid of G_k = max(N_k, M_k) points per axis.  U
+ * zero-pads the signal (n = N1*N2 entries) into the centred window of the
+ * grid (oversampling, M > N), S keeps the centred M1 x M2 window of it
+ * (undersampling, M < N; the identity when M = G), both at offset
+ * floor((G-N)/2) resp. floor((G-M)/2) per axis.  D_l = diag(exp(i theta_l))
+ * are the random phase diagonals on the grid and F is the unitary DFT (1D,
+ * or the separable 2D DFT for images).  On top of A and A^H it runs the paper's two
  * solvers: the spectral initialisation (shifted power iteration on
  * A^H diag(T(y)) A, section II-B.2, Eq. (3)-(4)) and gradient descent on the
  * l2 intensity loss (section II-B.1, Eq. (2)), and it also provides the dense
@@ -67,11 +70,13 @@ typedef enum {
 /* One phase-retrieval problem.
  *  ndim      1 (vector) or 2 (image)
  *  n[0..1]   signal shape N1 (, N2); n[1] ignored for ndim == 1
- *  m[0..1]   measurement shape M1 (, M2) with M_k >= N_k (oversampling alpha = m/n >= 1)
+ *  m[0..1]   measurement shape M1 (, M2); per axis M >= N pads the signal
+ *            (oversampling) and M < N trims the transformed grid (undersampling)
  *  layers    L >= 1 phase layers (structured only)
  *  kind      sr_kind; all problems of a plan have the same kind
- *  theta_offset  offset, in floats, of this problem's L*m phases inside the
- *            plan's theta buffer (problems may share a set of phases)        */
+ *  theta_offset  offset, in floats, of this problem's L phase grids (L*g
+ *            floats, g = G1*G2 grid points) inside the plan's theta buffer
+ *            (problems may share a set of phases)                            */
 typedef struct {
   int32_t ndim;
   int32_t n[2];
@@ -84,18 +89,19 @@ typedef struct {
 /* Create a plan for nprob problems.
  *  probs        host array of nprob problem descriptors
  *  theta_host   host, theta_len floats: phases theta_l of every problem, each
- *               problem's block is L consecutive m-grids (layer-major, row-major
- *               grid) starting at probs[p].theta_offset.  Copied into the plan.
+ *               problem's block is L consecutive G1 x G2 grids (layer-major,
+ *               row-major grid) starting at probs[p].theta_offset.  Copied into
+ *               the plan.
  *               Must be NULL (theta_len 0) for SR_DENSE plans.
  *  dense_A      SR_DENSE only: device pointer to the m x n complex64 matrix,
  *               row-major, shared by all problems of the plan (all problems
  *               must then have the same shape); the caller keeps it alive
  *               until sr_plan_destroy.  NULL for SR_STRUCTURED.
  *  hip_stream   hipStream_t to order all work on (NULL = default stream)
- * FFT lengths along each grid axis must be one of 16, 32, 64, 96, 128, 192,
- * 256, 384, 512, 768, 1024, 2048 (2D), or one of those or 4096 with
- * L*m <= 4096 (1D).  Dense problems need an even signal length n;
- * otherwise SR_E_UNSUPPORTED.  Allocates the plan's device workspace.     */
+ * Grid lengths G_k must be one of 16, 32, 64, 96, 128, 192, 256, 384, 512,
+ * 768, 1024, 2048 (2D), or one of those or 4096 with L*G <= 4096 (1D).
+ * Dense problems (any m, n) need an even signal length n; otherwise
+ * SR_E_UNSUPPORTED.  Allocates the plan's device workspace.                 */
 sr_status sr_plan_create(sr_plan* out, const sr_problem* probs, int32_t nprob, const float* theta_host,
                          int64_t theta_len, const void* dense_A, void* hip_stream);
 
@@ -133,7 +139,8 @@ sr_status sr_adjoint(sr_plan plan, const void* r, void* x_out);
 /* Spectral initialisation (section II-B.2, Eq. (3)-(4)).  With y~ = y/mean(y),
  * T(y~) = max(1 - 1/y~, lambda) (T = lambda where y = 0), the shifted power
  * iteration v <- B v / ||B v||, B = A^H diag(T) A / (m c) - 2 lambda I, with
- * c = 1/m for SR_STRUCTURED and c = 1 for SR_DENSE, runs `iters` times from
+ * m the number of measurements and c the mean squared entry of A (1/g for
+ * SR_STRUCTURED, g = G1*G2 grid points; 1 for SR_DENSE), runs `iters` times from
  * v0/||v0||; x0_out = sqrt(sum(y)/(m c)) * v_iters.
  *  y       float, measurements (y_off layout)
  *  v0      complex64 start vectors (x_off layout), not modified

@@ -23,6 +23,10 @@ the project's design notes):
       sqrt(sum(y) / (m c)).
 * R6  D_1 acts first, right after the zero padding U.
 * R7  Zero padding is centred: offset floor((M - N)/2) per axis.
+* R14 Undersampling (alpha <= 1, A = S prod(F D_i)): the transforms run on
+      the signal's grid and S keeps the centred measurement window, offset
+      floor((N - M)/2) per axis; in general the grid is max(N, M) per axis,
+      U pads into it and S trims it, and c = 1 / (grid size).
 
 Parity pins for every function live in the CPU test-suite (library DFT,
 brute-force dense products, closed forms, invariants, eigendecomposition,
@@ -94,32 +98,37 @@ def phase_diagonal(theta_l: np.ndarray) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
-# The structured sensing operator, Eq. (5) for alpha > 1
+# The structured sensing operator, Eq. (5)
 # ----------------------------------------------------------------------------
 
-def forward(x: np.ndarray, thetas: np.ndarray) -> np.ndarray:
-    """A x = F D_L ... F D_1 U x   (Eq. (5), oversampled case; reading R6).
+def forward(x: np.ndarray, thetas: np.ndarray, m_shape=None) -> np.ndarray:
+    """A x = S F D_L ... F D_1 U x   (Eq. (5); readings R6, R7, R14).
 
-    x: complex signal of shape n_shape; thetas: (L, *m_shape) phases.
+    x: complex signal of shape n_shape; thetas: (L, *grid) phases on the
+    transform grid (max(n, m) per axis).  U pads x into the grid, S keeps the
+    centred m_shape window (default: the whole grid, i.e. alpha >= 1).
     Returns z = A x of shape m_shape (complex128).
     """
     thetas = np.asarray(thetas, dtype=np.float64)
-    Z = zero_pad(np.asarray(x, dtype=np.complex128), thetas.shape[1:])
+    grid = thetas.shape[1:]
+    Z = zero_pad(np.asarray(x, dtype=np.complex128), grid)
     for th in thetas:
         Z = apply_dft(phase_diagonal(th) * Z)
-    return Z
+    return Z if m_shape is None else crop(Z, tuple(m_shape))
 
 
 def adjoint(r: np.ndarray, thetas: np.ndarray, n_shape) -> np.ndarray:
-    """A^H r = U^H D_1^* F^H ... D_L^* F^H r   (adjoint of Eq. (5))."""
+    """A^H r = U^H D_1^* F^H ... D_L^* F^H S^H r   (adjoint of Eq. (5)).
+
+    r has the measurement shape; S^H embeds it in the grid with zeros."""
     thetas = np.asarray(thetas, dtype=np.float64)
-    V = np.asarray(r, dtype=np.complex128)
+    V = zero_pad(np.asarray(r, dtype=np.complex128), thetas.shape[1:])
     for th in thetas[::-1]:
         V = np.conj(phase_diagonal(th)) * apply_dft(V, inverse=True)
     return crop(V, n_shape)
 
 
-def dense_matrix(thetas: np.ndarray, n_shape) -> np.ndarray:
+def dense_matrix(thetas: np.ndarray, n_shape, m_shape=None) -> np.ndarray:
     """Explicit m x n matrix of the structured operator, one column per unit
     vector e_j (row-major vectorisation).  Tiny sizes only (brute force)."""
     thetas = np.asarray(thetas, dtype=np.float64)
@@ -128,13 +137,13 @@ def dense_matrix(thetas: np.ndarray, n_shape) -> np.ndarray:
     for j in range(n):
         e = np.zeros(n, dtype=np.complex128)
         e[j] = 1.0
-        cols.append(forward(e.reshape(n_shape), thetas).ravel())
+        cols.append(forward(e.reshape(n_shape), thetas, m_shape).ravel())
     return np.stack(cols, axis=1)
 
 
-def measurements(x: np.ndarray, thetas: np.ndarray) -> np.ndarray:
+def measurements(x: np.ndarray, thetas: np.ndarray, m_shape=None) -> np.ndarray:
     """Noiseless intensities y = |A x|^2   (Eq. (1))."""
-    return np.abs(forward(x, thetas)) ** 2
+    return np.abs(forward(x, thetas, m_shape)) ** 2
 
 
 # ----------------------------------------------------------------------------
@@ -142,18 +151,21 @@ def measurements(x: np.ndarray, thetas: np.ndarray) -> np.ndarray:
 # ----------------------------------------------------------------------------
 
 class StructuredOperator:
-    """A of Eq. (5) (alpha > 1) with its adjoint; mean squared entry c = 1/m."""
+    """A of Eq. (5) with its adjoint; m = number of measurements, mean squared
+    entry c = 1/g with g the grid size (reading R14): the rows (alpha <= 1) or
+    columns (alpha >= 1) of A are orthonormal."""
 
-    def __init__(self, thetas, n_shape):
+    def __init__(self, thetas, n_shape, m_shape=None):
         self.thetas = np.asarray(thetas, dtype=np.float64)
         self.n_shape = tuple(n_shape)
-        self.m_shape = tuple(self.thetas.shape[1:])
+        self.grid_shape = tuple(self.thetas.shape[1:])
+        self.m_shape = self.grid_shape if m_shape is None else tuple(m_shape)
         self.m = int(np.prod(self.m_shape))
         self.n = int(np.prod(self.n_shape))
-        self.c = 1.0 / self.m  # columns of A are orthonormal: sum_i |A_ij|^2 = 1
+        self.c = 1.0 / int(np.prod(self.grid_shape))
 
     def A(self, x):
-        return forward(x, self.thetas)
+        return forward(x, self.thetas, self.m_shape)
 
     def AH(self, r):
         return adjoint(r, self.thetas, self.n_shape)
@@ -315,7 +327,7 @@ def forward_vjp(x, thetas, gz):
         u = phase_diagonal(th) * w
         us.append(u)
         w = apply_dft(u)
-    wbar = np.asarray(gz, dtype=np.complex128)
+    wbar = zero_pad(np.asarray(gz, dtype=np.complex128), thetas.shape[1:])  # S^H gz
     gth = np.zeros_like(thetas)
     for l in range(len(thetas) - 1, -1, -1):
         ubar = apply_dft(wbar, inverse=True)
@@ -324,7 +336,7 @@ def forward_vjp(x, thetas, gz):
     return crop(wbar, n_shape), gth
 
 
-def adjoint_vjp(r, thetas, n_shape, gv):
+def adjoint_vjp(r, thetas, n_shape, gv, m_shape=None):
     """Cotangents of v = A^H r: returns (gr, gtheta) for cotangent gv of v.
 
     Intermediates: s_L = r, t_l = F^H s_l, q_l = D_l^* t_l, s_{l-1} = q_l,
@@ -332,7 +344,7 @@ def adjoint_vjp(r, thetas, n_shape, gv):
     thetabar_l = Im(conj(qbar_l) * q_l), sbar_l = F D_l qbar_l, gr = sbar_L.
     """
     thetas = np.asarray(thetas, dtype=np.float64)
-    s = np.asarray(r, dtype=np.complex128)
+    s = zero_pad(np.asarray(r, dtype=np.complex128), thetas.shape[1:])  # S^H r
     qs = [None] * len(thetas)
     for l in range(len(thetas) - 1, -1, -1):
         q = np.conj(phase_diagonal(thetas[l])) * apply_dft(s, inverse=True)
@@ -343,7 +355,7 @@ def adjoint_vjp(r, thetas, n_shape, gv):
     for l in range(len(thetas)):
         gth[l] = np.imag(np.conj(sbar) * qs[l])
         sbar = apply_dft(phase_diagonal(thetas[l]) * sbar)
-    return sbar, gth
+    return (sbar if m_shape is None else crop(sbar, tuple(m_shape))), gth
 
 
 def unrolled_gd_loss(thetas, x_star, x0, steps: int, mu: float) -> float:

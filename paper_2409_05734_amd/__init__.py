@@ -29,10 +29,13 @@ __all__ = [
 
 @dataclass
 class Problem:
-    """Signal shape n_shape zero-padded into measurement grid m_shape, L layers.
+    """Signal shape n_shape, measurement shape m_shape, L layers.
 
-    theta_offset: float offset of this problem's L*m phases in the plan's
-    theta buffer (None: packed after the previous problem's block)."""
+    The transforms run on a grid of max(n, m) points per axis: the signal is
+    zero-padded into it where m > n, the measurements are its centred window
+    where m < n.  theta_offset: float offset of this problem's L phase grids
+    in the plan's theta buffer (None: packed after the previous problem's
+    block)."""
     n_shape: tuple
     m_shape: tuple
     layers: int = 2
@@ -46,6 +49,14 @@ class Problem:
     @property
     def m(self) -> int:
         return int(np.prod(self.m_shape))
+
+    @property
+    def grid_shape(self) -> tuple:
+        return tuple(max(a, b) for a, b in zip(self.n_shape, self.m_shape))
+
+    @property
+    def grid(self) -> int:
+        return int(np.prod(self.grid_shape))
 
 
 def _torch():
@@ -97,7 +108,7 @@ class Plan:
             q.kind = int(p.kind)
             if kind == SR_STRUCTURED:
                 q.theta_offset = int(off if p.theta_offset is None else p.theta_offset)
-                off = q.theta_offset + p.layers * p.m
+                off = q.theta_offset + p.layers * p.grid
             else:
                 q.theta_offset = 0
         self._theta_host = None

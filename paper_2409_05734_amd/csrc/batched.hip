@@ -228,7 +228,7 @@ static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const fl
     st = new BatchState();
     p->batch = st;
     size_t elems = 0;
-    for (const Geo& g : p->geo) elems += 2 * (size_t)g.m;
+    for (const Geo& g : p->geo) elems += 2 * (size_t)g.mg;
     hipError_t e = hipMalloc(&st->bufs, elems * sizeof(float2));
     if (e != hipSuccess) {
       st->bufs = nullptr;
@@ -245,8 +245,8 @@ static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const fl
   for (size_t i = 0; i < np && status == SR_OK; ++i) {
     const Geo& g = p->geo[i];
     p->bufA = st->bufs + off;  // each problem's private ping-pong buffers
-    p->bufB = st->bufs + off + g.m;
-    off += 2 * (size_t)g.m;
+    p->bufB = st->bufs + off + g.mg;
+    off += 2 * (size_t)g.mg;
     if (lds_resident(g)) continue;  // solved by the LDS-resident kernel
     const float* yi = y + p->yoff[i];
     float2* xi = x + p->xoff[i];

@@ -44,6 +44,7 @@ constexpr int BK = 64;    // reduction chunk
 constexpr int PADK = BK + 4;
 constexpr int NT = 256;   // 4 waves, 2 x 2 wave tiles of 32 x 32
 constexpr int kTargetGroups = 1024;
+constexpr int kMaxSplit = 8;  // the epilogue sums at most this many partial tiles
 
 enum Epi : int {
   E1_STORE = 0,  // after A X: z and/or |z|^2
@@ -262,10 +263,14 @@ __global__ void __launch_bounds__(NT) dense_epi1_kernel(const DenseArgs a) {
       const int gi = i0 + il;
       float2 z = make_float2(0.f, 0.f);
       if (gi < a.m) {
-        for (int s = 0; s < a.S; ++s) {
-          const float2 c = *reinterpret_cast<const float2*>(&a.split[((long long)s * a.m + gi) * a.q_ld + 2 * (p0 + pl)]);
-          z.x += c.x;
-          z.y += c.y;
+#pragma unroll
+        for (int s = 0; s < kMaxSplit; ++s) {
+          if (s < a.S) {
+            const float2 c =
+                *reinterpret_cast<const float2*>(&a.split[((long long)s * a.m + gi) * a.q_ld + 2 * (p0 + pl)]);
+            z.x += c.x;
+            z.y += c.y;
+          }
         }
       }
       zs[il][pl] = z;
@@ -333,13 +338,17 @@ __global__ void __launch_bounds__(NT) dense_epi2_kernel(const DenseArgs a) {
       const int gk = kb + q;
       if (gk >= a.n) break;
       float2 re = make_float2(0.f, 0.f), im = make_float2(0.f, 0.f);  // (P[2k][2p], P[2k+1][2p]), (.., 2p+1)
-      for (int s = 0; s < a.S; ++s) {
-        const float2 u = *reinterpret_cast<const float2*>(&a.split[((long long)s * a.q_ld + 2 * p) * J + 2 * gk]);
-        const float2 v = *reinterpret_cast<const float2*>(&a.split[((long long)s * a.q_ld + 2 * p + 1) * J + 2 * gk]);
-        re.x += u.x;
-        re.y += u.y;
-        im.x += v.x;
-        im.y += v.y;
+#pragma unroll
+      for (int s = 0; s < kMaxSplit; ++s) {
+        if (s < a.S) {
+          const float2 u = *reinterpret_cast<const float2*>(&a.split[((long long)s * a.q_ld + 2 * p) * J + 2 * gk]);
+          const float2 v =
+              *reinterpret_cast<const float2*>(&a.split[((long long)s * a.q_ld + 2 * p + 1) * J + 2 * gk]);
+          re.x += u.x;
+          re.y += u.y;
+          im.x += v.x;
+          im.y += v.y;
+        }
       }
       const float2 gv = make_float2(re.x + im.y, im.x - re.y);
       const long long o = (long long)p * a.n + gk;
@@ -436,7 +445,7 @@ __global__ void dense_final_scale_kernel(float2* x, int n, int nb, const double*
 // split a whole number of BK chunks.
 void plan_split(int tiles, int K, int* S, int* kchunk) {
   const int chunks = (K + BK - 1) / BK;
-  int want = std::max(1, std::min(chunks, (kTargetGroups + tiles - 1) / tiles));
+  int want = std::max(1, std::min(std::min(chunks, kMaxSplit), (kTargetGroups + tiles - 1) / tiles));
   const int per = (chunks + want - 1) / want;
   *kchunk = per * BK;
   *S = (chunks + per - 1) / per;

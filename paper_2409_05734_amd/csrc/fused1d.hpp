@@ -3,8 +3,9 @@
 // application, or every iteration of a GD / spectral solve, runs in a single
 // launch with no global-memory round trip between layers or iterations.
 //
-// 1D operator (section III, Eq. (5), oversampled case):
-//   A x = F D_L ... F D_1 U x with F the unitary m-point DFT.
+// 1D operator (section III, Eq. (5)): A x = S F D_L ... F D_1 U x with F the
+// unitary DFT on a grid of max(n, m) points, U the centred zero padding
+// (m > n) and S the centred trimming to the m measurements (m < n).
 #pragma once
 #include "fft_core.hpp"
 
@@ -16,7 +17,8 @@ constexpr int kFused1DPhaseSlots = 4096;
 enum Fused1DOp : int { F1_FORWARD = 0, F1_ADJOINT = 1, F1_GD = 2, F1_SPECTRAL = 3, F1_FWD_VJP = 4, F1_ADJ_VJP = 5 };
 
 struct Fused1DArgs {
-  int n, m, L, off;          // signal length, measurement length, layers, pad offset
+  int n, m, L, off;          // signal length, grid length, layers, pad offset
+  int mw, moff;              // measurement window [moff, moff + mw) of the grid
   const float* theta;        // L*m phases
   const float2* tw;          // exp(-2 pi i e/m), e = 0..m-1
   const float2* x_in;        // forward: x; spectral: v0
@@ -52,6 +54,7 @@ __global__ void __launch_bounds__((Tile<N, 1, false>::THREADS)) fused1d_kernel(c
   __syncthreads();
 
   auto in_window = [&](int k) { return k >= a.off && k < a.off + a.n; };
+  auto in_meas = [&](int k) { return k >= a.moff && k < a.moff + a.mw; };  // measurement window
   typename T::Twiddles w;
   T::load_twiddles(w, a.tw, t);
   int ph = 0;
@@ -86,12 +89,16 @@ __global__ void __launch_bounds__((Tile<N, 1, false>::THREADS)) fused1d_kernel(c
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int k = T::elem(t, j);
-      if (a.z_out) a.z_out[k] = v[j];
-      if (a.y_out) a.y_out[k] = cabs2(v[j]);
+      if (!in_meas(k)) continue;
+      if (a.z_out) a.z_out[k - a.moff] = v[j];
+      if (a.y_out) a.y_out[k - a.moff] = cabs2(v[j]);
     }
   } else if constexpr (OP == F1_ADJOINT) {
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = a.r_in[T::elem(t, j)];
+    for (int j = 0; j < E; ++j) {
+      const int k = T::elem(t, j);
+      v[j] = in_meas(k) ? a.r_in[k - a.moff] : make_float2(0.f, 0.f);
+    }
     adjoint_layers();
 #pragma unroll
     for (int j = 0; j < E; ++j) {
@@ -105,7 +112,7 @@ __global__ void __launch_bounds__((Tile<N, 1, false>::THREADS)) fused1d_kernel(c
     for (int j = 0; j < E; ++j) {
       const int k = T::elem(t, j);
       x[j] = in_window(k) ? a.x_out[k - a.off] : make_float2(0.f, 0.f);
-      yv[j] = a.y[k];
+      yv[j] = in_meas(k) ? a.y[k - a.moff] : 0.f;
     }
     for (int it = 0; it < a.iters; ++it) {
 #pragma unroll
@@ -114,7 +121,7 @@ __global__ void __launch_bounds__((Tile<N, 1, false>::THREADS)) fused1d_kernel(c
       float acc = 0.f;
 #pragma unroll
       for (int j = 0; j < E; ++j) {
-        float d = cabs2(v[j]) - yv[j];
+        const float d = in_meas(T::elem(t, j)) ? cabs2(v[j]) - yv[j] : 0.f;  // zero outside the window
         acc += d * d;
         v[j] = cscale(v[j], d);
       }
@@ -154,7 +161,10 @@ __global__ void __launch_bounds__((Tile<N, 1, false>::THREADS)) fused1d_kernel(c
       for (int j = 0; j < E; ++j) v[j] = cscale(v[j], s);
     }
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = a.r_in[T::elem(t, j)];
+    for (int j = 0; j < E; ++j) {
+      const int k = T::elem(t, j);
+      v[j] = in_meas(k) ? a.r_in[k - a.moff] : make_float2(0.f, 0.f);
+    }
     for (int l = L - 1; l >= 0; --l) {
       T::template fft<true>(v, lds, ph, w, t, 0);
 #pragma unroll
@@ -177,7 +187,10 @@ __global__ void __launch_bounds__((Tile<N, 1, false>::THREADS)) fused1d_kernel(c
     // r_in = r, x_in = cotangent of A^H r; z_out = A gv (nullable); gth += dtheta
     __shared__ float2 sv[kFused1DPhaseSlots];  // q_l = D_l^* F^H s_l
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = a.r_in[T::elem(t, j)];
+    for (int j = 0; j < E; ++j) {
+      const int k = T::elem(t, j);
+      v[j] = in_meas(k) ? a.r_in[k - a.moff] : make_float2(0.f, 0.f);
+    }
     for (int l = L - 1; l >= 0; --l) {
       T::template fft<true>(v, lds, ph, w, t, 0);
 #pragma unroll
@@ -206,7 +219,10 @@ __global__ void __launch_bounds__((Tile<N, 1, false>::THREADS)) fused1d_kernel(c
     }
     if (a.z_out) {
 #pragma unroll
-      for (int j = 0; j < E; ++j) a.z_out[T::elem(t, j)] = v[j];
+      for (int j = 0; j < E; ++j) {
+        const int k = T::elem(t, j);
+        if (in_meas(k)) a.z_out[k - a.moff] = v[j];
+      }
     }
   } else {  // F1_SPECTRAL
     float yv[E];
@@ -215,18 +231,18 @@ __global__ void __launch_bounds__((Tile<N, 1, false>::THREADS)) fused1d_kernel(c
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int k = T::elem(t, j);
-      yv[j] = a.y[k];
+      yv[j] = in_meas(k) ? a.y[k - a.moff] : 0.f;
       ys += yv[j];
       u[j] = in_window(k) ? a.x_in[k - a.off] : make_float2(0.f, 0.f);
       un += cabs2(u[j]);
     }
     const float ysum = block_sum<NT>(ys, red);
-    const float ybar = ysum / (float)N;
+    const float ybar = ysum / (float)a.mw;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       float w = a.lam;
       if (yv[j] > 0.f) w = fmaxf(1.f - ybar / yv[j], a.lam);
-      yv[j] = w;  // yv now holds T(y)
+      yv[j] = in_meas(T::elem(t, j)) ? w : 0.f;  // yv now holds T(y), zero outside the window
     }
     float inv = rsqrtf(block_sum<NT>(un, red));
     for (int it = 0; it < a.iters; ++it) {

@@ -402,7 +402,9 @@ bool fused2d_enabled() {
   return e != nullptr && std::atoi(e) != 0;
 }
 
-bool fused2d_supported(const Geo& g) { return g.ndim == 2 && g.L >= 1 && f2_shape_fits(g.M1, g.M2); }
+bool fused2d_supported(const Geo& g) {
+  return g.ndim == 2 && g.L >= 1 && !g.cropped() && f2_shape_fits(g.M1, g.M2);
+}
 
 static sr_status f2_launch(sr_plan_s* p, const std::vector<F2Desc>& descs, size_t lds, hipStream_t s) {
   if (descs.empty()) return SR_OK;
@@ -450,7 +452,7 @@ static F2Desc f2_desc(const sr_plan_s* p, size_t i, int op, const float* y, floa
   d.x = x + p->xoff[i];
   d.tw0 = p->twiddles(g.M1, 0);
   d.tw1 = p->twiddles(g.M2, 0);
-  d.inv_m = 1.f / (float)g.m;
+  d.inv_m = 1.f / (float)g.m;  // (not cropped: m is the grid size)
   d.iters = iters;
   d.op = op;
   return d;

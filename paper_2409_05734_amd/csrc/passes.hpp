@@ -90,6 +90,13 @@ struct PassArgs {
   const float2* xin;     // POST_PHASE_CONJ_GT: the signal x (crop layout = output layout)
   float2* out2;          // POST_*_FWD: compact output of the fused forward transform
   long long out2_ld;
+  // measurement window: grid rows [win_lo0, win_hi0) x columns [win_lo1,
+  // win_hi1), stored row-major with row length win_ld.  y, z_out, y_out (and
+  // the input when in_window is set) live on the window; the residual and
+  // the spectral weight are zero outside it.
+  int win_lo0, win_hi0, win_lo1, win_hi1;
+  long long win_ld;
+  int in_window;
 };
 
 // 1/sqrt of the sum of the previous iterate's squared-norm partials: strided
@@ -142,6 +149,16 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   auto out_addr = [&](int k) -> int { return COL ? (k - a.out_lo) * old + b : b * old + (k - a.out_lo); };
   auto in_win = [&](int k) { return active && k >= a.in_lo && k < a.in_hi; };
   auto out_win = [&](int k) { return active && k >= a.out_lo && k < a.out_hi; };
+  // measurement window: membership and index of grid element k of this transform
+  const int wld = (int)a.win_ld;
+  auto m_in = [&](int k) {
+    const int r = COL ? k : gb, c = COL ? gb : k;
+    return active && r >= a.win_lo0 && r < a.win_hi0 && c >= a.win_lo1 && c < a.win_hi1;
+  };
+  auto m_idx = [&](int k) -> int {
+    const int r = COL ? k : gb, c = COL ? gb : k;
+    return (r - a.win_lo0) * wld + (c - a.win_lo1);
+  };
 
   // ---- issue every global load
   float2 v[E];
@@ -167,7 +184,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
     const int k = T::elem(t, j);
     const bool iw = in_win(k);
     const int g = gidx(k);
-    v[j] = ld2(r_in, off8(iw, in_addr(k)));
+    v[j] = a.in_window ? ld2(r_in, off8(m_in(k), m_idx(k))) : ld2(r_in, off8(iw, in_addr(k)));
     if constexpr (PRE == PRE_PHASE) {
       if constexpr (TAB) dp[j] = ld2(r_pre, off8(iw, g));
       else dp[j].x = ld1(r_pre, off4(iw, g));
@@ -176,7 +193,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
       if constexpr (TAB) dm[j] = ld2(r_mid, off8(active, g));
       else dm[j].x = ld1(r_mid, off4(active, g));
     }
-    if constexpr (MID_Y) yv[j] = ld1(r_y, off4(active, g));
+    if constexpr (MID_Y) yv[j] = ld1(r_y, off4(m_in(k), m_idx(k)));
     if constexpr (MID_SAVED) {
       sv[j] = ld2(r_save, off8(active, g));
       gt[j] = ld1(r_gth, off4(active, g));
@@ -252,9 +269,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   } else if constexpr (MID == MID_GD) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
+      const bool in = m_in(T::elem(t, j));
       float2 z = cscale(v[j], a.scale_mid);
-      float d = cabs2(z) - yv[j];
-      acc += active ? d * d : 0.f;
+      float d = in ? cabs2(z) - yv[j] : 0.f;  // zero residual outside the measurement window
+      acc += d * d;
       v[j] = cscale(z, d);
     }
   } else if constexpr (MID == MID_SPEC) {
@@ -264,7 +282,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
       float2 z = cscale(v[j], a.scale_mid);
       float wgt = a.lam;
       if (yv[j] > 0.f) wgt = fmaxf(1.f - ybar / yv[j], a.lam);
-      v[j] = cscale(z, wgt);
+      v[j] = cscale(z, m_in(T::elem(t, j)) ? wgt : 0.f);
     }
   } else if constexpr (MID == MID_STORE) {
     const Rsrc r_z = rsrc(a.z_out), r_yo = rsrc(a.y_out);
@@ -272,8 +290,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
     for (int j = 0; j < E; ++j) {
       const int k = T::elem(t, j);
       float2 z = cscale(v[j], a.scale_mid);
-      if (a.z_out) st2(r_z, off8(active, gidx(k)), z);
-      if (a.y_out) st1(r_yo, off4(active, gidx(k)), cabs2(z));
+      if (a.z_out) st2(r_z, off8(m_in(k), m_idx(k)), z);
+      if (a.y_out) st1(r_yo, off4(m_in(k), m_idx(k)), cabs2(z));
     }
   }
 

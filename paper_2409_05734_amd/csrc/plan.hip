@@ -68,8 +68,10 @@ sr_status sr_plan_s::init(const float* theta_host) {
   std::set<int> lens;
   int64_t max_m = 0;
   int cap = 1;
+  int64_t max_grid = 0;
   for (const Geo& g : geo) {
     max_m = std::max(max_m, g.m);
+    max_grid = std::max(max_grid, g.mg);
     if (kind != SR_STRUCTURED) continue;
     lens.insert(g.M1);
     if (g.ndim == 2) lens.insert(g.M2);
@@ -89,7 +91,7 @@ sr_status sr_plan_s::init(const float* theta_host) {
   // partial sums: one per workgroup of any pass (at most one per transform)
   for (const Geo& g : geo) cap = std::max<int>(cap, (int)std::max(g.M1, g.M2) + 1);
   part_cap = std::max(cap, 64);
-  int64_t grid_elems = (kind == SR_DENSE) ? (int64_t)max_m * (int64_t)np : max_m;
+  int64_t grid_elems = (kind == SR_DENSE) ? (int64_t)max_m * (int64_t)np : max_grid;
   size_t b_theta = align256(sizeof(float) * (size_t)std::max<int64_t>(theta_len, 0));
   size_t b_eph = align256(sizeof(float2) * (size_t)std::max<int64_t>(theta_len, 0));
   size_t b_tw = align256(sizeof(float2) * tw_elems);

@@ -11,16 +11,23 @@
 
 namespace sr {
 
-// Geometry of one problem.  2D: signal N1 x N2 zero-padded into the centred
-// window (offsets o1, o2) of an M1 x M2 grid.  1D problems use N1, M1, o1 and
-// N2 = M2 = 1.
+// Geometry of one problem.  The transforms run on an M1 x M2 grid with
+// M_k = max(N_k, W_k) per axis: the N1 x N2 signal is zero-padded into the
+// centred window at (o1, o2) (oversampling, U) and the W1 x W2 measurements
+// are the centred window at (c1, c2) (undersampling, S; the whole grid when
+// W = M).  1D problems use the first axis only (N2 = M2 = W2 = 1).
 struct Geo {
   int ndim = 0;
   int N1 = 1, N2 = 1, M1 = 1, M2 = 1;
   int o1 = 0, o2 = 0;
+  int W1 = 1, W2 = 1;
+  int c1 = 0, c2 = 0;
   int L = 0;
-  int64_t n = 0, m = 0;
+  int64_t n = 0;   // signal entries
+  int64_t m = 0;   // measurements (W1 W2)
+  int64_t mg = 0;  // grid entries (M1 M2); the phases of one layer
   int64_t th_off = 0;
+  bool cropped() const { return W1 != M1 || W2 != M2; }
 };
 
 sr_status fail(sr_status s, const std::string& msg);

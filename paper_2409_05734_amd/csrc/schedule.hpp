@@ -31,6 +31,11 @@ inline PassArgs base_args(const sr_plan_s* p, const Geo& g, int k) {
   a.scale_mid = 1.f;
   a.scale_out = 1.f;
   a.inv_m = 1.f / (float)g.m;
+  a.win_lo0 = g.c1;
+  a.win_hi0 = g.c1 + g.W1;
+  a.win_lo1 = g.c2;
+  a.win_hi1 = g.c2 + g.W2;
+  a.win_ld = g.W2;
   return a;
 }
 

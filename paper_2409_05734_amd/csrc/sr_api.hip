@@ -72,7 +72,7 @@ using namespace sr;
     if (s_ != SR_OK) return s_;       \
   } while (0)
 
-const float* sr_plan_s::theta_l(const Geo& g, int l) const { return theta + g.th_off + (int64_t)(l - 1) * g.m; }
+const float* sr_plan_s::theta_l(const Geo& g, int l) const { return theta + g.th_off + (int64_t)(l - 1) * g.mg; }
 
 // Pass 1, [U, D_1, F_0] on the support columns of x, into the compact bufA.
 static sr_status first_pass(sr_plan_s* p, const Geo& g, const float2* x, float in_scale, const float* part_in,
@@ -203,6 +203,7 @@ static sr_status adjoint_2d(sr_plan_s* p, const Geo& g, const float2* r, float2*
   const int k = g.L + 1;
   PassArgs a = base_args(p, g, k);
   in_full(a, g, k, r);
+  a.in_window = 1;  // r lives on the measurement window
   set_out(a, g, k, p->bufA);
   a.scale_out = 1.f / std::sqrt((float)pass_len(g, k));
   SR_CHECK(launch(p, g, k, PK_FIRST_ADJ, a));
@@ -452,6 +453,8 @@ static sr_status fused_1d(sr_plan_s* p, const Geo& g, int op, Fused1DArgs a) {
   a.m = g.M1;
   a.L = g.L;
   a.off = g.o1;
+  a.mw = g.W1;
+  a.moff = g.c1;
   a.theta = p->theta_l(g, 1);
   a.tw = p->twiddles(g.M1);
   hipError_t e = launch_fused1d(g.M1, op, a, p->stream);
@@ -495,20 +498,26 @@ sr_status sr_plan_create(sr_plan* out, const sr_problem* probs, int32_t nprob, c
     if (q.ndim != 1 && q.ndim != 2) return fail(SR_E_ARG, "ndim must be 1 or 2");
     g.ndim = q.ndim;
     g.N1 = q.n[0];
-    g.M1 = q.m[0];
+    g.W1 = q.m[0];
     g.N2 = q.ndim == 2 ? q.n[1] : 1;
-    g.M2 = q.ndim == 2 ? q.m[1] : 1;
+    g.W2 = q.ndim == 2 ? q.m[1] : 1;
     if (g.N1 < 1 || g.N2 < 1) return fail(SR_E_SHAPE, "signal sizes must be positive");
-    if (g.M1 < g.N1 || g.M2 < g.N2) return fail(SR_E_SHAPE, "measurement grid smaller than the signal (alpha < 1)");
+    if (g.W1 < 1 || g.W2 < 1) return fail(SR_E_SHAPE, "measurement sizes must be positive");
+    // transform grid: zero padding for M > N (U), centred trimming for M < N (S)
+    g.M1 = kind == SR_STRUCTURED ? std::max(g.N1, g.W1) : g.W1;
+    g.M2 = kind == SR_STRUCTURED ? std::max(g.N2, g.W2) : g.W2;
     g.o1 = (g.M1 - g.N1) / 2;
     g.o2 = (g.M2 - g.N2) / 2;
+    g.c1 = (g.M1 - g.W1) / 2;
+    g.c2 = (g.M2 - g.W2) / 2;
     g.n = (int64_t)g.N1 * g.N2;
-    g.m = (int64_t)g.M1 * g.M2;
+    g.m = (int64_t)g.W1 * g.W2;
+    g.mg = (int64_t)g.M1 * g.M2;
     g.L = q.layers;
     g.th_off = q.theta_offset;
     if (kind == SR_STRUCTURED) {
       if (g.L < 1 || g.L > 16) return fail(SR_E_ARG, "layers must be in [1, 16]");
-      if (g.th_off < 0 || g.th_off + (int64_t)g.L * g.m > theta_len)
+      if (g.th_off < 0 || g.th_off + (int64_t)g.L * g.mg > theta_len)
         return fail(SR_E_SHAPE, "problem " + std::to_string(i) + ": theta block out of range");
       if (q.ndim == 1) {
         if (!supported_len_1d(g.M1)) return fail(SR_E_UNSUPPORTED, "unsupported 1D length " + std::to_string(g.M1));
@@ -729,7 +738,7 @@ sr_status sr_spectral_init(sr_plan p, const float* y, const void* v0, int32_t it
     const float* yi = y + p->yoff[i];
     const float2* vi = vs + p->xoff[i];
     float2* xi = xs + p->xoff[i];
-    const float inv_mc = 1.f;  // structured: c = 1/m
+    const float inv_mc = (float)((double)g.mg / (double)g.m);  // structured: c = 1/(grid size)
     if (g.ndim == 1) {
       Fused1DArgs a{};
       a.x_in = vi;

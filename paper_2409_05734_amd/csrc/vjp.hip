@@ -37,7 +37,7 @@ __global__ void gth_support_kernel(const float2* __restrict__ gv, const float2* 
 sr_status ensure_vjp_buf(sr_plan_s* p) {
   size_t need = 0;
   for (const Geo& g : p->geo)
-    if (g.ndim == 2) need = std::max(need, (size_t)std::max(g.L - 1, 1) * (size_t)g.m + (size_t)g.n);
+    if (g.ndim == 2) need = std::max(need, (size_t)std::max(g.L - 1, 1) * (size_t)g.mg + (size_t)g.n);
   if (need <= p->vjp_elems) return SR_OK;
   if (p->vjp_buf) {
     hipStreamSynchronize(p->stream);
@@ -52,11 +52,11 @@ sr_status ensure_vjp_buf(sr_plan_s* p) {
 }
 
 // save buffer of layer k (k = 2..L) and an n-sized scratch after them
-float2* save_of(sr_plan_s* p, const Geo& g, int k) { return p->vjp_buf + (size_t)(k - 2) * g.m; }
-float2* nscratch(sr_plan_s* p, const Geo& g) { return p->vjp_buf + (size_t)std::max(g.L - 1, 1) * g.m; }
+float2* save_of(sr_plan_s* p, const Geo& g, int k) { return p->vjp_buf + (size_t)(k - 2) * g.mg; }
+float2* nscratch(sr_plan_s* p, const Geo& g) { return p->vjp_buf + (size_t)std::max(g.L - 1, 1) * g.mg; }
 
 float* gth_of(const sr_plan_s* p, const Geo& g, float* gtheta, int l) {
-  return gtheta + g.th_off + (int64_t)(l - 1) * g.m;
+  return gtheta + g.th_off + (int64_t)(l - 1) * g.mg;
 }
 
 sr_status fused1d_vjp(sr_plan_s* p, const Geo& g, int op, Fused1DArgs a) {
@@ -64,6 +64,8 @@ sr_status fused1d_vjp(sr_plan_s* p, const Geo& g, int op, Fused1DArgs a) {
   a.m = g.M1;
   a.L = g.L;
   a.off = g.o1;
+  a.mw = g.W1;
+  a.moff = g.c1;
   a.theta = p->theta_l(g, 1);
   a.tw = p->twiddles(g.M1);
   hipError_t e = launch_fused1d(g.M1, op, a, p->stream);
@@ -126,6 +128,7 @@ sr_status adj_passes(sr_plan_s* p, const Geo& g, const float2* r, int kind_mid, 
   {
     PassArgs a = base_args(p, g, kt);
     in_full(a, g, kt, r);
+    a.in_window = 1;  // r lives on the measurement window
     set_out(a, g, kt, cur);
     a.scale_out = 1.f / std::sqrt((float)pass_len(g, kt));
     VJ_CHECK(launch(p, g, kt, PK_FIRST_ADJ, a));

@@ -64,7 +64,7 @@ def _create(lib, probs, theta_len, theta=True, dense=None):
 
 
 @pytest.mark.parametrize("n,m,L,tlen,status", [
-    ((64,), (32,), 2, 64, -2),            # alpha < 1
+    ((64,), (32,), 2, 64, -2),            # trimmed: theta must cover L x 64 grid points
     ((16, 16), (32, 30), 2, 2 * 960, -3),  # 30 has a prime factor 5
     ((16, 16), (32, 32), 0, 2048, -1),     # L = 0
     ((16, 16), (32, 32), 2, 1000, -2),     # theta block out of range

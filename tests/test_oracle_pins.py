@@ -337,3 +337,130 @@ def test_unrolled_loss_gradient_matches_central_differences():
     mask = np.ones(m_shape, bool)
     mask[2:6, 2:6] = False
     assert np.abs(g[0][mask]).max() == 0.0
+
+
+# ------------------------------------------------ undersampling (alpha <= 1)
+
+def _brute_force_general(thetas, n_shape, m_shape):
+    """S prod_l (F D_l) U on the grid max(n, m) per axis, with F from numpy.fft
+    on identity columns (Kronecker product), U and S explicit 0/1 matrices
+    built from centred offsets by index arithmetic."""
+    grid = tuple(max(a, b) for a, b in zip(n_shape, m_shape))
+    assert grid == thetas.shape[1:]
+    g, n, m = int(np.prod(grid)), int(np.prod(n_shape)), int(np.prod(m_shape))
+    F = np.ones((1, 1))
+    for G in grid:
+        F = np.kron(F, np.fft.fft(np.eye(G), axis=0, norm="ortho"))
+    U = np.zeros((g, n))
+    off = [(G - N) // 2 for N, G in zip(n_shape, grid)]
+    for j in range(n):
+        jj = np.unravel_index(j, n_shape)
+        U[np.ravel_multi_index(tuple(o + a for o, a in zip(off, jj)), grid), j] = 1.0
+    S = np.zeros((m, g))
+    cut = [(G - M) // 2 for M, G in zip(m_shape, grid)]
+    for i in range(m):
+        ii = np.unravel_index(i, m_shape)
+        S[i, np.ravel_multi_index(tuple(c + a for c, a in zip(cut, ii)), grid)] = 1.0
+    A = U.astype(complex)
+    for th in thetas:
+        A = F @ (np.exp(1j * th.ravel())[:, None] * A)
+    return S @ A
+
+
+@pytest.mark.parametrize("n_shape,m_shape,L", [
+    ((16,), (10,), 1), ((16,), (9,), 2), ((12,), (12,), 3),        # 1D trim, alpha = 1
+    ((8, 6), (5, 4), 2), ((6, 8), (8, 5), 2), ((8, 8), (3, 8), 1),  # 2D trim, mixed pad/trim
+])
+def test_undersampled_operator_matches_brute_force(n_shape, m_shape, L):
+    rng = np.random.default_rng(21)
+    grid = tuple(max(a, b) for a, b in zip(n_shape, m_shape))
+    th = rng.uniform(0, 2 * np.pi, (L,) + grid)
+    A_bf = _brute_force_general(th, n_shape, m_shape)
+    A_or = oracle.dense_matrix(th, n_shape, m_shape)
+    assert A_or.shape == A_bf.shape
+    assert np.abs(A_or - A_bf).max() < 1e-12
+    r = _cgauss(rng, m_shape)
+    assert np.abs(oracle.adjoint(r, th, n_shape).ravel() - A_bf.conj().T @ r.ravel()).max() < 1e-12
+    # mean squared entry: 1 / (grid size)
+    op = oracle.StructuredOperator(th, n_shape, m_shape)
+    if all(M <= N for N, M in zip(n_shape, m_shape)) or all(M >= N for N, M in zip(n_shape, m_shape)):
+        assert abs(np.mean(np.abs(A_bf) ** 2) - op.c) < 1e-12
+
+
+@pytest.mark.parametrize("n_shape,m_shape,L", [((32,), (20,), 2), ((12, 10), (7, 10), 2), ((9, 9), (9, 9), 1)])
+def test_undersampled_rows_are_orthonormal(n_shape, m_shape, L):
+    """alpha <= 1: A A^H = I_m (the rows of a unitary matrix); Parseval on
+    the range of A^H; adjoint identity."""
+    rng = np.random.default_rng(22)
+    th = rng.uniform(0, 2 * np.pi, (L,) + tuple(n_shape))
+    A = oracle.dense_matrix(th, n_shape, m_shape)
+    assert np.abs(A @ A.conj().T - np.eye(A.shape[0])).max() < 1e-12
+    r = _cgauss(rng, m_shape)
+    assert abs(np.linalg.norm(oracle.adjoint(r, th, n_shape)) - np.linalg.norm(r)) < 1e-12 * np.linalg.norm(r)
+    x = _cgauss(rng, n_shape)
+    lhs = np.vdot(oracle.forward(x, th, m_shape), r)
+    rhs = np.vdot(x, oracle.adjoint(r, th, n_shape))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_undersampled_zero_phase_single_layer_is_trimmed_fft():
+    rng = np.random.default_rng(23)
+    x = _cgauss(rng, (10, 12))
+    th = np.zeros((1, 10, 12))
+    z = oracle.forward(x, th, (6, 7))
+    ref = np.fft.fft2(x, norm="ortho")[2:8, 2:9]
+    assert np.abs(z - ref).max() < 1e-12
+
+
+def test_undersampled_spectral_iterates_match_eigendecomposition():
+    rng = np.random.default_rng(24)
+    n, m = 32, 24
+    th = rng.uniform(0, 2 * np.pi, (2, n))
+    op = oracle.StructuredOperator(th, (n,), (m,))
+    A = _brute_force_general(th, (n,), (m,))
+    y = np.abs(A @ _cgauss(rng, (n,))) ** 2
+    lam = -1.0
+    T = oracle.preprocess(y, lam)
+    c = 1.0 / n
+    M = A.conj().T @ (T[:, None] * A) / (m * c)
+    v0 = _cgauss(rng, (n,))
+    for K in (1, 6, 25):
+        _, its = oracle.spectral_init(op, y, v0, K, lam, return_iterates=True)
+        assert np.abs(its[-1] - _spectral_closed_form(M, lam, v0, K)).max() < 1e-10
+
+
+def test_undersampled_gd_gradient_matches_finite_differences():
+    rng = np.random.default_rng(25)
+    th = rng.uniform(0, 2 * np.pi, (2, 8, 10))
+    op = oracle.StructuredOperator(th, (8, 10), (6, 7))
+    xs = _cgauss(rng, (8, 10))
+    y = oracle.measurements(xs, th, (6, 7)) * rng.uniform(0.5, 1.5, (6, 7))
+    x = _cgauss(rng, (8, 10))
+    g = oracle.gd_gradient(op, y, x)
+    for _ in range(6):
+        d = _cgauss(rng, (8, 10))
+        eps = 1e-6
+        fd = (oracle.intensity_loss(op, y, x + eps * d) - oracle.intensity_loss(op, y, x - eps * d)) / (2 * eps)
+        assert abs(fd - 4 * op.m * np.vdot(g, d).real) < 1e-6 * (abs(fd) + 1)
+
+
+def test_undersampled_vjps_match_finite_differences():
+    """Phase cotangents of z = A x and v = A^H r for a trimmed operator,
+    against central differences of Re<w, A(theta) x> and Re<w, A(theta)^H r>."""
+    rng = np.random.default_rng(26)
+    n_shape, m_shape = (6, 8), (4, 8)
+    th = rng.uniform(0, 2 * np.pi, (2,) + n_shape)
+    x, r = _cgauss(rng, n_shape), _cgauss(rng, m_shape)
+    gz, gv = _cgauss(rng, m_shape), _cgauss(rng, n_shape)
+    _, gth_f = oracle.forward_vjp(x, th, gz)
+    gr, gth_a = oracle.adjoint_vjp(r, th, n_shape, gv, m_shape)
+    assert gr.shape == m_shape
+    assert np.abs(gr - oracle.forward(gv, th, m_shape)).max() < 1e-12  # cotangent of r is A gv
+    d = rng.standard_normal(th.shape)
+    eps = 1e-6
+    f = lambda t: np.vdot(gz, oracle.forward(x, t, m_shape)).real
+    fd = (f(th + eps * d) - f(th - eps * d)) / (2 * eps)
+    assert abs(fd - np.sum(gth_f * d)) < 1e-6 * (abs(fd) + 1)
+    h = lambda t: np.vdot(gv, oracle.adjoint(r, t, n_shape)).real
+    fd = (h(th + eps * d) - h(th - eps * d)) / (2 * eps)
+    assert abs(fd - np.sum(gth_a * d)) < 1e-6 * (abs(fd) + 1)
