@@ -436,6 +436,70 @@ def forward_time_sweep(torch, srpr, sr_inputs, dev):
     return out
 
 
+def layer_study(torch, srpr, sr_inputs, dev, n=128, reps=32, iters=1000):
+    """The paper's layer-count comparison, on 1D i.i.d. CN(0,1) signals: median
+    cosine similarity of the spectral estimate (1000 power iterations,
+    lambda = -1, noiseless y) for structured models with L = 1, 2, 3 layers,
+    one layer followed by an extra FFT (L = 2 with theta_2 = 0), and random
+    unitary matrices (first n columns of a Haar unitary, scaled so that the
+    mean squared entry is 1).  All structured problems of one oversampling
+    ratio run in one plan (one workgroup each)."""
+    rng = np.random.default_rng(21)
+    alphas = (2, 3, 4, 6)
+    models = (("L1", 1, False), ("L2", 2, False), ("L3", 3, False), ("L1+FFT", 2, True))
+    out = {"workload": f"n = {n}, {reps} signals per point, {iters} power iterations", "alpha": list(alphas)}
+    for name, _, _ in models:
+        out[name] = []
+    out["unitary"] = []
+    t0 = time.perf_counter()
+    for alpha in alphas:
+        m = alpha * n
+        probs, thetas, xs, names = [], [], [], []
+        for name, L, extra_fft in models:
+            for _ in range(reps):
+                th = rng.uniform(0, 2 * np.pi, (L, m)).astype(np.float32)
+                if extra_fft:
+                    th[1] = 0.0
+                probs.append(srpr.Problem((n,), (m,), L))
+                thetas.append(th.ravel())
+                xs.append(sr_inputs.complex_gaussian(rng, (n,)))
+                names.append(name)
+        plan = srpr.Plan(probs, np.concatenate(thetas))
+        x = torch.from_numpy(np.concatenate(xs)).to(dev)
+        y = torch.empty(plan.m_total, dtype=torch.float32, device=dev)
+        srpr.sr_forward(plan, x, None, y)
+        v0 = torch.from_numpy(np.concatenate([sr_inputs.complex_gaussian(rng, (n,)) for _ in probs])).to(dev)
+        est = torch.empty_like(v0)
+        srpr.sr_spectral_init(plan, y, v0, iters, -1.0, est)
+        torch.cuda.synchronize()
+        xe = est.reshape(len(probs), n).cpu().numpy().astype(np.complex128)
+        xt = x.reshape(len(probs), n).cpu().numpy().astype(np.complex128)
+        cos = np.abs(np.sum(np.conj(xe) * xt, axis=1)) / (np.linalg.norm(xe, axis=1) * np.linalg.norm(xt, axis=1))
+        for name, _, _ in models:
+            sel = [i for i, nm in enumerate(names) if nm == name]
+            out[name].append(float(np.median(cos[sel])))
+        # random unitary baseline: Q from the QR factorisation of a complex Gaussian m x n matrix
+        g = torch.from_numpy(sr_inputs.complex_gaussian(rng, (m, n))).to(dev)
+        q, r = torch.linalg.qr(g)
+        d = torch.diagonal(r)
+        q = (q * (d / d.abs()).unsqueeze(0) * float(np.sqrt(m))).contiguous()
+        dplan = srpr.Plan([srpr.Problem((n,), (m,), 1, kind=srpr.SR_DENSE) for _ in range(reps)], None, dense_A=q)
+        xu = torch.from_numpy(np.concatenate([sr_inputs.complex_gaussian(rng, (n,)) for _ in range(reps)])).to(dev)
+        yu = torch.empty(reps * m, dtype=torch.float32, device=dev)
+        srpr.sr_forward(dplan, xu, None, yu)
+        v0u = torch.from_numpy(np.concatenate([sr_inputs.complex_gaussian(rng, (n,)) for _ in range(reps)])).to(dev)
+        eu = torch.empty_like(v0u)
+        srpr.sr_spectral_init(dplan, yu, v0u, iters, -1.0, eu)
+        torch.cuda.synchronize()
+        xe = eu.reshape(reps, n).cpu().numpy().astype(np.complex128)
+        xt = xu.reshape(reps, n).cpu().numpy().astype(np.complex128)
+        cos = np.abs(np.sum(np.conj(xe) * xt, axis=1)) / (np.linalg.norm(xe, axis=1) * np.linalg.norm(xt, axis=1))
+        out["unitary"].append(float(np.median(cos)))
+        del plan, dplan
+    out["gpu_wall_s"] = round(time.perf_counter() - t0, 2)
+    return out
+
+
 def tiny_1d(torch, srpr, sr_inputs, dev):
     d = sr_inputs.tiny_1d(0)
     plan = srpr.Plan([srpr.Problem(d["n_shape"], d["m_shape"], d["layers"])], d["theta"])
@@ -510,7 +574,7 @@ def main():
         extras = {}
         for name, fn in (("large_2d", large_2d), ("dense_baseline", dense), ("batched", batched),
                          ("autograd", autograd), ("lds_resident_2d", lds_resident), ("forward_time_sweep", forward_time_sweep),
-                         ("tiny_1d", tiny_1d)):
+                         ("layer_study", layer_study), ("tiny_1d", tiny_1d)):
             t0 = time.perf_counter()
             try:
                 extras[name] = fn(torch, srpr, sr_inputs, dev)

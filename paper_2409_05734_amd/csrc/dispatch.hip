@@ -51,6 +51,23 @@ int pass_groups(int N, bool col, int B, int ntr) {
 }
 
 namespace {
+template <int N, int OP>
+void go1d_batch_op(const Fused1DArgs* as, int count, hipStream_t s) {
+  hipLaunchKernelGGL((fused1d_batch_kernel<N, OP>), dim3(count), dim3(Tile<N, 1, false>::THREADS), 0, s, as);
+}
+
+template <int N>
+hipError_t go1d_batch(int op, const Fused1DArgs* as, int count, hipStream_t s) {
+  switch (op) {
+    case F1_FORWARD: go1d_batch_op<N, F1_FORWARD>(as, count, s); break;
+    case F1_ADJOINT: go1d_batch_op<N, F1_ADJOINT>(as, count, s); break;
+    case F1_GD: go1d_batch_op<N, F1_GD>(as, count, s); break;
+    case F1_SPECTRAL: go1d_batch_op<N, F1_SPECTRAL>(as, count, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <int N>
 hipError_t go1d(int op, const Fused1DArgs& a, hipStream_t s) {
   constexpr int NT = Tile<N, 1, false>::THREADS;
@@ -79,6 +96,20 @@ hipError_t go1d(int op, const Fused1DArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 }  // namespace
+
+hipError_t launch_fused1d_batch(int m, int op, const Fused1DArgs* dev_args, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  switch (m) {
+#define SR_CASE(n) \
+  case n:          \
+    return go1d_batch<n>(op, dev_args, count, s);
+    SR_FOR_EACH_2D_LEN(SR_CASE)
+    SR_CASE(4096)
+#undef SR_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_fused1d(int m, int op, const Fused1DArgs& a, hipStream_t s) {
   switch (m) {

@@ -35,7 +35,7 @@ struct Fused1DArgs {
 };
 
 template <int N, int OP>
-__global__ void __launch_bounds__((Tile<N, 1, false>::THREADS)) fused1d_kernel(const Fused1DArgs a) {
+__device__ __forceinline__ void fused1d_body(const Fused1DArgs& a) {
   using T = Tile<N, 1, false>;
   constexpr int E = T::E;
   constexpr int NT = T::THREADS;
@@ -274,6 +274,19 @@ __global__ void __launch_bounds__((Tile<N, 1, false>::THREADS)) fused1d_kernel(c
       if (in_window(k)) a.x_out[k - a.off] = cscale(u[j], scale);
     }
   }
+}
+
+// One problem per launch.
+template <int N, int OP>
+__global__ void __launch_bounds__((Tile<N, 1, false>::THREADS)) fused1d_kernel(const Fused1DArgs a) {
+  fused1d_body<N, OP>(a);
+}
+
+// Many problems of one length per launch, one workgroup each.
+template <int N, int OP>
+__global__ void __launch_bounds__((Tile<N, 1, false>::THREADS)) fused1d_batch_kernel(const Fused1DArgs* __restrict__ as) {
+  const Fused1DArgs a = as[blockIdx.x];
+  fused1d_body<N, OP>(a);
 }
 
 }  // namespace sr

@@ -83,6 +83,8 @@ int tile_options_n(bool col, int* out, int max_out);
 // 1D LDS-resident kernels (fused1d.hpp)
 struct Fused1DArgs;
 hipError_t launch_fused1d(int m, int op, const Fused1DArgs& a, hipStream_t s);
+// many problems of grid length m, one workgroup each (device argument array)
+hipError_t launch_fused1d_batch(int m, int op, const Fused1DArgs* dev_args, int count, hipStream_t s);
 
 }  // namespace sr
 

@@ -92,11 +92,10 @@ struct PassArgs {
   long long out2_ld;
   // measurement window: grid rows [win_lo0, win_hi0) x columns [win_lo1,
   // win_hi1), stored row-major with row length win_ld.  y, z_out, y_out (and
-  // the input when in_window is set) live on the window; the residual and
-  // the spectral weight are zero outside it.
+  // the input of the adjoint's first pass) live on the window; the residual
+  // and the spectral weight are zero outside it.
   int win_lo0, win_hi0, win_lo1, win_hi1;
   long long win_ld;
-  int in_window;
 };
 
 // 1/sqrt of the sum of the previous iterate's squared-norm partials: strided
@@ -149,16 +148,18 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   auto out_addr = [&](int k) -> int { return COL ? (k - a.out_lo) * old + b : b * old + (k - a.out_lo); };
   auto in_win = [&](int k) { return active && k >= a.in_lo && k < a.in_hi; };
   auto out_win = [&](int k) { return active && k >= a.out_lo && k < a.out_hi; };
-  // measurement window: membership and index of grid element k of this transform
+  // measurement window: membership and index of grid element k of this
+  // transform (the transform's own coordinate is tested once; the index is
+  // affine in k)
   const int wld = (int)a.win_ld;
-  auto m_in = [&](int k) {
-    const int r = COL ? k : gb, c = COL ? gb : k;
-    return active && r >= a.win_lo0 && r < a.win_hi0 && c >= a.win_lo1 && c < a.win_hi1;
-  };
-  auto m_idx = [&](int k) -> int {
-    const int r = COL ? k : gb, c = COL ? gb : k;
-    return (r - a.win_lo0) * wld + (c - a.win_lo1);
-  };
+  const bool m_lane = active && (COL ? (gb >= a.win_lo1 && gb < a.win_hi1) : (gb >= a.win_lo0 && gb < a.win_hi0));
+  const int m_klo = COL ? a.win_lo0 : a.win_lo1;
+  const int m_khi = COL ? a.win_hi0 : a.win_hi1;
+  const int m_base = COL ? (gb - a.win_lo1) - a.win_lo0 * wld : (gb - a.win_lo0) * wld - a.win_lo1;
+  auto m_in = [&](int k) { return m_lane && k >= m_klo && k < m_khi; };
+  auto m_idx = [&](int k) -> int { return COL ? m_base + k * wld : m_base + k; };
+  // the adjoint's first pass ([F_a^H] alone) reads its input on the window
+  constexpr bool IN_WIN = (PRE == PRE_NONE && MID == MID_NONE && !FFT2 && INV1 && POST == POST_STORE);
 
   // ---- issue every global load
   float2 v[E];
@@ -184,7 +185,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
     const int k = T::elem(t, j);
     const bool iw = in_win(k);
     const int g = gidx(k);
-    v[j] = a.in_window ? ld2(r_in, off8(m_in(k), m_idx(k))) : ld2(r_in, off8(iw, in_addr(k)));
+    if constexpr (IN_WIN) v[j] = ld2(r_in, off8(m_in(k), m_idx(k)));
+    else v[j] = ld2(r_in, off8(iw, in_addr(k)));
     if constexpr (PRE == PRE_PHASE) {
       if constexpr (TAB) dp[j] = ld2(r_pre, off8(iw, g));
       else dp[j].x = ld1(r_pre, off4(iw, g));

@@ -202,6 +202,7 @@ sr_plan_s::~sr_plan_s() {
   if (ev_fork) hipEventDestroy(ev_fork);
   if (ev_join) hipEventDestroy(ev_join);
   if (f2_descs) hipFree(f2_descs);
+  if (f1_args) hipFree(f1_args);
   if (cap_stream) hipStreamDestroy(cap_stream);
   if (vjp_buf) hipFree(vjp_buf);
   if (batch) sr::destroy_batch_state(batch);

@@ -76,6 +76,9 @@ struct sr_plan_s {
   // LDS-resident small-problem solver (fused2d.hip): device descriptors, their
   // host staging copy, and a second stream (with fork/join events) so that it
   // runs beside the batched level launches of the larger problems
+  void* f1_args = nullptr;  // batched 1D launches: device argument array and its host staging copy
+  size_t f1_cap = 0;
+  std::vector<unsigned char> f1_host;
   void* f2_descs = nullptr;
   size_t f2_desc_cap = 0;
   std::vector<unsigned char> f2_host;

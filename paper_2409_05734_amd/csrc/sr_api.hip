@@ -203,7 +203,6 @@ static sr_status adjoint_2d(sr_plan_s* p, const Geo& g, const float2* r, float2*
   const int k = g.L + 1;
   PassArgs a = base_args(p, g, k);
   in_full(a, g, k, r);
-  a.in_window = 1;  // r lives on the measurement window
   set_out(a, g, k, p->bufA);
   a.scale_out = 1.f / std::sqrt((float)pass_len(g, k));
   SR_CHECK(launch(p, g, k, PK_FIRST_ADJ, a));
@@ -272,10 +271,11 @@ static int turn_groups(const sr_plan_s* p, const Geo& g) {
 }
 
 // ------------------------------------------------------------------ tuner
-// Picks the tile width of every (FFT length, mode) a plan uses by timing one
-// GD iteration of each 2D problem shape for every combination of the
-// compiled column- and row-tile widths (on zeroed stand-in data in the
-// plan's spare buffers), keeping the fastest.  SR_TUNE=0 keeps the defaults;
+// Picks the tile width of every (FFT length, mode) a plan uses by timing the
+// steady-state GD iteration of each 2D problem shape for every combination of
+// the compiled column- and row-tile widths and phase sources (on zeroed
+// stand-in data in the plan's spare buffers; best of three runs), keeping the
+// fastest.  SR_TUNE=0 keeps the defaults;
 // SR_TUNE_CACHE=<file> reuses and records decisions across processes.
 
 static std::string tune_key(const Geo& g) {
@@ -364,13 +364,19 @@ static sr_status tune_plan(sr_plan_s* p) {
           p->use_table = tab != 0;
           p->tiles[{g.M1, 1}] = copt[i];
           p->tiles[{g.M2, 0}] = ropt[j];
-          for (int w = 0; w < 3; ++w) SR_CHECK(gd_iter_2d(p, g, y, x, 0.f, nullptr));
-          SR_HIP(hipEventRecord(e0, p->stream));
-          for (int w = 0; w < 10; ++w) SR_CHECK(gd_iter_2d(p, g, y, x, 0.f, nullptr));
-          SR_HIP(hipEventRecord(e1, p->stream));
-          SR_HIP(hipEventSynchronize(e1));
-          float ms = 0.f;
-          SR_HIP(hipEventElapsedTime(&ms, e0, e1));
+          // the steady-state iteration the solvers run (update fused with the next first pass)
+          SR_CHECK(first_pass(p, g, x, 1.f, nullptr, 0));
+          for (int w = 0; w < 3; ++w) SR_CHECK(gd_steady(p, g, y, x, 0.f, nullptr, false));
+          float ms = 1e30f;  // best of three timed runs (one run is noisy at microsecond scale)
+          for (int rep = 0; rep < 3; ++rep) {
+            SR_HIP(hipEventRecord(e0, p->stream));
+            for (int w = 0; w < 8; ++w) SR_CHECK(gd_steady(p, g, y, x, 0.f, nullptr, false));
+            SR_HIP(hipEventRecord(e1, p->stream));
+            SR_HIP(hipEventSynchronize(e1));
+            float t = 0.f;
+            SR_HIP(hipEventElapsedTime(&t, e0, e1));
+            ms = std::min(ms, t);
+          }
           if (ms < best) {
             best = ms;
             cb = copt[i];
@@ -448,7 +454,7 @@ static sr_status run_persistent(sr_plan_s* p, const Geo& g, int op, int iters, F
 
 // ------------------------------------------------------------ 1D (fused)
 
-static sr_status fused_1d(sr_plan_s* p, const Geo& g, int op, Fused1DArgs a) {
+static Fused1DArgs args_1d(const sr_plan_s* p, const Geo& g, Fused1DArgs a) {
   a.n = g.N1;
   a.m = g.M1;
   a.L = g.L;
@@ -457,8 +463,44 @@ static sr_status fused_1d(sr_plan_s* p, const Geo& g, int op, Fused1DArgs a) {
   a.moff = g.c1;
   a.theta = p->theta_l(g, 1);
   a.tw = p->twiddles(g.M1);
-  hipError_t e = launch_fused1d(g.M1, op, a, p->stream);
-  if (e != hipSuccess) return hip_fail(e, "fused 1D launch");
+  return a;
+}
+
+// The 1D problems of one call, launched together: one workgroup per problem,
+// one launch per grid length (a single problem launches on its own).
+using Batch1D = std::vector<std::pair<int, Fused1DArgs>>;
+
+static sr_status flush_1d(sr_plan_s* p, int op, Batch1D& items) {
+  if (items.empty()) return SR_OK;
+  if (items.size() == 1) {
+    hipError_t e = launch_fused1d(items[0].first, op, items[0].second, p->stream);
+    items.clear();
+    return e == hipSuccess ? SR_OK : hip_fail(e, "fused 1D launch");
+  }
+  std::stable_sort(items.begin(), items.end(),
+                   [](const std::pair<int, Fused1DArgs>& a, const std::pair<int, Fused1DArgs>& b) { return a.first < b.first; });
+  const size_t bytes = items.size() * sizeof(Fused1DArgs);
+  if (p->f1_cap < items.size()) {
+    if (p->f1_args) (void)hipFree(p->f1_args);
+    p->f1_args = nullptr;
+    p->f1_cap = 0;
+    hipError_t e = hipMalloc(&p->f1_args, bytes);
+    if (e != hipSuccess) return fail(SR_E_NOMEM, "1D argument allocation failed");
+    p->f1_cap = items.size();
+  }
+  p->f1_host.resize(bytes);  // kept alive by the plan while the upload is in flight
+  for (size_t i = 0; i < items.size(); ++i)
+    std::memcpy(p->f1_host.data() + i * sizeof(Fused1DArgs), &items[i].second, sizeof(Fused1DArgs));
+  SR_HIP(hipMemcpyAsync(p->f1_args, p->f1_host.data(), bytes, hipMemcpyHostToDevice, p->stream));
+  const Fused1DArgs* dev = (const Fused1DArgs*)p->f1_args;
+  for (size_t lo = 0; lo < items.size();) {
+    size_t hi = lo;
+    while (hi < items.size() && items[hi].first == items[lo].first) ++hi;
+    hipError_t e = launch_fused1d_batch(items[lo].first, op, dev + lo, (int)(hi - lo), p->stream);
+    if (e != hipSuccess) return hip_fail(e, "fused 1D batch launch");
+    lo = hi;
+  }
+  items.clear();
   return SR_OK;
 }
 
@@ -615,6 +657,7 @@ sr_status sr_forward(sr_plan p, const void* x, void* z, float* y) {
   const float2* xs = (const float2*)x;
   float2* zs = (float2*)z;
   if (p->kind == SR_DENSE) return dense_forward(p, xs, zs, y);
+  Batch1D b1;
   for (size_t i = 0; i < p->geo.size(); ++i) {
     const Geo& g = p->geo[i];
     const float2* xi = xs + p->xoff[i];
@@ -625,12 +668,12 @@ sr_status sr_forward(sr_plan p, const void* x, void* z, float* y) {
       a.x_in = xi;
       a.z_out = zi;
       a.y_out = yi;
-      SR_CHECK(fused_1d(p, g, F1_FORWARD, a));
+      b1.push_back({g.M1, args_1d(p, g, a)});
     } else {
       SR_CHECK(forward_2d(p, g, xi, zi, yi));
     }
   }
-  return SR_OK;
+  return flush_1d(p, F1_FORWARD, b1);
 }
 
 sr_status sr_adjoint(sr_plan p, const void* r, void* x_out) {
@@ -638,18 +681,19 @@ sr_status sr_adjoint(sr_plan p, const void* r, void* x_out) {
   const float2* rs = (const float2*)r;
   float2* xs = (float2*)x_out;
   if (p->kind == SR_DENSE) return dense_adjoint(p, rs, xs);
+  Batch1D b1;
   for (size_t i = 0; i < p->geo.size(); ++i) {
     const Geo& g = p->geo[i];
     if (g.ndim == 1) {
       Fused1DArgs a{};
       a.r_in = rs + p->yoff[i];
       a.x_out = xs + p->xoff[i];
-      SR_CHECK(fused_1d(p, g, F1_ADJOINT, a));
+      b1.push_back({g.M1, args_1d(p, g, a)});
     } else {
       SR_CHECK(adjoint_2d(p, g, rs + p->yoff[i], xs + p->xoff[i]));
     }
   }
-  return SR_OK;
+  return flush_1d(p, F1_ADJOINT, b1);
 }
 
 sr_status sr_gd_solve(sr_plan p, const float* y, void* x_inout, int32_t iters, const float* eta_host,
@@ -664,6 +708,7 @@ sr_status sr_gd_solve(sr_plan p, const float* y, void* x_inout, int32_t iters, c
   if (p->kind == SR_DENSE) return dense_gd(p, y, xs, iters, eta_host, loss_trace);
   const bool want_batched = p->schedule == SR_SCHED_BATCHED || (p->schedule == SR_SCHED_AUTO && p->geo.size() >= 8);
   if (want_batched && loss_trace == nullptr && batched_supported(p)) return batched_gd(p, y, xs, iters, eta_host);
+  Batch1D b1;
   for (size_t i = 0; i < p->geo.size(); ++i) {
     const Geo& g = p->geo[i];
     const float* yi = y + p->yoff[i];
@@ -677,7 +722,7 @@ sr_status sr_gd_solve(sr_plan p, const float* y, void* x_inout, int32_t iters, c
       a.iters = iters;
       a.step = step;
       a.loss_trace = lt;
-      SR_CHECK(fused_1d(p, g, F1_GD, a));
+      b1.push_back({g.M1, args_1d(p, g, a)});
       continue;
     }
     if (use_persistent(p, g)) {
@@ -701,7 +746,7 @@ sr_status sr_gd_solve(sr_plan p, const float* y, void* x_inout, int32_t iters, c
       if (lt) SR_CHECK(reduce_partials(p, p->part, nparts, lt + it));
     }
   }
-  return SR_OK;
+  return flush_1d(p, F1_GD, b1);
 }
 
 sr_status sr_spectral_init(sr_plan p, const float* y, const void* v0, int32_t iters, float lambda, void* x0_out) {
@@ -732,6 +777,7 @@ sr_status sr_spectral_init(sr_plan p, const float* y, const void* v0, int32_t it
     }
     SR_CHECK(fused2d_spectral(p, small, y, vs, iters, lambda, xs, s2));
   }
+  Batch1D b1;
   for (size_t i = 0; i < p->geo.size(); ++i) {
     if (resident[i]) continue;
     const Geo& g = p->geo[i];
@@ -747,7 +793,7 @@ sr_status sr_spectral_init(sr_plan p, const float* y, const void* v0, int32_t it
       a.iters = iters;
       a.step = inv_mc;
       a.lam = lambda;
-      SR_CHECK(fused_1d(p, g, F1_SPECTRAL, a));
+      b1.push_back({g.M1, args_1d(p, g, a)});
       continue;
     }
     // sum(y), then u_0 = v0 with its squared-norm partial
@@ -794,6 +840,7 @@ sr_status sr_spectral_init(sr_plan p, const float* y, const void* v0, int32_t it
     // x0 = sqrt(sum(y)/(m c)) u / ||u||
     SR_CHECK(final_scale(p, xi, g.n, parts[iters & 1], npart, p->ysum, inv_mc));
   }
+  SR_CHECK(flush_1d(p, F1_SPECTRAL, b1));
   if (forked) SR_CHECK(aux_join(p));
   return SR_OK;
 }

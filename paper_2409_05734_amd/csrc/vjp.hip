@@ -128,8 +128,7 @@ sr_status adj_passes(sr_plan_s* p, const Geo& g, const float2* r, int kind_mid, 
   {
     PassArgs a = base_args(p, g, kt);
     in_full(a, g, kt, r);
-    a.in_window = 1;  // r lives on the measurement window
-    set_out(a, g, kt, cur);
+      set_out(a, g, kt, cur);
     a.scale_out = 1.f / std::sqrt((float)pass_len(g, kt));
     VJ_CHECK(launch(p, g, kt, PK_FIRST_ADJ, a));
   }
