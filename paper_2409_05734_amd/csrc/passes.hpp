@@ -96,6 +96,7 @@ struct PassArgs {
   // and the spectral weight are zero outside it.
   int win_lo0, win_hi0, win_lo1, win_hi1;
   long long win_ld;
+  int crop;  // nonzero when the window is smaller than the grid (host: picks the window-aware kernels)
 };
 
 // 1/sqrt of the sum of the previous iterate's squared-norm partials: strided
@@ -122,7 +123,7 @@ __device__ __forceinline__ float inv_norm_from_partials(const float* part, int n
 // stores go through buffer resources: lanes outside a window (the zero-padded
 // rows/columns, transforms past ntr) read zeros and drop their writes.
 template <int N, int B, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST, bool DB = true,
-          int EV = 0, bool TAB = false>
+          int EV = 0, bool TAB = false, bool WIN = false>
 __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* lds, float* red, const float* part_in,
                                           int npart, float* part_out) {
   using T = TileV<N, B, COL, DB, EV>;
@@ -150,16 +151,18 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   auto out_win = [&](int k) { return active && k >= a.out_lo && k < a.out_hi; };
   // measurement window: membership and index of grid element k of this
   // transform (the transform's own coordinate is tested once; the index is
-  // affine in k)
+  // affine in k).  Kernels built without WIN take the window to be the whole
+  // grid (no trimming), where membership is `active` and the index is gidx.
   const int wld = (int)a.win_ld;
-  const bool m_lane = active && (COL ? (gb >= a.win_lo1 && gb < a.win_hi1) : (gb >= a.win_lo0 && gb < a.win_hi0));
+  const bool m_lane =
+      WIN ? active && (COL ? (gb >= a.win_lo1 && gb < a.win_hi1) : (gb >= a.win_lo0 && gb < a.win_hi0)) : active;
   const int m_klo = COL ? a.win_lo0 : a.win_lo1;
   const int m_khi = COL ? a.win_hi0 : a.win_hi1;
   const int m_base = COL ? (gb - a.win_lo1) - a.win_lo0 * wld : (gb - a.win_lo0) * wld - a.win_lo1;
-  auto m_in = [&](int k) { return m_lane && k >= m_klo && k < m_khi; };
-  auto m_idx = [&](int k) -> int { return COL ? m_base + k * wld : m_base + k; };
+  auto m_in = [&](int k) { return WIN ? m_lane && k >= m_klo && k < m_khi : active; };
+  auto m_idx = [&](int k) -> int { return WIN ? (COL ? m_base + k * wld : m_base + k) : gidx(k); };
   // the adjoint's first pass ([F_a^H] alone) reads its input on the window
-  constexpr bool IN_WIN = (PRE == PRE_NONE && MID == MID_NONE && !FFT2 && INV1 && POST == POST_STORE);
+  constexpr bool IN_WIN = WIN && (PRE == PRE_NONE && MID == MID_NONE && !FFT2 && INV1 && POST == POST_STORE);
 
   // ---- issue every global load
   float2 v[E];
@@ -225,9 +228,11 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
 
   float s_pre = a.scale_pre;
   float s_prev = 1.f;  // 1/||u_prev|| for the spectral update
-  if (part_in != nullptr) {
-    s_prev = inv_norm_from_partials<T::THREADS>(part_in, npart);
-    if (PRE == PRE_PHASE) s_pre *= s_prev;
+  if constexpr (PRE == PRE_PHASE || POST_IS_SPEC) {  // the only shapes that take the previous norm
+    if (part_in != nullptr) {
+      s_prev = inv_norm_from_partials<T::THREADS>(part_in, npart);
+      if (PRE == PRE_PHASE) s_pre *= s_prev;
+    }
   }
 
   // ---- pre-diagonal, first transform
@@ -350,27 +355,29 @@ constexpr bool pass_has_phase() {
 }
 
 // pass_tile with the phase source picked at run time (the tables are set
-// for every diagonal of a pass or for none).
+// for every diagonal of a pass or for none), window-aware so that it serves
+// every geometry.
 template <int N, int B, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST>
 __device__ __forceinline__ void pass_tile_rt(const PassArgs& a, int tile, float2* lds, float* red, const float* part_in,
                                              int npart, float* part_out) {
   if constexpr (pass_has_phase<PRE, MID, POST>()) {
     if (a.ep_pre != nullptr || a.ep_mid != nullptr || a.ep_post != nullptr) {
-      pass_tile<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, true, 0, true>(a, tile, lds, red, part_in, npart,
-                                                                           part_out);
+      pass_tile<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, true, 0, true, true>(a, tile, lds, red, part_in, npart,
+                                                                                 part_out);
       return;
     }
   }
-  pass_tile<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, true, 0, false>(a, tile, lds, red, part_in, npart, part_out);
+  pass_tile<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, true, 0, false, true>(a, tile, lds, red, part_in, npart,
+                                                                              part_out);
 }
 
 template <int N, int B, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST, bool DB = true,
-          int EV = 0, bool TAB = false>
+          int EV = 0, bool TAB = false, bool WIN = false>
 __global__ void __launch_bounds__((TileV<N, B, COL, DB, EV>::THREADS)) pass_kernel(const PassArgs a) {
   extern __shared__ float2 lds[];
   __shared__ float red[TileV<N, B, COL, DB, EV>::THREADS];
-  pass_tile<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, DB, EV, TAB>(a, xcd_tile(blockIdx.x, gridDim.x), lds, red,
-                                                                       a.part_in, a.npart, a.part_out);
+  pass_tile<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, DB, EV, TAB, WIN>(a, xcd_tile(blockIdx.x, gridDim.x), lds,
+                                                                            red, a.part_in, a.npart, a.part_out);
 }
 
 }  // namespace sr

@@ -17,13 +17,13 @@ namespace {
 
 // Tile widths are encoded as B | kSingleBuffer for single-buffered tiles and
 // B | kNarrow for the narrow thread shape.
-template <int N, int BE, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST, bool TAB>
+template <int N, int BE, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST, bool TAB, bool WIN>
 hipError_t go_src(const PassArgs& a, hipStream_t s) {
   constexpr int B = BE & (kSingleBuffer - 1);
   constexpr bool DB = (BE & kSingleBuffer) == 0;
   constexpr int EV = (BE & kNarrow) ? 1 : 0;
   using T = TileV<N, B, COL, DB, EV>;
-  auto kern = pass_kernel<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, DB, EV, TAB>;
+  auto kern = pass_kernel<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, DB, EV, TAB, WIN>;
   const size_t lds = T::NBUF * sizeof(float2) * (size_t)T::BUF;
   if (lds > 65536) {
     static bool raised = false;  // once per instantiation
@@ -41,13 +41,22 @@ hipError_t go_src(const PassArgs& a, hipStream_t s) {
 
 // Phase source: the exp(i theta) tables when the pass carries them (they are
 // set for every diagonal of a pass or for none), else the phases.
-template <int N, int BE, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST>
+template <int N, int BE, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST, bool WIN = false>
 hipError_t go(const PassArgs& a, hipStream_t s) {
   if constexpr (pass_has_phase<PRE, MID, POST>()) {
     if (a.ep_pre != nullptr || a.ep_mid != nullptr || a.ep_post != nullptr)
-      return go_src<N, BE, COL, PRE, MID, FFT2, INV1, INV2, POST, true>(a, s);
+      return go_src<N, BE, COL, PRE, MID, FFT2, INV1, INV2, POST, true, WIN>(a, s);
   }
-  return go_src<N, BE, COL, PRE, MID, FFT2, INV1, INV2, POST, false>(a, s);
+  return go_src<N, BE, COL, PRE, MID, FFT2, INV1, INV2, POST, false, WIN>(a, s);
+}
+
+// Shapes that touch the measurement window (the epilogue, the stores of z
+// and |z|^2, the adjoint's input): the window-aware build when the window is
+// smaller than the grid, else the build that takes the whole grid.
+template <int N, int BE, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST>
+hipError_t go_w(const PassArgs& a, hipStream_t s) {
+  if (a.crop) return go<N, BE, COL, PRE, MID, FFT2, INV1, INV2, POST, true>(a, s);
+  return go<N, BE, COL, PRE, MID, FFT2, INV1, INV2, POST, false>(a, s);
 }
 
 template <int N, bool COL, int B>  // B: encoded tile width
@@ -75,13 +84,13 @@ hipError_t dispatch(int kind, const PassArgs& a, hipStream_t s) {
     case PK_MID_FWD:
       return go<N, B, COL, PRE_NONE, MID_PHASE, true, false, false, POST_STORE>(a, s);
     case PK_LAST_STORE:
-      return go<N, B, COL, PRE_NONE, MID_STORE, false, false, false, POST_STORE>(a, s);
+      return go_w<N, B, COL, PRE_NONE, MID_STORE, false, false, false, POST_STORE>(a, s);
     case PK_TURN_GD:
-      return go<N, B, COL, PRE_NONE, MID_GD, true, false, true, POST_STORE>(a, s);
+      return go_w<N, B, COL, PRE_NONE, MID_GD, true, false, true, POST_STORE>(a, s);
     case PK_TURN_SPEC:
-      return go<N, B, COL, PRE_NONE, MID_SPEC, true, false, true, POST_STORE>(a, s);
+      return go_w<N, B, COL, PRE_NONE, MID_SPEC, true, false, true, POST_STORE>(a, s);
     case PK_FIRST_ADJ:
-      return go<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_STORE>(a, s);
+      return go_w<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_STORE>(a, s);
     case PK_MID_ADJ:
       return go<N, B, COL, PRE_NONE, MID_PHASE_CONJ, true, true, true, POST_STORE>(a, s);
     default:

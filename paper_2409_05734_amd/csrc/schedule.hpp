@@ -36,6 +36,7 @@ inline PassArgs base_args(const sr_plan_s* p, const Geo& g, int k) {
   a.win_lo1 = g.c2;
   a.win_hi1 = g.c2 + g.W2;
   a.win_ld = g.W2;
+  a.crop = g.cropped() ? 1 : 0;
   return a;
 }
 
