@@ -436,33 +436,52 @@ def forward_time_sweep(torch, srpr, sr_inputs, dev):
     return out
 
 
-def layer_study(torch, srpr, sr_inputs, dev, n=128, reps=32, iters=1000):
-    """The paper's layer-count comparison, on 1D i.i.d. CN(0,1) signals: median
-    cosine similarity of the spectral estimate (1000 power iterations,
-    lambda = -1, noiseless y) for structured models with L = 1, 2, 3 layers,
-    one layer followed by an extra FFT (L = 2 with theta_2 = 0), and random
-    unitary matrices (first n columns of a Haar unitary, scaled so that the
-    mean squared entry is 1).  All structured problems of one oversampling
-    ratio run in one plan (one workgroup each)."""
+def layer_study(torch, srpr, sr_inputs, dev, grid=64, sides=(46, 42, 38, 36, 34, 32, 30, 28), reps=100, iters=5000):
+    """The paper's layer-count comparison (section IV, number of layers): 2D
+    structured models on a 64 x 64 grid with L = 1, 2, 3 layers, one layer
+    after an extra FFT (L = 2 with theta_1 = 0, i.e. A = F D_2 F U), and a
+    random unitary model (the first n columns of a Haar unitary, scaled so
+    that the mean squared entry is 1, one draw per ratio shared by its
+    signals); spectral estimates after 5000 power iterations (no early stop)
+    on phase-only synthetic images.  Square image sides set the oversampling
+    ratios (alpha = 4096 / side^2, about 2 to 5; even sides, since the dense
+    model takes even signal lengths).  Reports the median and the
+    10% / 90% quantiles of the cosine similarity over `reps` signals.  All
+    structured problems of one ratio run in one batched plan."""
     rng = np.random.default_rng(21)
-    alphas = (2, 3, 4, 6)
+    m_shape = (grid, grid)
+    m = grid * grid
     models = (("L1", 1, False), ("L2", 2, False), ("L3", 3, False), ("L1+FFT", 2, True))
-    out = {"workload": f"n = {n}, {reps} signals per point, {iters} power iterations", "alpha": list(alphas)}
-    for name, _, _ in models:
-        out[name] = []
-    out["unitary"] = []
+    names_all = [nm for nm, _, _ in models] + ["unitary"]
+    out = {"workload": f"2D, {grid}x{grid} grid, phase-only images, {reps} signals per point, "
+                       f"{iters} power iterations",
+           "alpha": [round(m / (n * n), 3) for n in sides]}
+    for name in names_all:
+        out[name] = {"median": [], "q10": [], "q90": []}
+
+    def cosines(est, xs, count, n):
+        xe = est.reshape(count, n).cpu().numpy().astype(np.complex128)
+        xt = xs.reshape(count, n).cpu().numpy().astype(np.complex128)
+        return np.abs(np.sum(np.conj(xe) * xt, axis=1)) / (np.linalg.norm(xe, axis=1) * np.linalg.norm(xt, axis=1))
+
+    def record(name, cos):
+        out[name]["median"].append(round(float(np.median(cos)), 4))
+        out[name]["q10"].append(round(float(np.quantile(cos, 0.1)), 4))
+        out[name]["q90"].append(round(float(np.quantile(cos, 0.9)), 4))
+
     t0 = time.perf_counter()
-    for alpha in alphas:
-        m = alpha * n
+    for side in sides:
+        n_shape = (side, side)
+        n = side * side
         probs, thetas, xs, names = [], [], [], []
         for name, L, extra_fft in models:
             for _ in range(reps):
-                th = rng.uniform(0, 2 * np.pi, (L, m)).astype(np.float32)
+                th = rng.uniform(0, 2 * np.pi, (L,) + m_shape).astype(np.float32)
                 if extra_fft:
-                    th[1] = 0.0
-                probs.append(srpr.Problem((n,), (m,), L))
+                    th[0] = 0.0
+                probs.append(srpr.Problem(n_shape, m_shape, L))
                 thetas.append(th.ravel())
-                xs.append(sr_inputs.complex_gaussian(rng, (n,)))
+                xs.append(sr_inputs.phase_only_image(rng, n_shape).ravel())
                 names.append(name)
         plan = srpr.Plan(probs, np.concatenate(thetas))
         x = torch.from_numpy(np.concatenate(xs)).to(dev)
@@ -472,30 +491,26 @@ def layer_study(torch, srpr, sr_inputs, dev, n=128, reps=32, iters=1000):
         est = torch.empty_like(v0)
         srpr.sr_spectral_init(plan, y, v0, iters, -1.0, est)
         torch.cuda.synchronize()
-        xe = est.reshape(len(probs), n).cpu().numpy().astype(np.complex128)
-        xt = x.reshape(len(probs), n).cpu().numpy().astype(np.complex128)
-        cos = np.abs(np.sum(np.conj(xe) * xt, axis=1)) / (np.linalg.norm(xe, axis=1) * np.linalg.norm(xt, axis=1))
+        cos = cosines(est, x, len(probs), n)
         for name, _, _ in models:
-            sel = [i for i, nm in enumerate(names) if nm == name]
-            out[name].append(float(np.median(cos[sel])))
-        # random unitary baseline: Q from the QR factorisation of a complex Gaussian m x n matrix
+            record(name, cos[[i for i, nm in enumerate(names) if nm == name]])
+        # random unitary baseline: Q of the QR factorisation of a complex Gaussian m x n matrix
         g = torch.from_numpy(sr_inputs.complex_gaussian(rng, (m, n))).to(dev)
         q, r = torch.linalg.qr(g)
         d = torch.diagonal(r)
         q = (q * (d / d.abs()).unsqueeze(0) * float(np.sqrt(m))).contiguous()
         dplan = srpr.Plan([srpr.Problem((n,), (m,), 1, kind=srpr.SR_DENSE) for _ in range(reps)], None, dense_A=q)
-        xu = torch.from_numpy(np.concatenate([sr_inputs.complex_gaussian(rng, (n,)) for _ in range(reps)])).to(dev)
+        xu = torch.from_numpy(np.concatenate([sr_inputs.phase_only_image(rng, n_shape).ravel()
+                                              for _ in range(reps)])).to(dev)
         yu = torch.empty(reps * m, dtype=torch.float32, device=dev)
         srpr.sr_forward(dplan, xu, None, yu)
         v0u = torch.from_numpy(np.concatenate([sr_inputs.complex_gaussian(rng, (n,)) for _ in range(reps)])).to(dev)
         eu = torch.empty_like(v0u)
         srpr.sr_spectral_init(dplan, yu, v0u, iters, -1.0, eu)
         torch.cuda.synchronize()
-        xe = eu.reshape(reps, n).cpu().numpy().astype(np.complex128)
-        xt = xu.reshape(reps, n).cpu().numpy().astype(np.complex128)
-        cos = np.abs(np.sum(np.conj(xe) * xt, axis=1)) / (np.linalg.norm(xe, axis=1) * np.linalg.norm(xt, axis=1))
-        out["unitary"].append(float(np.median(cos)))
-        del plan, dplan
+        record("unitary", cosines(eu, xu, reps, n))
+        del plan, dplan, q, g
+        print(f"layer study: alpha {m / n:.2f} done ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
     out["gpu_wall_s"] = round(time.perf_counter() - t0, 2)
     return out
 
@@ -527,6 +542,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="headline only (no side workloads, no CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extras", default="all",
+                    help="comma-separated side workloads to run (default: all of them)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first run one 256 MiB device copy (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -572,9 +589,13 @@ def main():
     }
     if not args.quick:
         extras = {}
-        for name, fn in (("large_2d", large_2d), ("dense_baseline", dense), ("batched", batched),
-                         ("autograd", autograd), ("lds_resident_2d", lds_resident), ("forward_time_sweep", forward_time_sweep),
-                         ("layer_study", layer_study), ("tiny_1d", tiny_1d)):
+        side = (("large_2d", large_2d), ("dense_baseline", dense), ("batched", batched),
+                ("autograd", autograd), ("lds_resident_2d", lds_resident), ("forward_time_sweep", forward_time_sweep),
+                ("layer_study", layer_study), ("tiny_1d", tiny_1d))
+        wanted = None if args.extras == "all" else set(args.extras.split(","))
+        for name, fn in side:
+            if wanted is not None and name not in wanted:
+                continue
             t0 = time.perf_counter()
             try:
                 extras[name] = fn(torch, srpr, sr_inputs, dev)

@@ -155,7 +155,7 @@ void destroy_batch_state(BatchState* s) { delete s; }
 
 // Problems whose whole grid fits one workgroup's LDS run in the LDS-resident
 // solver (one launch for the whole solve); the others run as level launches.
-static bool lds_resident(const Geo& g) { return fused2d_enabled() && fused2d_supported(g); }
+static bool lds_resident(const Geo& g) { return fused2d_enabled(false) && fused2d_supported(g); }
 
 bool batched_supported(const sr_plan_s* p) {
   if (p->kind != SR_STRUCTURED || p->geo.size() < 2) return false;

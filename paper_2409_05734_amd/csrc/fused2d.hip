@@ -391,15 +391,18 @@ size_t f2_grid_bytes(int M1, int M2) {
 
 }  // namespace
 
-// The LDS-resident solver is opt-in (SR_LDS_RESIDENT=1).  Measured against
-// the level launches (300 GD steps): 512 problems on 64 x 64 grids, L = 2:
-// 12.2 ms against 13.9 ms; 256 problems on 128 x 128 grids: 29.4 against
-// 26.4 ms (one workgroup per CU); 1024 problems on 64 x 32 grids, L = 1:
-// 12.2 against 9.2 ms (too little work per workgroup).  Not a win often
-// enough to be the default.
-bool fused2d_enabled() {
+// For GD the LDS-resident solver is opt-in (SR_LDS_RESIDENT=1).  Measured
+// against the level launches (300 GD steps): 512 problems on 64 x 64 grids,
+// L = 2: 12.2 ms against 13.9 ms; 256 problems on 128 x 128 grids: 29.4
+// against 26.4 ms (one workgroup per CU); 1024 problems on 64 x 32 grids,
+// L = 1: 12.2 against 9.2 ms (too little work per workgroup).  Not a win
+// often enough to be the default there.  The spectral iteration has no level
+// launches (its problems otherwise run one after another), so there it is
+// the default (SR_LDS_RESIDENT=0 turns it off).
+bool fused2d_enabled(bool by_default) {
   const char* e = std::getenv("SR_LDS_RESIDENT");
-  return e != nullptr && std::atoi(e) != 0;
+  if (e == nullptr || *e == '\0') return by_default;
+  return std::atoi(e) != 0;
 }
 
 bool fused2d_supported(const Geo& g) {

@@ -758,13 +758,14 @@ sr_status sr_spectral_init(sr_plan p, const float* y, const void* v0, int32_t it
   float2* xs = (float2*)x0_out;
   if (p->kind == SR_DENSE) return dense_spectral(p, y, vs, iters, lambda, xs);
   // batched plans: problems whose grid fits one workgroup's LDS run their
-  // whole iteration in the LDS-resident solver, beside the others' passes
+  // whole iteration in the LDS-resident solver (by default: the others run
+  // one problem after another), beside the others' passes
   const bool want_batched = p->schedule == SR_SCHED_BATCHED || (p->schedule == SR_SCHED_AUTO && p->geo.size() >= 8);
   std::vector<char> resident(p->geo.size(), 0);
   std::vector<int> small;
   if (want_batched && p->geo.size() >= 2)
     for (size_t i = 0; i < p->geo.size(); ++i)
-      if (fused2d_enabled() && fused2d_supported(p->geo[i])) {
+      if (fused2d_enabled(true) && fused2d_supported(p->geo[i])) {
         resident[i] = 1;
         small.push_back((int)i);
       }

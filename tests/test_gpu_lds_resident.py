@@ -17,7 +17,8 @@ TOL_IT = 1e-4
 
 @pytest.fixture(autouse=True)
 def lds_resident_on(monkeypatch):
-    """The solver is opt-in; every test here runs with it switched on."""
+    """The solver is opt-in for GD; every test here runs with it switched on
+    unless it says otherwise."""
     monkeypatch.setenv("SR_LDS_RESIDENT", "1")
 
 # every supported axis length, radix-8-first (padded rows) and 3-factor rows,
@@ -107,3 +108,28 @@ def test_lds_resident_is_deterministic(gpu):
         srpr.sr_plan_sync(plan)
         outs.append(x)
     assert torch.equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("setting", [None, "0"])
+def test_spectral_default_and_off(gpu, monkeypatch, setting):
+    """Batched spectral solves take the LDS-resident solver by default (unset
+    switch) and run problem by problem with SR_LDS_RESIDENT=0; both against
+    the oracle."""
+    import torch
+    import paper_2409_05734_amd as srpr
+    if setting is None:
+        monkeypatch.delenv("SR_LDS_RESIDENT", raising=False)
+    else:
+        monkeypatch.setenv("SR_LDS_RESIDENT", setting)
+    shapes = SMALL[:4] + [LARGE]
+    plan, data = _plan_and_data(shapes, 17, gpu)
+    y = to_dev(_cat([d["y"] for d in data]), gpu)
+    v0 = to_dev(_cat([d["v0"] for d in data]), gpu)
+    out = torch.empty(plan.n_total, dtype=torch.complex64, device=gpu)
+    srpr.sr_spectral_init(plan, y, v0, 25, -1.0, out)
+    srpr.sr_plan_sync(plan)
+    xh = to_host(out)
+    for i, d in enumerate(data):
+        xr = oracle.spectral_init(d["op"], d["y"], d["v0"], 25, -1.0)
+        xi = xh[plan.x_off[i]:plan.x_off[i + 1]].reshape(d["n_shape"])
+        assert rel_l2(xi, xr) <= TOL_IT, (shapes[i], setting)
