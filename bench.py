@@ -515,6 +515,98 @@ def layer_study(torch, srpr, sr_inputs, dev, grid=64, sides=(46, 42, 38, 36, 34,
     return out
 
 
+def accuracy_sweep(torch, srpr, sr_inputs, dev, side=32, reps=100, dense_groups=4, gd_iters=10000, pi_iters=5000,
+                   mu=0.05):
+    """The paper's accuracy comparison (section IV-A): cosine similarity of
+    gradient descent from a random start (GD), the spectral estimate alone
+    (SM, lambda = -1) and GD from the spectral estimate (GD+SM) against the
+    oversampling ratio, for the structured model (L = 2, fresh phases per
+    repetition) and the i.i.d. CN(0,1) model (`dense_groups` matrices, each
+    shared by reps/dense_groups repetitions), on one 32 x 32 phase-only
+    synthetic image; 10000 GD / 5000 power iterations without early
+    stopping, step eta = mu / (c mean(y)); median and 10 % / 90 % quantiles
+    over `reps` repetitions (random starts differ per repetition)."""
+    rng = np.random.default_rng(33)
+    n_shape = (side, side)
+    n = side * side
+    x_star = sr_inputs.phase_only_image(rng, n_shape).ravel()
+    grids = {1: (32, 32), 2: (64, 32), 3: (96, 32), 4: (64, 64), 6: (96, 64), 8: (128, 64), 9: (96, 96)}
+    out = {"workload": f"{side}x{side} phase-only image, {reps} repetitions, {gd_iters} GD / {pi_iters} power "
+                       f"iterations, mu = {mu}, structured L = 2 vs i.i.d. CN(0,1)",
+           "alpha": sorted(grids)}
+    for model in ("structured", "iid"):
+        for meth in ("GD", "SM", "GD+SM"):
+            out[f"{model} {meth}"] = {"median": [], "q10": [], "q90": [], "nonfinite": []}
+
+    def record(key, est, count):
+        xe = est.reshape(count, n).cpu().numpy().astype(np.complex128)
+        xt = x_star.astype(np.complex128)
+        with np.errstate(invalid="ignore", over="ignore"):
+            cos = np.abs(xe.conj() @ xt) / (np.linalg.norm(xe, axis=1) * np.linalg.norm(xt))
+        bad = ~np.isfinite(cos)
+        cos = np.where(bad, 0.0, cos)  # a diverged run recovers nothing
+        out[key]["median"].append(round(float(np.median(cos)), 4))
+        out[key]["q10"].append(round(float(np.quantile(cos, 0.1)), 4))
+        out[key]["q90"].append(round(float(np.quantile(cos, 0.9)), 4))
+        out[key]["nonfinite"].append(int(bad.sum()))
+
+    def starts(count, ysum_over_mc):
+        # random starts CN(0,1) scaled to the norm the measurements imply
+        v = np.stack([sr_inputs.complex_gaussian(rng, (n,)) for _ in range(count)])
+        v *= np.sqrt(ysum_over_mc[:, None] / np.sum(np.abs(v) ** 2, axis=1, keepdims=True))
+        return torch.from_numpy(v.astype(np.complex64).ravel()).to(dev)
+
+    def solve_all(plans, c_of, key_model):
+        # plans: list of (plan, count); returns nothing, records the three methods
+        for meth in ("GD", "SM", "GD+SM"):
+            ests = []
+            for plan, count, y, m in plans:
+                yh = y.cpu().numpy().astype(np.float64).reshape(count, m)
+                c = c_of(m)
+                eta = (mu / (c * yh.mean(axis=1))).astype(np.float32)
+                if meth == "GD":
+                    x = starts(count, yh.sum(axis=1) / (m * c))
+                    srpr.sr_gd_solve(plan, y, x, gd_iters, eta)
+                else:
+                    v0 = torch.from_numpy(np.concatenate([sr_inputs.complex_gaussian(rng, (n,))
+                                                          for _ in range(count)])).to(dev)
+                    x = torch.empty_like(v0)
+                    srpr.sr_spectral_init(plan, y, v0, pi_iters, -1.0, x)
+                    if meth == "GD+SM":
+                        srpr.sr_gd_solve(plan, y, x, gd_iters, eta)
+                ests.append(x)
+            torch.cuda.synchronize()
+            record(f"{key_model} {meth}", torch.cat(ests), reps)
+
+    t0 = time.perf_counter()
+    xs_all = torch.from_numpy(np.tile(x_star, reps)).to(dev)
+    for alpha in sorted(grids):
+        m_shape = grids[alpha]
+        m = m_shape[0] * m_shape[1]
+        # structured, L = 2: one plan with a fresh theta per repetition
+        th = rng.uniform(0, 2 * np.pi, (reps, 2) + m_shape).astype(np.float32)
+        plan = srpr.Plan([srpr.Problem(n_shape, m_shape, 2) for _ in range(reps)], th.ravel())
+        y = torch.empty(plan.m_total, dtype=torch.float32, device=dev)
+        srpr.sr_forward(plan, xs_all, None, y)
+        solve_all([(plan, reps, y, m)], lambda mm: 1.0 / mm, "structured")
+        del plan, y
+        # i.i.d.: dense_groups matrices, each shared by reps / dense_groups signals
+        per = reps // dense_groups
+        dplans = []
+        for _ in range(dense_groups):
+            A = torch.from_numpy(sr_inputs.complex_gaussian(rng, (m, n))).to(dev)
+            dp = srpr.Plan([srpr.Problem((n,), (m,), 1, kind=srpr.SR_DENSE) for _ in range(per)], None, dense_A=A)
+            yd = torch.empty(per * m, dtype=torch.float32, device=dev)
+            srpr.sr_forward(dp, xs_all[:per * n], None, yd)
+            dplans.append((dp, per, yd, m))
+        solve_all(dplans, lambda mm: 1.0, "iid")
+        del dplans
+        torch.cuda.empty_cache()
+        print(f"accuracy sweep: alpha {alpha} done ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    out["gpu_wall_s"] = round(time.perf_counter() - t0, 2)
+    return out
+
+
 def tiny_1d(torch, srpr, sr_inputs, dev):
     d = sr_inputs.tiny_1d(0)
     plan = srpr.Plan([srpr.Problem(d["n_shape"], d["m_shape"], d["layers"])], d["theta"])
@@ -543,7 +635,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline only (no side workloads, no CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extras", default="all",
-                    help="comma-separated side workloads to run (default: all of them)")
+                    help="comma-separated side workloads to run (default: all but accuracy_sweep)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first run one 256 MiB device copy (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -591,10 +683,11 @@ def main():
         extras = {}
         side = (("large_2d", large_2d), ("dense_baseline", dense), ("batched", batched),
                 ("autograd", autograd), ("lds_resident_2d", lds_resident), ("forward_time_sweep", forward_time_sweep),
-                ("layer_study", layer_study), ("tiny_1d", tiny_1d))
+                ("layer_study", layer_study), ("tiny_1d", tiny_1d), ("accuracy_sweep", accuracy_sweep))
+        on_request = {"accuracy_sweep"}  # about a minute of GPU time: run only when named
         wanted = None if args.extras == "all" else set(args.extras.split(","))
         for name, fn in side:
-            if wanted is not None and name not in wanted:
+            if (wanted is None and name in on_request) or (wanted is not None and name not in wanted):
                 continue
             t0 = time.perf_counter()
             try:
