@@ -27,6 +27,11 @@ the project's design notes):
       the signal's grid and S keeps the centred measurement window, offset
       floor((N - M)/2) per axis; in general the grid is max(N, M) per axis,
       U pads into it and S trims it, and c = 1 / (grid size).
+* R18 Noise-model loss (section II-B.1 says other losses follow from the
+      noise statistics; none is written out): the negative Poisson
+      log-likelihood of the intensities, sum |z|^2 - y log(|z|^2 + eps) with a
+      guard eps > 0, whose Wirtinger gradient is A^H((1 - y/(|z|^2 + eps)) . z);
+      as in R1 the gradient is taken as g = A^H r / m.
 
 Parity pins for every function live in the CPU test-suite (library DFT,
 brute-force dense products, closed forms, invariants, eigendecomposition,
@@ -246,19 +251,41 @@ def intensity_loss(op, y, x) -> float:
     return float(np.sum((np.abs(z) ** 2 - np.asarray(y, dtype=np.float64)) ** 2))
 
 
+def poisson_gradient(op, y, x, eps: float) -> np.ndarray:
+    """g = A^H((1 - y/(|Ax|^2 + eps)) . Ax) / m: the Wirtinger gradient of the
+    Poisson negative log-likelihood (reading R18), scaled like gd_gradient."""
+    z = op.A(x)
+    r = (1.0 - np.asarray(y, dtype=np.float64) / (np.abs(z) ** 2 + eps)) * z
+    return op.AH(r) / op.m
+
+
+def poisson_loss(op, y, x, eps: float) -> float:
+    """sum_i |z_i|^2 - y_i log(|z_i|^2 + eps), z = Ax (reading R18)."""
+    z2 = np.abs(op.A(x)) ** 2
+    return float(np.sum(z2 - np.asarray(y, dtype=np.float64) * np.log(z2 + eps)))
+
+
 def gd_solve(op, y, x0, iters: int, eta: float, return_iterates: bool = False,
-             return_loss: bool = False):
-    """Fixed-step gradient descent x <- x - eta g(x) on the intensity loss (Eq. (2)).
+             return_loss: bool = False, loss: str = "l2", eps: float = 0.0):
+    """Fixed-step gradient descent x <- x - eta g(x) on the intensity loss (Eq. (2)),
+    or with loss="poisson" on the Poisson negative log-likelihood (reading R18,
+    guard eps > 0).
 
     eta is the raw multiplier of g; no early stopping (fixed iteration count).
-    The optional loss trace records L(x_t) before each step.
+    The optional loss trace records the loss at x_t before each step.
     """
+    if loss not in ("l2", "poisson"):
+        raise ValueError(f"unknown loss {loss!r}")
+    if loss == "poisson" and not eps > 0:
+        raise ValueError("the Poisson loss needs eps > 0")
+    grad = gd_gradient if loss == "l2" else (lambda o, yy, xx: poisson_gradient(o, yy, xx, eps))
+    value = intensity_loss if loss == "l2" else (lambda o, yy, xx: poisson_loss(o, yy, xx, eps))
     x = np.asarray(x0, dtype=np.complex128).copy()
     its, losses = [], []
     for _ in range(iters):
         if return_loss:
-            losses.append(intensity_loss(op, y, x))
-        x = x - eta * gd_gradient(op, y, x)
+            losses.append(value(op, y, x))
+        x = x - eta * grad(op, y, x)
         if return_iterates:
             its.append(x.copy())
     out = [x]

@@ -256,6 +256,50 @@ def test_gd_gradient_vanishes_at_truth_up_to_global_phase():
         assert np.abs(oracle.gd_gradient(op, y, xs * np.exp(1j * phi))).max() < 1e-12
 
 
+def test_poisson_gradient_matches_finite_differences():
+    """Reading R18: the Poisson gradient against central differences of the
+    Poisson loss, on a 2D structured and a dense model (noisy y, so the point
+    is not a stationary one)."""
+    rng = np.random.default_rng(31)
+    th = rng.uniform(0, 2 * np.pi, (2, 6, 8))
+    ops = [oracle.StructuredOperator(th, (3, 4)),
+           oracle.DenseOperator((rng.standard_normal((40, 12)) + 1j * rng.standard_normal((40, 12))) / np.sqrt(2))]
+    for op in ops:
+        n_shape = (3, 4) if op is ops[0] else (12,)
+        xs = _cgauss(rng, n_shape)
+        y = np.abs(op.A(xs)) ** 2 * rng.uniform(0.5, 1.5, np.shape(op.A(xs)))
+        x = _cgauss(rng, n_shape)
+        for eps in (1e-3, 0.5):
+            g = oracle.poisson_gradient(op, y, x, eps)
+            for _ in range(6):
+                d = _cgauss(rng, n_shape)
+                h = 1e-6
+                fd = (oracle.poisson_loss(op, y, x + h * d, eps) - oracle.poisson_loss(op, y, x - h * d, eps)) / (2 * h)
+                # a real f with Wirtinger gradient G has df = 2 Re<G, dx>; g = G / m
+                assert abs(fd - 2 * op.m * np.vdot(g, d).real) < 1e-6 * (abs(fd) + 1)
+
+
+def test_poisson_gradient_vanishes_at_truth_and_differs_from_l2():
+    """With noiseless y the truth (any global phase) is a stationary point of
+    the Poisson loss as eps -> 0; away from it the Poisson and l2 steps point
+    in different directions (the loss switch is not a no-op)."""
+    rng = np.random.default_rng(32)
+    th = rng.uniform(0, 2 * np.pi, (2, 64))
+    op = oracle.StructuredOperator(th, (16,))
+    xs = _cgauss(rng, (16,))
+    y = oracle.measurements(xs, th)
+    for phi in (0.0, 2.2):
+        assert np.abs(oracle.poisson_gradient(op, y, xs * np.exp(1j * phi), 1e-14)).max() < 1e-10
+    x = xs + 0.3 * _cgauss(rng, (16,))
+    gp, gl = oracle.poisson_gradient(op, y, x, 1e-6), oracle.gd_gradient(op, y, x)
+    assert oracle.cosine_similarity(gp, gl) < 0.999
+    # a small Poisson GD run from near the truth lowers the Poisson loss monotonically
+    _, losses = oracle.gd_solve(op, y, x, 20, 0.05 * op.m, return_loss=True, loss="poisson", eps=1e-6)
+    assert np.all(np.diff(losses) < 0)
+    with pytest.raises(ValueError):
+        oracle.gd_solve(op, y, x, 1, 0.1, loss="poisson", eps=0.0)
+
+
 def test_tiny_1d_recovers_signal():
     d = sr_inputs.tiny_1d(0)
     xs = d["x_star"].astype(np.complex128)
