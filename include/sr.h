@@ -62,6 +62,11 @@ typedef enum {
 } sr_kind;
 
 typedef enum {
+  SR_LOSS_L2 = 0,          /* l2 intensity loss || |Ax|^2 - y ||^2 (section II-B.1, Eq. (2)) */
+  SR_LOSS_POISSON = 1      /* Poisson negative log-likelihood of the intensities (see sr_plan_set_loss) */
+} sr_loss;
+
+typedef enum {
   SR_SCHED_AUTO = 0,       /* library's choice */
   SR_SCHED_LOOP = 1,       /* one problem after another, one launch per fused pass */
   SR_SCHED_BATCHED = 2     /* all problems together (persistent batched launches) */
@@ -120,6 +125,19 @@ sr_status sr_plan_offsets(sr_plan plan, int64_t* x_off, int64_t* y_off);
 /* Choose how multi-problem plans are scheduled (sr_schedule).                */
 sr_status sr_plan_set_schedule(sr_plan plan, int32_t schedule);
 
+/* Choose the loss sr_gd_solve descends, for every problem of the plan and
+ * every later call (default SR_LOSS_L2).  Section II-B.1 notes that the loss
+ * can follow the noise model; SR_LOSS_POISSON is the negative Poisson
+ * log-likelihood of the intensities, sum_i |z_i|^2 - y_i log(|z_i|^2 + eps)
+ * (z = A x), whose gradient step replaces the residual (|z|^2 - y) . z by
+ * (1 - y / (|z|^2 + eps)) . z; eps > 0 guards the logarithm and the division
+ * and is ignored for SR_LOSS_L2.  The step keeps its meaning (x <- x - eta
+ * A^H r / m); for the Poisson loss a step of order mu / c (c as for
+ * sr_spectral_init) plays the part of mu / (c mean(y)).  The loss trace
+ * records the chosen loss.  SR_E_ARG for an unknown loss, or for
+ * SR_LOSS_POISSON with eps not finite and positive.                          */
+sr_status sr_plan_set_loss(sr_plan plan, int32_t loss, float eps);
+
 /* Wait for all work of the plan's stream; reports device-side failures.      */
 sr_status sr_plan_sync(sr_plan plan);
 
@@ -151,7 +169,7 @@ sr_status sr_spectral_init(sr_plan plan, const float* y, const void* v0, int32_t
 
 /* Gradient descent on the intensity loss || |Ax|^2 - y ||^2 (section II-B.1,
  * Eq. (2) read with diag(A x)): x <- x - eta * A^H((|Ax|^2 - y) . Ax) / m,
- * `iters` times, in place.
+ * `iters` times, in place (or on the loss chosen with sr_plan_set_loss).
  *  y           float measurements (y_off layout)
  *  x_inout     complex64 iterates (x_off layout), updated in place
  *  eta_host    HOST array of nprob raw step sizes (no hidden normalisation)

@@ -17,13 +17,15 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _lib
-from ._lib import SR_DENSE, SR_SCHED_AUTO, SR_SCHED_BATCHED, SR_SCHED_LOOP, SR_STRUCTURED, SrError
+from ._lib import (SR_DENSE, SR_LOSS_L2, SR_LOSS_POISSON, SR_SCHED_AUTO, SR_SCHED_BATCHED, SR_SCHED_LOOP,
+                   SR_STRUCTURED, SrError)
 
 __all__ = [
     "Problem", "Plan", "SrError",
-    "sr_plan_set_theta", "sr_plan_workspace_size", "sr_plan_offsets", "sr_plan_set_schedule", "sr_plan_sync",
+    "sr_plan_set_theta", "sr_plan_workspace_size", "sr_plan_offsets", "sr_plan_set_schedule", "sr_plan_set_loss",
+    "sr_plan_sync",
     "sr_forward", "sr_adjoint", "sr_spectral_init", "sr_gd_solve", "sr_forward_vjp", "sr_adjoint_vjp",
-    "SR_STRUCTURED", "SR_DENSE", "SR_SCHED_AUTO", "SR_SCHED_LOOP", "SR_SCHED_BATCHED",
+    "SR_STRUCTURED", "SR_DENSE", "SR_SCHED_AUTO", "SR_SCHED_LOOP", "SR_SCHED_BATCHED", "SR_LOSS_L2", "SR_LOSS_POISSON",
 ]
 
 
@@ -175,6 +177,11 @@ def sr_plan_offsets(plan: Plan):
 
 def sr_plan_set_schedule(plan: Plan, schedule: int) -> None:
     _lib.call("sr_plan_set_schedule", plan.handle, int(schedule))
+
+
+def sr_plan_set_loss(plan: Plan, loss: int, eps: float = 0.0) -> None:
+    """GD loss of the plan: SR_LOSS_L2 (default) or SR_LOSS_POISSON with guard eps > 0."""
+    _lib.call("sr_plan_set_loss", plan.handle, int(loss), float(eps))
 
 
 def sr_plan_sync(plan: Plan) -> None:

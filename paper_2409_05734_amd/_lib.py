@@ -18,6 +18,8 @@ SR_DENSE = 1
 SR_SCHED_AUTO = 0
 SR_SCHED_LOOP = 1
 SR_SCHED_BATCHED = 2
+SR_LOSS_L2 = 0
+SR_LOSS_POISSON = 1
 
 STATUS_NAMES = {
     0: "SR_OK", -1: "SR_E_ARG", -2: "SR_E_SHAPE", -3: "SR_E_UNSUPPORTED", -4: "SR_E_HIP",
@@ -48,6 +50,7 @@ SIGNATURES = {
     "sr_plan_workspace_size": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     "sr_plan_offsets": (ctypes.c_int, [_vp, _vp, _vp]),
     "sr_plan_set_schedule": (ctypes.c_int, [_vp, _i32]),
+    "sr_plan_set_loss": (ctypes.c_int, [_vp, _i32, _f32]),
     "sr_plan_sync": (ctypes.c_int, [_vp]),
     "sr_plan_destroy": (ctypes.c_int, [_vp]),
     "sr_forward": (ctypes.c_int, [_vp, _vp, _vp, _vp]),

@@ -71,6 +71,10 @@ __device__ __forceinline__ void run_kind(const PassArgs& a, int kind, int tile, 
     case PK_TURN_GD:
       pass_tile_rt<N, B, COL, PRE_NONE, MID_GD, true, false, true, POST_STORE>(a, tile, lds, red, nullptr, 0, nullptr);
       return;
+    case PK_TURN_GD_POIS:
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_GD_POIS, true, false, true, POST_STORE>(a, tile, lds, red, nullptr, 0,
+                                                                                 nullptr);
+      return;
     case PK_MID_ADJ:
       pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE_CONJ, true, true, true, POST_STORE>(a, tile, lds, red, nullptr, 0,
                                                                                    nullptr);

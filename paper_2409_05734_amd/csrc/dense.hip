@@ -23,6 +23,7 @@
 #include <cmath>
 
 #include "fft_core.hpp"
+#include "loss.hpp"
 #include "plan.hpp"
 
 namespace sr {
@@ -48,7 +49,7 @@ constexpr int kMaxSplit = 8;  // the epilogue sums at most this many partial til
 
 enum Epi : int {
   E1_STORE = 0,  // after A X: z and/or |z|^2
-  E1_GD = 1,     // after A X: r = (|z|^2 - y) z, loss partials
+  E1_GD = 1,     // after A X: r = (|z|^2 - y) z (or the Poisson residual), loss partials
   E1_SPEC = 2,   // after A X: r = T(y/mean(y)) z
   E2_STORE = 3,  // after A^H R: x_out = A^H r * scale
   E2_GD = 4,     // after A^H R: x <- x - step * A^H r
@@ -75,6 +76,8 @@ struct DenseArgs {
   int S;                   // reduction splits
   int kchunk;              // reduction length per split (multiple of BK)
   int q_ld;                // 2 * (signals rounded up to 32): row length of the partials of A X
+  int loss;                // E1_GD: LOSS_L2 or LOSS_POISSON
+  float loss_eps;          // E1_GD: Poisson guard
 };
 
 __device__ __forceinline__ f4 ld4(const float* p) { return *reinterpret_cast<const f4*>(p); }
@@ -296,9 +299,15 @@ __global__ void __launch_bounds__(NT) dense_epi1_kernel(const DenseArgs a) {
         if (a.z_out) a.z_out[o] = z;
         if (a.y_out) a.y_out[o] = cabs2(z);
       } else if constexpr (EPI == E1_GD) {
-        const float d = cabs2(z) - a.y[o];
-        part += d * d;
-        a.z_out[o] = cscale(z, d);
+        const float z2 = cabs2(z), yy = a.y[o];
+        if (a.loss == LOSS_POISSON) {
+          part += poisson_term(z2, yy, a.loss_eps);
+          a.z_out[o] = cscale(z, poisson_weight(z2, yy, a.loss_eps));
+        } else {
+          const float d = z2 - yy;
+          part += d * d;
+          a.z_out[o] = cscale(z, d);
+        }
       } else {
         const float yy = a.y[o];
         float w = a.lam;
@@ -541,6 +550,8 @@ sr_status dense_gd(sr_plan_s* p, const float* y, float2* x, int iters, const flo
     g1.z_out = p->bufA;
     g1.part = p->part;
     g1.part_ld = t1;
+    g1.loss = p->loss;
+    g1.loss_eps = p->loss_eps;
     DN_HIP((gemm<1, E1_GD>(g1, p->dsplit, p->stream)));
     if (loss_trace) {
       hipLaunchKernelGGL(sum_rows_kernel, dim3((a.nb + 63) / 64), dim3(64), 0, p->stream, p->part, t1, t1, a.nb,

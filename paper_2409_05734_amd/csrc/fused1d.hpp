@@ -8,6 +8,7 @@
 // (m > n) and S the centred trimming to the m measurements (m < n).
 #pragma once
 #include "fft_core.hpp"
+#include "loss.hpp"
 
 namespace sr {
 
@@ -31,6 +32,8 @@ struct Fused1DArgs {
   float step;                // GD: eta/m; spectral: 1/(m c)
   float lam;                 // spectral lambda
   float* loss_trace;         // GD: loss before each step (nullable)
+  int loss;                  // GD: LOSS_L2 or LOSS_POISSON
+  float loss_eps;            // GD: Poisson guard
   float* gth;                // derivatives: phase-cotangent accumulator (L*m)
 };
 
@@ -119,11 +122,21 @@ __device__ __forceinline__ void fused1d_body(const Fused1DArgs& a) {
       for (int j = 0; j < E; ++j) v[j] = x[j];
       forward_layers();
       float acc = 0.f;
+      if (a.loss == LOSS_POISSON) {
 #pragma unroll
-      for (int j = 0; j < E; ++j) {
-        const float d = in_meas(T::elem(t, j)) ? cabs2(v[j]) - yv[j] : 0.f;  // zero outside the window
-        acc += d * d;
-        v[j] = cscale(v[j], d);
+        for (int j = 0; j < E; ++j) {
+          const bool in = in_meas(T::elem(t, j));  // zero residual outside the window
+          const float z2 = cabs2(v[j]);
+          if (a.loss_trace) acc += in ? poisson_term(z2, yv[j], a.loss_eps) : 0.f;
+          v[j] = cscale(v[j], in ? poisson_weight(z2, yv[j], a.loss_eps) : 0.f);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          const float d = in_meas(T::elem(t, j)) ? cabs2(v[j]) - yv[j] : 0.f;  // zero outside the window
+          acc += d * d;
+          v[j] = cscale(v[j], d);
+        }
       }
       if (a.loss_trace) {
         float tot = block_sum<NT>(acc, red);

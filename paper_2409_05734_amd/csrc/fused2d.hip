@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "launch.hpp"
+#include "loss.hpp"
 #include "plan.hpp"
 
 namespace sr {
@@ -52,6 +53,8 @@ struct F2Desc {
   float inv_m;
   int iters;
   int op;
+  int loss;          // GD: LOSS_L2 or LOSS_POISSON
+  float loss_eps;    // GD: Poisson guard
 };
 
 template <int N>
@@ -213,11 +216,13 @@ __device__ __noinline__ float f2_pass(const F2Desc* __restrict__ dp, float2* g, 
       } else if constexpr (KIND == F2P_TURN) {
         f2_fft<N, false>(v, w, t, active, g, idx);
         if (d.op == F2_GD) {
+          // residual weight of the plan's loss (no loss trace on this path)
+          if (d.loss == LOSS_POISSON) {
 #pragma unroll
-          for (int j = 0; j < E; ++j) {
-            const float r = cabs2(v[j]) - yv[j];
-            acc += r * r;
-            v[j] = cscale(v[j], r);
+            for (int j = 0; j < E; ++j) v[j] = cscale(v[j], poisson_weight(cabs2(v[j]), yv[j], d.loss_eps));
+          } else {
+#pragma unroll
+            for (int j = 0; j < E; ++j) v[j] = cscale(v[j], cabs2(v[j]) - yv[j]);
           }
         } else {
 #pragma unroll
@@ -458,6 +463,8 @@ static F2Desc f2_desc(const sr_plan_s* p, size_t i, int op, const float* y, floa
   d.inv_m = 1.f / (float)g.m;  // (not cropped: m is the grid size)
   d.iters = iters;
   d.op = op;
+  d.loss = p->loss;
+  d.loss_eps = p->loss_eps;
   return d;
 }
 

@@ -28,7 +28,8 @@ enum PassKind : int {
   // GD / spectral update fused with the next iteration's [U, D_1, F_0]
   PK_LAST_GD_FWD = 15,
   PK_LAST_SPEC_FWD = 16,
-  PK_COUNT = 17
+  PK_TURN_GD_POIS = 17,  // [F_a -> (1 - y/(|z|^2 + eps)) z -> F_a^H]  (Poisson loss)
+  PK_COUNT = 18
 };
 
 // Tile widths: each length is compiled for a few tile widths (transforms per

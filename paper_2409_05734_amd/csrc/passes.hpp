@@ -17,6 +17,7 @@
 // zero-padded support only touch the N_2 support columns ("compact" buffers).
 #pragma once
 #include "fft_core.hpp"
+#include "loss.hpp"
 
 namespace sr {
 
@@ -32,8 +33,12 @@ enum MidOp : int {
   MID_PHASE_SAVE = 6,       // u <- D v, save <- u                  (forward recompute)
   MID_PHASE_CONJ_GT = 7,    // gth += Im(v conj(save)), v <- D^* v   (forward VJP)
   MID_PHASE_CONJ_SAVE = 8,  // q <- D^* v, save <- q                (adjoint recompute)
-  MID_PHASE_GT = 9          // gth += Im(conj(v) save), v <- D v     (adjoint VJP)
+  MID_PHASE_GT = 9,         // gth += Im(conj(v) save), v <- D v     (adjoint VJP)
+  MID_GD_POIS = 10          // v <- (1 - y/(|v|^2 + eps)) v, Poisson loss partials
 };
+// The reverse-mode mid operations (phase diagonal with a saved intermediate).
+constexpr bool mid_rev_phase(int mid) { return mid >= MID_PHASE_SAVE && mid <= MID_PHASE_GT; }
+
 enum PostOp : int {
   POST_STORE = 0,
   POST_PHASE_CONJ_STORE = 1,
@@ -72,7 +77,7 @@ struct PassArgs {
   const float2* ep_post;
   float scale_pre, scale_mid, scale_out;
   // epilogues
-  const float* y;        // measurements on the grid (MID_GD, MID_SPEC)
+  const float* y;        // measurements on the window (MID_GD, MID_GD_POIS, MID_SPEC)
   const double* ysum;    // sum(y) (MID_SPEC)
   float inv_m;           // 1/m
   float lam;             // spectral threshold lambda
@@ -97,6 +102,7 @@ struct PassArgs {
   int win_lo0, win_hi0, win_lo1, win_hi1;
   long long win_ld;
   int crop;  // nonzero when the window is smaller than the grid (host: picks the window-aware kernels)
+  float loss_eps;  // Poisson loss guard (MID_GD_POIS)
 };
 
 // 1/sqrt of the sum of the previous iterate's squared-norm partials: strided
@@ -128,9 +134,9 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
                                           int npart, float* part_out) {
   using T = TileV<N, B, COL, DB, EV>;
   constexpr int E = T::E;
-  constexpr bool MID_PH = (MID == MID_PHASE || MID == MID_PHASE_CONJ || MID >= MID_PHASE_SAVE);
+  constexpr bool MID_PH = (MID == MID_PHASE || MID == MID_PHASE_CONJ || mid_rev_phase(MID));
   constexpr bool MID_SAVED = (MID == MID_PHASE_CONJ_GT || MID == MID_PHASE_GT);
-  constexpr bool MID_Y = (MID == MID_GD || MID == MID_SPEC);
+  constexpr bool MID_Y = (MID == MID_GD || MID == MID_GD_POIS || MID == MID_SPEC);
   constexpr bool POST_PH = (POST != POST_STORE);
   constexpr bool POST_X = (POST == POST_GD || POST == POST_SPEC || POST == POST_GD_FWD || POST == POST_SPEC_FWD);
   constexpr bool POST_FWD = (POST == POST_GD_FWD || POST == POST_SPEC_FWD);
@@ -252,7 +258,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
       const float2 d = cscale(dm[j], a.scale_mid);
       v[j] = (MID == MID_PHASE_CONJ) ? cmulc(v[j], d) : cmul(v[j], d);
     }
-  } else if constexpr (MID >= MID_PHASE_SAVE) {
+  } else if constexpr (mid_rev_phase(MID)) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int k = T::elem(t, j);
@@ -281,6 +287,20 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
       float d = in ? cabs2(z) - yv[j] : 0.f;  // zero residual outside the measurement window
       acc += d * d;
       v[j] = cscale(z, d);
+    }
+  } else if constexpr (MID == MID_GD_POIS) {
+    float z2[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const bool in = m_in(T::elem(t, j));
+      float2 z = cscale(v[j], a.scale_mid);
+      z2[j] = cabs2(z);
+      v[j] = cscale(z, in ? poisson_weight(z2[j], yv[j], a.loss_eps) : 0.f);
+    }
+    if (part_out != nullptr) {  // the logarithms only for a loss trace
+#pragma unroll
+      for (int j = 0; j < E; ++j)
+        acc += m_in(T::elem(t, j)) ? poisson_term(z2[j], yv[j], a.loss_eps) : 0.f;
     }
   } else if constexpr (MID == MID_SPEC) {
     const float ybar = (float)(*a.ysum * (double)a.inv_m);
@@ -340,7 +360,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
     }
   }
 
-  if constexpr (MID == MID_GD || POST_IS_SPEC) {
+  if constexpr (MID == MID_GD || MID == MID_GD_POIS || POST_IS_SPEC) {
     if (part_out != nullptr) {
       float sum = block_sum<T::THREADS>(acc, red);
       if (threadIdx.x == 0) part_out[tile] = sum;
@@ -351,7 +371,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
 // Whether a pass shape reads any phase diagonal.
 template <int PRE, int MID, int POST>
 constexpr bool pass_has_phase() {
-  return PRE == PRE_PHASE || MID == MID_PHASE || MID == MID_PHASE_CONJ || MID >= MID_PHASE_SAVE || POST != POST_STORE;
+  return PRE == PRE_PHASE || MID == MID_PHASE || MID == MID_PHASE_CONJ || mid_rev_phase(MID) || POST != POST_STORE;
 }
 
 // pass_tile with the phase source picked at run time (the tables are set

@@ -87,6 +87,8 @@ hipError_t dispatch(int kind, const PassArgs& a, hipStream_t s) {
       return go_w<N, B, COL, PRE_NONE, MID_STORE, false, false, false, POST_STORE>(a, s);
     case PK_TURN_GD:
       return go_w<N, B, COL, PRE_NONE, MID_GD, true, false, true, POST_STORE>(a, s);
+    case PK_TURN_GD_POIS:
+      return go_w<N, B, COL, PRE_NONE, MID_GD_POIS, true, false, true, POST_STORE>(a, s);
     case PK_TURN_SPEC:
       return go_w<N, B, COL, PRE_NONE, MID_SPEC, true, false, true, POST_STORE>(a, s);
     case PK_FIRST_ADJ:

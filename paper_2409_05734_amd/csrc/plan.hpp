@@ -86,6 +86,8 @@ struct sr_plan_s {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   int schedule = SR_SCHED_AUTO;
+  int loss = SR_LOSS_L2;  // GD loss (sr_plan_set_loss) and its Poisson guard
+  float loss_eps = 0.f;
   hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
   std::vector<std::pair<std::string, hipGraphExec_t>> graphs;  // captured solver chunks (most recent last)
   std::map<std::pair<int, int>, int> tiles;  // (FFT length, column mode) -> tuned tile width

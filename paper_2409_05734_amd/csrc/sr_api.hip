@@ -209,11 +209,14 @@ static sr_status adjoint_2d(sr_plan_s* p, const Geo& g, const float2* r, float2*
   return adjoint_body(p, g, p->bufA, PK_LAST_ADJ, x, 0.f, 0.f, nullptr, 0, nullptr);
 }
 
+// The turnaround pass of a GD iteration for the plan's loss.
+static int gd_turn_kind(const sr_plan_s* p) { return p->loss == SR_LOSS_POISSON ? PK_TURN_GD_POIS : PK_TURN_GD; }
+
 static sr_status gd_iter_2d(sr_plan_s* p, const Geo& g, const float* y, float2* x, float step, float* loss_part) {
   float2* cur = nullptr;
   SR_CHECK(forward_body(p, g, x, 1.f, nullptr, 0, &cur));
   float2* back = nullptr;
-  SR_CHECK(turnaround(p, g, cur, PK_TURN_GD, y, 0.f, nullptr, loss_part, &back));
+  SR_CHECK(turnaround(p, g, cur, gd_turn_kind(p), y, 0.f, nullptr, loss_part, &back));
   return adjoint_body(p, g, back, PK_LAST_GD, x, step, 0.f, nullptr, 0, nullptr);
 }
 
@@ -239,7 +242,7 @@ static sr_status gd_steady(sr_plan_s* p, const Geo& g, const float* y, float2* x
   float2* cur = nullptr;
   SR_CHECK(forward_rest(p, g, &cur));
   float2* back = nullptr;
-  SR_CHECK(turnaround(p, g, cur, PK_TURN_GD, y, 0.f, nullptr, loss_part, &back));
+  SR_CHECK(turnaround(p, g, cur, gd_turn_kind(p), y, 0.f, nullptr, loss_part, &back));
   return adjoint_body(p, g, back, last ? PK_LAST_GD : PK_LAST_GD_FWD, x, step, 0.f, nullptr, 0, nullptr,
                       last ? nullptr : p->bufA);
 }
@@ -408,7 +411,7 @@ static int persist_b() {
 }
 
 static bool use_persistent(const sr_plan_s* p, const Geo& g) {
-  if (p->schedule == SR_SCHED_LOOP) return false;
+  if (p->schedule == SR_SCHED_LOOP || p->loss != SR_LOSS_L2) return false;  // built for the l2 epilogue
   if (g.ndim != 2 || g.M1 != g.M2 || g.L > (kMaxPersistPasses - 1) / 2) return false;
   return persistent_supported(g.M1, persist_b());
 }
@@ -463,6 +466,8 @@ static Fused1DArgs args_1d(const sr_plan_s* p, const Geo& g, Fused1DArgs a) {
   a.moff = g.c1;
   a.theta = p->theta_l(g, 1);
   a.tw = p->twiddles(g.M1);
+  a.loss = p->loss;
+  a.loss_eps = p->loss_eps;
   return a;
 }
 
@@ -628,6 +633,16 @@ sr_status sr_plan_set_schedule(sr_plan p, int32_t schedule) {
   if (p == nullptr) return fail(SR_E_ARG, "NULL plan");
   if (schedule < SR_SCHED_AUTO || schedule > SR_SCHED_BATCHED) return fail(SR_E_ARG, "unknown schedule");
   p->schedule = schedule;
+  return SR_OK;
+}
+
+sr_status sr_plan_set_loss(sr_plan p, int32_t loss, float eps) {
+  if (p == nullptr) return fail(SR_E_ARG, "NULL plan");
+  if (loss != SR_LOSS_L2 && loss != SR_LOSS_POISSON) return fail(SR_E_ARG, "unknown loss");
+  if (loss == SR_LOSS_POISSON && !(std::isfinite(eps) && eps > 0.f))
+    return fail(SR_E_ARG, "the Poisson loss needs a finite eps > 0");
+  p->loss = loss;
+  p->loss_eps = loss == SR_LOSS_POISSON ? eps : 0.f;
   return SR_OK;
 }
 
