@@ -607,6 +607,46 @@ def accuracy_sweep(torch, srpr, sr_inputs, dev, side=32, reps=100, dense_groups=
     return out
 
 
+def poisson_loss(torch, srpr, sr_inputs, dev, iters=1000, time_iters=500, pi_iters=400):
+    """GD on the image workload (256^2 -> 512^2, L = 2, Poisson noise at 1000
+    photons) with the l2 intensity loss (mu = 0.05) and with the Poisson
+    negative log-likelihood (eta = mu / c, mu = 0.05, eps = 1e-2 mean(y)),
+    both from the same spectral start (400 power iterations: the headline's
+    100 leave the start unconverged at this size): cosine similarity after
+    `iters` steps and time per iteration."""
+    d = sr_inputs.image_2d(1)
+    n_shape, m_shape, L = d["n_shape"], d["m_shape"], d["layers"]
+    n, m = int(np.prod(n_shape)), int(np.prod(m_shape))
+    plan = srpr.Plan([srpr.Problem(n_shape, m_shape, L)], d["theta"])
+    s = plan.stream
+    y = make_measurements(torch, srpr, plan, d["x_star"], d["noise_rng"], d["photons"], dev)
+    ybar = float(y.double().mean().item())
+    v0 = torch.from_numpy(d["v0"].ravel()).to(dev)
+    x0 = torch.empty(n, dtype=torch.complex64, device=dev)
+    srpr.sr_spectral_init(plan, y, v0, pi_iters, d["lam"], x0)
+    xt = d["x_star"].ravel().astype(np.complex128)
+    out = {"workload": f"256^2 -> 512^2, L = 2, Poisson noise (1000 photons), {pi_iters} PI then {iters} GD"}
+    xh0 = x0.cpu().numpy().astype(np.complex128)
+    out["spectral_start_cosine"] = float(abs(np.vdot(xh0, xt)) / (np.linalg.norm(xh0) * np.linalg.norm(xt)))
+    x = torch.empty_like(x0)
+    for name, loss, eps, eta in (("l2", srpr.SR_LOSS_L2, 0.0, 0.05 * m / ybar),
+                                 ("poisson", srpr.SR_LOSS_POISSON, 1e-2 * ybar, 0.05 * m)):
+        srpr.sr_plan_set_loss(plan, loss, eps)
+
+        def solve(k):
+            x.copy_(x0)
+            srpr.sr_gd_solve(plan, y, x, k, float(eta))
+        ms = _time_calls(torch, s, lambda: solve(time_iters), 3, warm=1)
+        solve(iters)
+        torch.cuda.synchronize()
+        xh = x.cpu().numpy().astype(np.complex128)
+        with np.errstate(invalid="ignore"):
+            cos = float(abs(np.vdot(xh, xt)) / (np.linalg.norm(xh) * np.linalg.norm(xt)))
+        out[name] = {"gd_iteration_us": ms * 1e3 / time_iters, "cosine_similarity": cos}
+    srpr.sr_plan_set_loss(plan, srpr.SR_LOSS_L2)
+    return out
+
+
 def tiny_1d(torch, srpr, sr_inputs, dev):
     d = sr_inputs.tiny_1d(0)
     plan = srpr.Plan([srpr.Problem(d["n_shape"], d["m_shape"], d["layers"])], d["theta"])
@@ -683,7 +723,8 @@ def main():
         extras = {}
         side = (("large_2d", large_2d), ("dense_baseline", dense), ("batched", batched),
                 ("autograd", autograd), ("lds_resident_2d", lds_resident), ("forward_time_sweep", forward_time_sweep),
-                ("layer_study", layer_study), ("tiny_1d", tiny_1d), ("accuracy_sweep", accuracy_sweep))
+                ("layer_study", layer_study), ("poisson_loss", poisson_loss), ("tiny_1d", tiny_1d),
+                ("accuracy_sweep", accuracy_sweep))
         on_request = {"accuracy_sweep"}  # about a minute of GPU time: run only when named
         wanted = None if args.extras == "all" else set(args.extras.split(","))
         for name, fn in side:
