@@ -124,11 +124,12 @@ __global__ void __launch_bounds__(NT) dense_mm_kernel(const DenseArgs a) {
 
   auto load_chunk = [&](int k0) {
     if constexpr (G == 1) {
-      // A row i0 + tid/4, k = k0 + 16*(tid&3) .. +16
-      const int gi = i0 + (tid >> 2);
+      // A rows i0 + tid/16 + 16h, k = k0 + 4*(tid&15) .. +4: sixteen lanes read
+      // one row's 256 contiguous bytes
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
-        const int gk = k0 + (tid & 3) * 16 + 4 * h;
+        const int gi = i0 + (tid >> 4) + 16 * h;
+        const int gk = k0 + (tid & 15) * 4;
         f4 v = f4{0.f, 0.f, 0.f, 0.f};
         if (gi < M) {
           if (gk + 3 < kend) {
@@ -154,11 +155,11 @@ __global__ void __launch_bounds__(NT) dense_mm_kernel(const DenseArgs a) {
       br[2] = f4{xv[0].y, xv[0].x, xv[1].y, xv[1].x};
       br[3] = f4{xv[2].y, xv[2].x, xv[3].y, xv[3].x};
     } else {
-      // A row k = k0 + tid/4 (an m index), columns j = i0 + 16*(tid&3) .. +16
-      const int gk = k0 + (tid >> 2);
+      // A rows k = k0 + tid/16 + 16h (m indices), columns j = i0 + 4*(tid&15) .. +4
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
-        const int gj = i0 + (tid & 3) * 16 + 4 * h;
+        const int gk = k0 + (tid >> 4) + 16 * h;
+        const int gj = i0 + (tid & 15) * 4;
         f4 v = f4{0.f, 0.f, 0.f, 0.f};
         if (gk < kend) {
           if (gj + 3 < M) {
@@ -184,10 +185,10 @@ __global__ void __launch_bounds__(NT) dense_mm_kernel(const DenseArgs a) {
   };
 
   auto store_chunk = [&]() {
-    // A: natural layout in both products (rows tid/4, 16 consecutive floats)
+    // A: natural layout in both products (row tid/16 + 16h, 4 consecutive floats)
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
-      float* dst = G == 1 ? &As[tid >> 2][(tid & 3) * 16 + 4 * h] : &Bs[tid >> 2][(tid & 3) * 16 + 4 * h];
+      float* dst = G == 1 ? &As[(tid >> 4) + 16 * h][(tid & 15) * 4] : &Bs[(tid >> 4) + 16 * h][(tid & 15) * 4];
       *reinterpret_cast<f4*>(dst) = ar[h];
     }
     float(*S2)[PADK] = G == 1 ? Bs : As;
