@@ -103,6 +103,11 @@ struct PassArgs {
   long long win_ld;
   int crop;  // nonzero when the window is smaller than the grid (host: picks the window-aware kernels)
   float loss_eps;  // Poisson loss guard (MID_GD_POIS)
+  // stacked problems: one launch runs this pass for `stack` problems of one
+  // geometry; ntr counts the transforms of all of them, ntr_p those of one,
+  // and problem s's data sits s * s_<buffer> elements after problem 0's
+  int stack, ntr_p;
+  int s_in, s_out, s_out2, s_win, s_th, s_save, s_gth, s_xin;
 };
 
 // 1/sqrt of the sum of the previous iterate's squared-norm partials: strided
@@ -144,15 +149,24 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   constexpr bool POST_IS_SPEC = (POST == POST_SPEC || POST == POST_SPEC_FWD);
   const int t = T::thread_t();
   const int bl = T::thread_b();
-  const int b = tile * B + bl;
-  const bool active = b < a.ntr;
+  const int tb = tile * B + bl;  // transform index (over every problem of a stack)
+  const bool active = tb < a.ntr;
+  int b = tb, sp = 0;            // this lane's transform within its problem, and the problem
+  if (a.stack > 1) {
+    sp = tb / a.ntr_p;
+    b = tb - sp * a.ntr_p;
+  }
   const int gb = a.tr_lo + b;  // grid coordinate of this transform
   const int gld = (int)a.grid_ld, ild = (int)a.in_ld, old = (int)a.out_ld;
+  // the lane's problem's offset in each buffer (zero without a stack)
+  const int o_in = sp * a.s_in, o_out = sp * a.s_out, o_out2 = sp * a.s_out2, o_win = sp * a.s_win;
+  const int o_th = sp * a.s_th, o_sv = sp * a.s_save, o_gt = sp * a.s_gth, o_xin = sp * a.s_xin;
 
   // element offsets: grid position, input and output buffer positions
   auto gidx = [&](int k) -> int { return COL ? k * gld + gb : gb * gld + k; };
-  auto in_addr = [&](int k) -> int { return COL ? (k - a.in_lo) * ild + b : b * ild + (k - a.in_lo); };
-  auto out_addr = [&](int k) -> int { return COL ? (k - a.out_lo) * old + b : b * old + (k - a.out_lo); };
+  auto in_addr = [&](int k) -> int { return o_in + (COL ? (k - a.in_lo) * ild + b : b * ild + (k - a.in_lo)); };
+  auto out_rel = [&](int k) -> int { return COL ? (k - a.out_lo) * old + b : b * old + (k - a.out_lo); };
+  auto out_addr = [&](int k) -> int { return o_out + out_rel(k); };
   auto in_win = [&](int k) { return active && k >= a.in_lo && k < a.in_hi; };
   auto out_win = [&](int k) { return active && k >= a.out_lo && k < a.out_hi; };
   // measurement window: membership and index of grid element k of this
@@ -166,7 +180,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   const int m_khi = COL ? a.win_hi0 : a.win_hi1;
   const int m_base = COL ? (gb - a.win_lo1) - a.win_lo0 * wld : (gb - a.win_lo0) * wld - a.win_lo1;
   auto m_in = [&](int k) { return WIN ? m_lane && k >= m_klo && k < m_khi : active; };
-  auto m_idx = [&](int k) -> int { return WIN ? (COL ? m_base + k * wld : m_base + k) : gidx(k); };
+  auto m_idx = [&](int k) -> int { return o_win + (WIN ? (COL ? m_base + k * wld : m_base + k) : gidx(k)); };
   // the adjoint's first pass ([F_a^H] alone) reads its input on the window
   constexpr bool IN_WIN = WIN && (PRE == PRE_NONE && MID == MID_NONE && !FFT2 && INV1 && POST == POST_STORE);
 
@@ -193,8 +207,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   for (int j = 0; j < E; ++j) {
     const int k = T::elem(t, j);
     const bool iw = in_win(k);
-    const int g = gidx(k);
-    if constexpr (IN_WIN) v[j] = ld2(r_in, off8(m_in(k), m_idx(k)));
+    const int g = gidx(k) + o_th;  // phase index
+    if constexpr (IN_WIN) v[j] = ld2(r_in, off8(m_in(k), m_idx(k) - o_win + o_in));
     else v[j] = ld2(r_in, off8(iw, in_addr(k)));
     if constexpr (PRE == PRE_PHASE) {
       if constexpr (TAB) dp[j] = ld2(r_pre, off8(iw, g));
@@ -206,8 +220,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
     }
     if constexpr (MID_Y) yv[j] = ld1(r_y, off4(m_in(k), m_idx(k)));
     if constexpr (MID_SAVED) {
-      sv[j] = ld2(r_save, off8(active, g));
-      gt[j] = ld1(r_gth, off4(active, g));
+      sv[j] = ld2(r_save, off8(active, g - o_th + o_sv));
+      gt[j] = ld1(r_gth, off4(active, g - o_th + o_gt));
     }
     if constexpr (MID != MID_STORE) {
       const bool ow = out_win(k);
@@ -217,8 +231,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
       }
       if constexpr (POST_X) xo[j] = ld2(r_out, off8(ow, out_addr(k)));
       if constexpr (POST == POST_PHASE_CONJ_GT) {
-        xo[j] = ld2(rsrc(a.xin), off8(ow, out_addr(k)));
-        gt[j] = ld1(r_gth, off4(ow, g));
+        xo[j] = ld2(rsrc(a.xin), off8(ow, o_xin + out_rel(k)));
+        gt[j] = ld1(r_gth, off4(ow, g - o_th + o_gt));
       }
     }
   }
@@ -262,7 +276,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int k = T::elem(t, j);
-      const unsigned go8 = off8(active, gidx(k)), go4 = off4(active, gidx(k));
+      const unsigned go8 = off8(active, gidx(k) + o_sv), go4 = off4(active, gidx(k) + o_gt);
       const float2 u = cscale(v[j], a.scale_mid);
       if constexpr (MID == MID_PHASE_SAVE) {
         v[j] = cmul(u, dm[j]);
@@ -333,7 +347,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
       float2 val = cscale(v[j], a.scale_out);
       if constexpr (POST == POST_PHASE_CONJ_GT) {
         const float2 u1 = cmul(xo[j], dq[j]);  // u_1 = D_1 U x at this position
-        st1(r_gth, off4(ow, gidx(k)), gt[j] + (val.y * u1.x - val.x * u1.y));
+        st1(r_gth, off4(ow, gidx(k) + o_gt), gt[j] + (val.y * u1.x - val.x * u1.y));
       }
       if constexpr (POST_PH) val = cmulc(val, dq[j]);
       if constexpr (POST_IS_GD) {
@@ -356,7 +370,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int k = T::elem(t, j);
-      st2(r_o2, off8(active, k * o2ld + b), cscale(v[j], s1));
+      st2(r_o2, off8(active, o_out2 + k * o2ld + b), cscale(v[j], s1));
     }
   }
 

@@ -205,6 +205,8 @@ sr_plan_s::~sr_plan_s() {
   if (f1_args) hipFree(f1_args);
   if (cap_stream) hipStreamDestroy(cap_stream);
   if (vjp_buf) hipFree(vjp_buf);
+  if (stk_buf) hipFree(stk_buf);
+  if (stk_gth) hipFree(stk_gth);
   if (batch) sr::destroy_batch_state(batch);
   if (ws) hipFree(ws);
 }

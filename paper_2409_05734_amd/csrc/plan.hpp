@@ -38,6 +38,38 @@ sr_status hip_fail(hipError_t e, const char* what);
 namespace sr {
 struct BatchState;
 void destroy_batch_state(BatchState* s);
+
+// A stack of problems of one geometry run as one: every fused pass of the
+// first problem's schedule is launched once for all P problems, each buffer
+// the pass touches registered with its per-problem stride (problem s's data
+// sits s * stride elements after problem 0's).
+struct StackRegion {
+  uintptr_t lo, hi;  // problem 0's bytes
+  int stride;        // elements between consecutive problems
+};
+struct StackState {
+  int P = 1;          // problems in the stack (1: no stack)
+  int th_stride = 0;  // elements between the problems' phase blocks (0: shared)
+  std::vector<StackRegion> regions;
+  void add(const void* base, size_t elems, size_t elem_bytes, int stride) {
+    const uintptr_t lo = (uintptr_t)base;
+    regions.push_back({lo, lo + elems * elem_bytes, stride});
+  }
+  // stride of the buffer `ptr` points into; false if no region holds it
+  bool stride_of(const void* ptr, int* stride) const {
+    if (ptr == nullptr) {
+      *stride = 0;
+      return true;
+    }
+    const uintptr_t q = (uintptr_t)ptr;
+    for (const StackRegion& r : regions)
+      if (q >= r.lo && q < r.hi) {
+        *stride = r.stride;
+        return true;
+      }
+    return false;
+  }
+};
 }  // namespace sr
 
 struct sr_plan_s {
@@ -70,6 +102,11 @@ struct sr_plan_s {
   unsigned* sync = nullptr;   // [0] grid-barrier counter, [1] barrier error flag
   double* red_ws = nullptr;   // per-workgroup partials of the two-stage reductions (kRedGroups)
   float2* vjp_buf = nullptr;  // per-layer intermediates for derivatives (allocated on first use)
+  sr::StackState stk;         // the stack being run (P = 1 outside stacked calls)
+  float2* stk_buf = nullptr;  // stacked ping-pong buffers (allocated on first stacked call)
+  size_t stk_elems = 0;
+  float* stk_gth = nullptr;   // per-problem phase cotangents of a stack sharing its phases
+  size_t stk_gth_elems = 0;
   sr::BatchState* batch = nullptr;  // batched-schedule state (built on first batched solve)
   size_t vjp_elems = 0;
 

@@ -93,6 +93,70 @@ inline void out_full(PassArgs& a, const Geo& g, int k, float2* buf) {
   a.out_hi = pass_len(g, k);
 }
 
+// Problems of one 2D geometry whose phase blocks are equal (shared masks) or
+// evenly spaced without overlap run as a stack: every fused pass is one
+// launch for all of them.  Returns the stack size (1: the plan does not
+// qualify) and the spacing of the phase blocks.  SR_STACK=0 turns it off.
+inline int stack_size(const sr_plan_s* p, int* th_stride) {
+  const size_t np = p->geo.size();
+  if (p->kind != SR_STRUCTURED || np < 2 || p->schedule == SR_SCHED_LOOP) return 1;
+  const char* env = std::getenv("SR_STACK");
+  if (env != nullptr && std::atoi(env) == 0) return 1;
+  const Geo& g0 = p->geo[0];
+  if (g0.ndim != 2) return 1;
+  const int64_t d = p->geo[1].th_off - g0.th_off;
+  const int64_t block = (int64_t)g0.L * g0.mg;
+  if (d < 0 || (d != 0 && d < block)) return 1;
+  for (size_t i = 0; i < np; ++i) {
+    const Geo& g = p->geo[i];
+    if (g.ndim != 2 || g.N1 != g0.N1 || g.N2 != g0.N2 || g.M1 != g0.M1 || g.M2 != g0.M2 || g.W1 != g0.W1 ||
+        g.W2 != g0.W2 || g.L != g0.L || g.th_off != g0.th_off + (int64_t)i * d)
+      return 1;
+  }
+  // every offset inside a stacked buffer stays well within 32-bit byte offsets
+  const int64_t lim = (int64_t)1 << 26;
+  if ((int64_t)np * std::max<int64_t>(block, std::max<int64_t>(g0.mg, d)) >= lim) return 1;
+  *th_stride = (int)d;
+  return (int)np;
+}
+
+// The plan's ping-pong buffers for a stack of P problems (P grids each).
+inline sr_status ensure_stack_bufs(sr_plan_s* p, size_t elems) {
+  if (elems <= p->stk_elems) return SR_OK;
+  if (p->stk_buf) {
+    hipStreamSynchronize(p->stream);
+    hipFree(p->stk_buf);
+    p->stk_buf = nullptr;
+    p->stk_elems = 0;
+  }
+  hipError_t e = hipMalloc(&p->stk_buf, elems * sizeof(float2));
+  if (e != hipSuccess) return fail(SR_E_NOMEM, "stacked workspace allocation failed");
+  p->stk_elems = elems;
+  return SR_OK;
+}
+
+// Runs a stack for the lifetime of the object: the plan's ping-pong buffers
+// are the stacked ones (registered with stride mg), restored afterwards.
+struct StackScope {
+  sr_plan_s* p;
+  float2 *a0, *b0;
+  StackScope(sr_plan_s* pl, int P, int th_stride) : p(pl), a0(pl->bufA), b0(pl->bufB) {
+    const Geo& g = p->geo[0];
+    p->stk.P = P;
+    p->stk.th_stride = th_stride;
+    p->stk.regions.clear();
+    p->bufA = p->stk_buf;
+    p->bufB = p->stk_buf + (size_t)P * g.mg;
+    p->stk.add(p->bufA, g.mg, sizeof(float2), (int)g.mg);
+    p->stk.add(p->bufB, g.mg, sizeof(float2), (int)g.mg);
+  }
+  ~StackScope() {
+    p->bufA = a0;
+    p->bufB = b0;
+    p->stk = StackState{};
+  }
+};
+
 // Launch one fused pass, or, while a persistent schedule is being recorded,
 // append it to the recording instead.
 struct PassRecord {
@@ -113,6 +177,19 @@ inline sr_status launch(sr_plan_s* p, const Geo& g, int k, int kind, const PassA
     a.ep_pre = table_of(p, a.th_pre);
     a.ep_mid = table_of(p, a.th_mid);
     a.ep_post = table_of(p, a.th_post);
+  }
+  if (p->stk.P > 1) {  // one launch for the whole stack
+    a.stack = p->stk.P;
+    a.ntr_p = a.ntr;
+    a.ntr *= p->stk.P;
+    a.s_th = p->stk.th_stride;
+    int sy = 0, sz = 0, syo = 0;
+    const StackState& st = p->stk;
+    if (!st.stride_of(a.in, &a.s_in) || !st.stride_of(a.out, &a.s_out) || !st.stride_of(a.out2, &a.s_out2) ||
+        !st.stride_of(a.save, &a.s_save) || !st.stride_of(a.gth, &a.s_gth) || !st.stride_of(a.xin, &a.s_xin) ||
+        !st.stride_of(a.y, &sy) || !st.stride_of(a.z_out, &sz) || !st.stride_of(a.y_out, &syo))
+      return fail(SR_E_STATE, "stacked pass: a buffer without a per-problem stride");
+    a.s_win = std::max(sy, std::max(sz, syo));  // measurement-shaped buffers share one stride
   }
   if (g_recording != nullptr) {
     g_recording->push_back({k, kind, a});

@@ -666,12 +666,36 @@ sr_status sr_plan_destroy(sr_plan p) {
   return SR_OK;
 }
 
+// A x for a stack of problems (stack_size > 1): problem 0's schedule, each
+// pass launched once for all of them.
+static sr_status forward_stacked(sr_plan_s* p, int P, int ths, const float2* x, float2* z, float* y) {
+  const Geo& g = p->geo[0];
+  SR_CHECK(ensure_stack_bufs(p, 2 * (size_t)P * g.mg));
+  StackScope sc(p, P, ths);
+  p->stk.add(x, g.n, sizeof(float2), (int)g.n);
+  if (z) p->stk.add(z, g.m, sizeof(float2), (int)g.m);
+  if (y) p->stk.add(y, g.m, sizeof(float), (int)g.m);
+  return forward_2d(p, g, x, z, y);
+}
+
+static sr_status adjoint_stacked(sr_plan_s* p, int P, int ths, const float2* r, float2* x) {
+  const Geo& g = p->geo[0];
+  SR_CHECK(ensure_stack_bufs(p, 2 * (size_t)P * g.mg));
+  StackScope sc(p, P, ths);
+  p->stk.add(r, g.m, sizeof(float2), (int)g.m);
+  p->stk.add(x, g.n, sizeof(float2), (int)g.n);
+  return adjoint_2d(p, g, r, x);
+}
+
 sr_status sr_forward(sr_plan p, const void* x, void* z, float* y) {
   if (p == nullptr || x == nullptr) return fail(SR_E_ARG, "NULL argument");
   if (z == nullptr && y == nullptr) return fail(SR_E_ARG, "need z or y");
   const float2* xs = (const float2*)x;
   float2* zs = (float2*)z;
   if (p->kind == SR_DENSE) return dense_forward(p, xs, zs, y);
+  int ths = 0;
+  const int P = stack_size(p, &ths);
+  if (P > 1) return forward_stacked(p, P, ths, xs, zs, y);
   Batch1D b1;
   for (size_t i = 0; i < p->geo.size(); ++i) {
     const Geo& g = p->geo[i];
@@ -696,6 +720,9 @@ sr_status sr_adjoint(sr_plan p, const void* r, void* x_out) {
   const float2* rs = (const float2*)r;
   float2* xs = (float2*)x_out;
   if (p->kind == SR_DENSE) return dense_adjoint(p, rs, xs);
+  int ths = 0;
+  const int P = stack_size(p, &ths);
+  if (P > 1) return adjoint_stacked(p, P, ths, rs, xs);
   Batch1D b1;
   for (size_t i = 0; i < p->geo.size(); ++i) {
     const Geo& g = p->geo[i];

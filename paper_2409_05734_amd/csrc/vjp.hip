@@ -23,21 +23,33 @@ namespace sr {
 
 namespace {
 
-// gth_1[support] += Im(conj(gv) v) for the adjoint derivative's first layer
+// gth_1[support] += Im(conj(gv) v) for the adjoint derivative's first layer,
+// for P stacked problems (problem s: gv, v at s n, gth at s gth_stride)
 __global__ void gth_support_kernel(const float2* __restrict__ gv, const float2* __restrict__ v, float* gth, int N1,
-                                   int N2, int o1, int o2, long long M2) {
+                                   int N2, int o1, int o2, long long M2, int P, long long gth_stride) {
   const long long n = (long long)N1 * N2;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(e / N2), j = (int)(e % N2);
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n * P; e += (long long)gridDim.x * blockDim.x) {
+    const long long s = e / n, l = e - s * n;
+    const int i = (int)(l / N2), j = (int)(l % N2);
     const float2 a = gv[e], b = v[e];
-    gth[(long long)(o1 + i) * M2 + (o2 + j)] += a.x * b.y - a.y * b.x;
+    gth[s * gth_stride + (long long)(o1 + i) * M2 + (o2 + j)] += a.x * b.y - a.y * b.x;
   }
 }
 
-sr_status ensure_vjp_buf(sr_plan_s* p) {
+// gth[e] += sum over the stack of part[s * len + e], added in problem order
+// (the order of a problem-by-problem loop)
+__global__ void gth_reduce_kernel(const float* __restrict__ part, float* gth, long long len, int P) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < len; e += (long long)gridDim.x * blockDim.x) {
+    float acc = gth[e];
+    for (int s = 0; s < P; ++s) acc += part[(long long)s * len + e];
+    gth[e] = acc;
+  }
+}
+
+sr_status ensure_vjp_buf(sr_plan_s* p, int P = 1) {
   size_t need = 0;
   for (const Geo& g : p->geo)
-    if (g.ndim == 2) need = std::max(need, (size_t)std::max(g.L - 1, 1) * (size_t)g.mg + (size_t)g.n);
+    if (g.ndim == 2) need = std::max(need, (size_t)P * ((size_t)std::max(g.L - 1, 1) * (size_t)g.mg + (size_t)g.n));
   if (need <= p->vjp_elems) return SR_OK;
   if (p->vjp_buf) {
     hipStreamSynchronize(p->stream);
@@ -51,11 +63,17 @@ sr_status ensure_vjp_buf(sr_plan_s* p) {
   return SR_OK;
 }
 
-// save buffer of layer k (k = 2..L) and an n-sized scratch after them
-float2* save_of(sr_plan_s* p, const Geo& g, int k) { return p->vjp_buf + (size_t)(k - 2) * g.mg; }
-float2* nscratch(sr_plan_s* p, const Geo& g) { return p->vjp_buf + (size_t)std::max(g.L - 1, 1) * g.mg; }
+// save buffer of layer k (k = 2..L) and an n-sized scratch after them (for
+// a stack: P grids per layer, then P signals)
+float2* save_of(sr_plan_s* p, const Geo& g, int k) { return p->vjp_buf + (size_t)(k - 2) * p->stk.P * g.mg; }
+float2* nscratch(sr_plan_s* p, const Geo& g) {
+  return p->vjp_buf + (size_t)std::max(g.L - 1, 1) * p->stk.P * g.mg;
+}
 
+// phase cotangents of layer l: the caller's array, or, for a stack sharing
+// its phases, problem 0's block of the per-problem scratch
 float* gth_of(const sr_plan_s* p, const Geo& g, float* gtheta, int l) {
+  if (p->stk.P > 1 && p->stk.th_stride == 0) return p->stk_gth + (int64_t)(l - 1) * g.mg;
   return gtheta + g.th_off + (int64_t)(l - 1) * g.mg;
 }
 
@@ -167,7 +185,109 @@ sr_status adj_passes(sr_plan_s* p, const Geo& g, const float2* r, int kind_mid, 
 
 }  // namespace
 
+namespace {
+
+// Stack set-up shared by both derivatives: buffers, the registered
+// per-problem strides of the intermediates and of the phase cotangents, and
+// the zeroed per-problem scratch when the stack shares its phases.
+sr_status stack_vjp_setup(sr_plan_s* p, int P, float* gtheta) {
+  const Geo& g = p->geo[0];
+  for (int k = 2; k <= g.L; ++k) p->stk.add(save_of(p, g, k), g.mg, sizeof(float2), (int)g.mg);
+  p->stk.add(nscratch(p, g), g.n, sizeof(float2), (int)g.n);
+  const size_t block = (size_t)g.L * g.mg;
+  if (p->stk.th_stride == 0) {
+    const size_t need = (size_t)P * block;
+    if (need > p->stk_gth_elems) {
+      if (p->stk_gth) {
+        hipStreamSynchronize(p->stream);
+        hipFree(p->stk_gth);
+        p->stk_gth = nullptr;
+        p->stk_gth_elems = 0;
+      }
+      if (hipMalloc(&p->stk_gth, need * sizeof(float)) != hipSuccess)
+        return fail(SR_E_NOMEM, "stacked derivative workspace allocation failed");
+      p->stk_gth_elems = need;
+    }
+    hipError_t e = hipMemsetAsync(p->stk_gth, 0, need * sizeof(float), p->stream);
+    if (e != hipSuccess) return hip_fail(e, "stacked derivative workspace clear");
+    p->stk.add(p->stk_gth, block, sizeof(float), (int)block);
+  } else {
+    p->stk.add(gtheta + g.th_off, block, sizeof(float), p->stk.th_stride);
+  }
+  return SR_OK;
+}
+
+// a stack sharing its phases: add the per-problem cotangents in problem order
+sr_status stack_vjp_finish(sr_plan_s* p, int P, float* gtheta) {
+  if (p->stk.th_stride != 0) return SR_OK;
+  const Geo& g = p->geo[0];
+  const long long len = (long long)g.L * g.mg;
+  const int groups = (int)std::min<long long>((len + 255) / 256, 2048);
+  hipLaunchKernelGGL(gth_reduce_kernel, dim3(groups), dim3(256), 0, p->stream, p->stk_gth, gtheta + g.th_off, len, P);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SR_OK : hip_fail(e, "gth_reduce");
+}
+
+sr_status vjp_forward_stacked(sr_plan_s* p, int P, int ths, const float2* x, const float2* gz, float2* gx,
+                              float* gtheta) {
+  const Geo& g = p->geo[0];
+  VJ_CHECK(ensure_stack_bufs(p, 2 * (size_t)P * g.mg));
+  VJ_CHECK(ensure_vjp_buf(p, P));
+  StackScope sc(p, P, ths);
+  VJ_CHECK(stack_vjp_setup(p, P, gtheta));
+  p->stk.add(x, g.n, sizeof(float2), (int)g.n);
+  p->stk.add(gz, g.m, sizeof(float2), (int)g.m);
+  if (gx) p->stk.add(gx, g.n, sizeof(float2), (int)g.n);
+  float2* gxi = gx ? gx : nscratch(p, g);
+  float2* cur = nullptr;
+  if (g.L >= 2) VJ_CHECK(fwd_passes(p, g, x, PK_MID_FWD_SAVE, gtheta, &cur));
+  VJ_CHECK(adj_passes(p, g, gz, PK_MID_ADJ_GT, PK_LAST_ADJ_GT, gtheta, x, gxi));
+  return stack_vjp_finish(p, P, gtheta);
+}
+
+sr_status vjp_adjoint_stacked(sr_plan_s* p, int P, int ths, const float2* r, const float2* gv, float2* gr,
+                              float* gtheta) {
+  const Geo& g = p->geo[0];
+  VJ_CHECK(ensure_stack_bufs(p, 2 * (size_t)P * g.mg));
+  VJ_CHECK(ensure_vjp_buf(p, P));
+  StackScope sc(p, P, ths);
+  VJ_CHECK(stack_vjp_setup(p, P, gtheta));
+  p->stk.add(r, g.m, sizeof(float2), (int)g.m);
+  p->stk.add(gv, g.n, sizeof(float2), (int)g.n);
+  if (gr) p->stk.add(gr, g.m, sizeof(float2), (int)g.m);
+  float2* v = nscratch(p, g);
+  VJ_CHECK(adj_passes(p, g, r, PK_MID_ADJ_SAVE, PK_LAST_ADJ, gtheta, nullptr, v));
+  {
+    const long long n = g.n * P;
+    const int groups = (int)std::min<long long>((n + 255) / 256, 1024);
+    int sg = 0;
+    p->stk.stride_of(gth_of(p, g, gtheta, 1), &sg);
+    hipLaunchKernelGGL(gth_support_kernel, dim3(groups), dim3(256), 0, p->stream, gv, v, gth_of(p, g, gtheta, 1),
+                       g.N1, g.N2, g.o1, g.o2, (long long)g.M2, P, (long long)sg);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "gth_support");
+  }
+  float2* cur = nullptr;
+  VJ_CHECK(fwd_passes(p, g, gv, PK_MID_FWD_GT, gtheta, &cur));
+  if (gr != nullptr) {
+    const int k = g.L + 1;
+    PassArgs a = base_args(p, g, k);
+    set_in(a, g, k, cur);
+    a.scale_mid = 1.f / std::sqrt((float)pass_len(g, k));
+    a.z_out = gr;
+    VJ_CHECK(launch(p, g, k, PK_LAST_STORE, a));
+  }
+  return stack_vjp_finish(p, P, gtheta);
+}
+
+}  // namespace
+
 sr_status vjp_forward(sr_plan_s* p, const float2* x, const float2* gz, float2* gx, float* gtheta) {
+  {
+    int ths = 0;
+    const int P = stack_size(p, &ths);
+    if (P > 1) return vjp_forward_stacked(p, P, ths, x, gz, gx, gtheta);
+  }
   VJ_CHECK(ensure_vjp_buf(p));
   for (size_t i = 0; i < p->geo.size(); ++i) {
     const Geo& g = p->geo[i];
@@ -191,6 +311,11 @@ sr_status vjp_forward(sr_plan_s* p, const float2* x, const float2* gz, float2* g
 }
 
 sr_status vjp_adjoint(sr_plan_s* p, const float2* r, const float2* gv, float2* gr, float* gtheta) {
+  {
+    int ths = 0;
+    const int P = stack_size(p, &ths);
+    if (P > 1) return vjp_adjoint_stacked(p, P, ths, r, gv, gr, gtheta);
+  }
   VJ_CHECK(ensure_vjp_buf(p));
   for (size_t i = 0; i < p->geo.size(); ++i) {
     const Geo& g = p->geo[i];
@@ -213,7 +338,7 @@ sr_status vjp_adjoint(sr_plan_s* p, const float2* r, const float2* gv, float2* g
       const long long n = g.n;
       const int groups = (int)std::min<long long>((n + 255) / 256, 1024);
       hipLaunchKernelGGL(gth_support_kernel, dim3(groups), dim3(256), 0, p->stream, gvi, v, gth_of(p, g, gtheta, 1),
-                         g.N1, g.N2, g.o1, g.o2, (long long)g.M2);
+                         g.N1, g.N2, g.o1, g.o2, (long long)g.M2, 1, 0LL);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return hip_fail(e, "gth_support");
     }
