@@ -336,6 +336,39 @@ def batched(torch, srpr, sr_inputs, dev, iters=300):
             "max_err_gap_finite": float(np.max(np.abs((eb - el)[np.isfinite(eb) & np.isfinite(el)])))}
 
 
+def stacked_gd(torch, srpr, sr_inputs, dev, count=16, iters=300):
+    """A uniform batch at the headline shape (256^2 -> 512^2, L = 2, each
+    problem with its own masks and step): every pass launched once for the
+    whole stack against the problem-by-problem loop."""
+    rng = np.random.default_rng(17)
+    n_shape, m_shape, L = (256, 256), (512, 512), 2
+    n, m = 256 * 256, 512 * 512
+    theta = rng.uniform(0, 2 * np.pi, (count, L) + m_shape).astype(np.float32)
+    plan = srpr.Plan([srpr.Problem(n_shape, m_shape, L, theta_offset=i * L * m) for i in range(count)], theta.ravel())
+    xs = torch.from_numpy(np.concatenate([sr_inputs.complex_gaussian(rng, n_shape).ravel()
+                                          for _ in range(count)])).to(dev)
+    y = torch.empty(plan.m_total, dtype=torch.float32, device=dev)
+    srpr.sr_forward(plan, xs, None, y)
+    x0 = (xs + 0.5 * torch.randn_like(xs)).contiguous()
+    ym = y.reshape(count, m).double().mean(dim=1).cpu().numpy()
+    eta = (0.2 * m / ym).astype(np.float32)
+    x = torch.empty_like(x0)
+
+    def run():
+        x.copy_(x0)
+        srpr.sr_gd_solve(plan, y, x, iters, eta)
+    s_ms = _time_calls(torch, plan.stream, run, 3, warm=1)
+    xa = x.clone()
+    srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_LOOP)
+    l_ms = _time_calls(torch, plan.stream, run, 2, warm=1)
+    byt = count * schedule_bytes_gd(n_shape, m_shape, L)
+    return {"workload": f"{count} problems 256^2 -> 512^2, L=2, own masks and steps, {iters} GD steps",
+            "stacked_ms": s_ms, "loop_ms": l_ms, "speedup_vs_loop": l_ms / s_ms,
+            "stacked_problem_iters_per_s": count * iters / (s_ms * 1e-3),
+            "stacked_GBps": byt * iters / (s_ms * 1e-3) / 1e9,
+            "bit_identical_to_loop": bool(torch.equal(xa, x))}
+
+
 def autograd(torch, srpr, sr_inputs, dev):
     from paper_2409_05734_amd.autograd import unrolled_gd_loss
     d = sr_inputs.mask_design(3)
@@ -390,8 +423,12 @@ def lds_resident(torch, srpr, sr_inputs, dev, count=512, iters=300):
     x = torch.empty_like(x0)
     out = {"workload": f"{count} problems 32^2 -> 64^2, L=2, {iters} GD steps from x* + CN(0, 1/4)"}
     finals = {}
-    for key, env in (("lds_resident_ms", "1"), ("levels_ms", "0")):
-        os.environ["SR_LDS_RESIDENT"] = env
+    for key, env in (("lds_resident_ms", "1"), ("levels_ms", "0"), ("stacked_ms", None)):
+        if env is None:  # the default schedule of a uniform plan: each pass once for the whole stack
+            os.environ.pop("SR_LDS_RESIDENT", None)
+            srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_AUTO)
+        else:
+            os.environ["SR_LDS_RESIDENT"] = env
 
         def run():
             x.copy_(x0)
@@ -402,6 +439,8 @@ def lds_resident(torch, srpr, sr_inputs, dev, count=512, iters=300):
     a, b = finals["lds_resident_ms"], finals["levels_ms"]
     out["rel_diff_between_schedules"] = float(((a - b).abs().pow(2).sum() / b.abs().pow(2).sum()).sqrt())
     out["speedup_vs_levels"] = out["levels_ms"] / out["lds_resident_ms"]
+    out["rel_diff_stacked_vs_levels"] = float(((finals["stacked_ms"] - b).abs().pow(2).sum()
+                                               / b.abs().pow(2).sum()).sqrt())
     return out
 
 
@@ -722,7 +761,7 @@ def main():
     if not args.quick:
         extras = {}
         side = (("large_2d", large_2d), ("dense_baseline", dense), ("batched", batched),
-                ("autograd", autograd), ("lds_resident_2d", lds_resident), ("forward_time_sweep", forward_time_sweep),
+                ("stacked_gd", stacked_gd), ("autograd", autograd), ("lds_resident_2d", lds_resident), ("forward_time_sweep", forward_time_sweep),
                 ("layer_study", layer_study), ("poisson_loss", poisson_loss), ("tiny_1d", tiny_1d),
                 ("accuracy_sweep", accuracy_sweep))
         on_request = {"accuracy_sweep"}  # about a minute of GPU time: run only when named

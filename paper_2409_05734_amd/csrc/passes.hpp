@@ -108,6 +108,7 @@ struct PassArgs {
   // and problem s's data sits s * s_<buffer> elements after problem 0's
   int stack, ntr_p;
   int s_in, s_out, s_out2, s_win, s_th, s_save, s_gth, s_xin;
+  const float* step_v;  // GD update of a stack: each problem's step (nullable: `step` for all)
 };
 
 // 1/sqrt of the sum of the previous iterate's squared-norm partials: strided
@@ -340,6 +341,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   if constexpr (FFT2) T::template fft<INV2>(v, lds, ph, w, t, bl);
 
   if constexpr (MID != MID_STORE) {
+    float step = a.step;
+    if constexpr (POST_IS_GD) {
+      if (a.step_v != nullptr && active) step = a.step_v[sp];
+    }
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int k = T::elem(t, j);
@@ -351,7 +356,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
       }
       if constexpr (POST_PH) val = cmulc(val, dq[j]);
       if constexpr (POST_IS_GD) {
-        val = make_float2(xo[j].x - a.step * val.x, xo[j].y - a.step * val.y);
+        val = make_float2(xo[j].x - step * val.x, xo[j].y - step * val.y);
       } else if constexpr (POST_IS_SPEC) {
         val = make_float2(s_prev * (a.step * val.x - a.two_lam * xo[j].x),
                           s_prev * (a.step * val.y - a.two_lam * xo[j].y));

@@ -50,6 +50,7 @@ struct StackRegion {
 struct StackState {
   int P = 1;          // problems in the stack (1: no stack)
   int th_stride = 0;  // elements between the problems' phase blocks (0: shared)
+  const float* steps = nullptr;  // device: each problem's GD step (GD on a stack)
   std::vector<StackRegion> regions;
   void add(const void* base, size_t elems, size_t elem_bytes, int stride) {
     const uintptr_t lo = (uintptr_t)base;
@@ -107,6 +108,8 @@ struct sr_plan_s {
   size_t stk_elems = 0;
   float* stk_gth = nullptr;   // per-problem phase cotangents of a stack sharing its phases
   size_t stk_gth_elems = 0;
+  float* stk_steps = nullptr;          // device: per-problem GD steps of a stack
+  std::vector<float> stk_steps_host;   // their upload's source (kept alive while it is in flight)
   sr::BatchState* batch = nullptr;  // batched-schedule state (built on first batched solve)
   size_t vjp_elems = 0;
 

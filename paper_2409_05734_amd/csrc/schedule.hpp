@@ -190,6 +190,7 @@ inline sr_status launch(sr_plan_s* p, const Geo& g, int k, int kind, const PassA
         !st.stride_of(a.y, &sy) || !st.stride_of(a.z_out, &sz) || !st.stride_of(a.y_out, &syo))
       return fail(SR_E_STATE, "stacked pass: a buffer without a per-problem stride");
     a.s_win = std::max(sy, std::max(sz, syo));  // measurement-shaped buffers share one stride
+    a.step_v = p->stk.steps;
   }
   if (g_recording != nullptr) {
     g_recording->push_back({k, kind, a});

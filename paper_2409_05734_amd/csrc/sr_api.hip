@@ -738,6 +738,46 @@ sr_status sr_adjoint(sr_plan p, const void* r, void* x_out) {
   return flush_1d(p, F1_ADJOINT, b1);
 }
 
+// GD on a stack (no loss trace): problem 0's schedule, each pass launched
+// once for all problems, each with its own step.
+static sr_status gd_stacked(sr_plan_s* p, int P, int ths, const float* y, float2* x, int iters,
+                            const float* eta_host) {
+  const Geo& g = p->geo[0];
+  SR_CHECK(ensure_stack_bufs(p, 2 * (size_t)P * g.mg));
+  if (p->stk_steps_host.size() < (size_t)P) {
+    if (p->stk_steps) {
+      SR_HIP(hipStreamSynchronize(p->stream));
+      SR_HIP(hipFree(p->stk_steps));
+      p->stk_steps = nullptr;
+    }
+    SR_HIP(hipMalloc(&p->stk_steps, sizeof(float) * P));
+  } else {
+    SR_HIP(hipStreamSynchronize(p->stream));  // the previous upload has left the host array
+  }
+  p->stk_steps_host.assign(P, 0.f);
+  for (int i = 0; i < P; ++i) p->stk_steps_host[i] = eta_host[i] / (float)p->geo[i].m;
+  SR_HIP(hipMemcpyAsync(p->stk_steps, p->stk_steps_host.data(), sizeof(float) * P, hipMemcpyHostToDevice,
+                        p->stream));
+  StackScope sc(p, P, ths);
+  p->stk.steps = p->stk_steps;
+  p->stk.add(x, g.n, sizeof(float2), (int)g.n);
+  p->stk.add(y, g.m, sizeof(float), (int)g.m);
+  const float step = p->stk_steps_host[0];  // (unused by the stacked update, which reads the array)
+  SR_CHECK(first_pass(p, g, x, 1.f, nullptr, 0));
+  int it = 0;
+  if (graphs_enabled(p) && iters - 1 >= kGraphChunk) {
+    const std::string key = "gdstack:" + std::to_string(P) + ":" + ptr_key(y) + ":" + ptr_key(x) + ":" +
+                            ptr_key(p->stk_buf) + ":" + ptr_key(p->stk_steps);
+    for (; it + kGraphChunk <= iters - 1; it += kGraphChunk)
+      SR_CHECK(launch_captured(p, key, [&]() -> sr_status {
+        for (int c = 0; c < kGraphChunk; ++c) SR_CHECK(gd_steady(p, g, y, x, step, nullptr, false));
+        return SR_OK;
+      }));
+  }
+  for (; it < iters; ++it) SR_CHECK(gd_steady(p, g, y, x, step, nullptr, it == iters - 1));
+  return SR_OK;
+}
+
 sr_status sr_gd_solve(sr_plan p, const float* y, void* x_inout, int32_t iters, const float* eta_host,
                       float* loss_trace) {
   if (p == nullptr || y == nullptr || x_inout == nullptr || eta_host == nullptr)
@@ -748,6 +788,13 @@ sr_status sr_gd_solve(sr_plan p, const float* y, void* x_inout, int32_t iters, c
   if (iters == 0) return SR_OK;
   float2* xs = (float2*)x_inout;
   if (p->kind == SR_DENSE) return dense_gd(p, y, xs, iters, eta_host, loss_trace);
+  // a uniform plan runs as one stack (unless the level launches or the
+  // LDS-resident solver are asked for)
+  if (p->schedule == SR_SCHED_AUTO && loss_trace == nullptr && !fused2d_enabled(false)) {
+    int ths = 0;
+    const int P = stack_size(p, &ths);
+    if (P > 1) return gd_stacked(p, P, ths, y, xs, iters, eta_host);
+  }
   const bool want_batched = p->schedule == SR_SCHED_BATCHED || (p->schedule == SR_SCHED_AUTO && p->geo.size() >= 8);
   if (want_batched && loss_trace == nullptr && batched_supported(p)) return batched_gd(p, y, xs, iters, eta_host);
   Batch1D b1;
