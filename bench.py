@@ -357,16 +357,28 @@ def stacked_gd(torch, srpr, sr_inputs, dev, count=16, iters=300):
     def run():
         x.copy_(x0)
         srpr.sr_gd_solve(plan, y, x, iters, eta)
+    v0 = torch.randn_like(xs)
+    est = torch.empty_like(xs)
+
+    def run_spec():
+        srpr.sr_spectral_init(plan, y, v0, iters, -1.0, est)
     s_ms = _time_calls(torch, plan.stream, run, 3, warm=1)
     xa = x.clone()
+    s_spec_ms = _time_calls(torch, plan.stream, run_spec, 3, warm=1)
+    ea = est.clone()
     srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_LOOP)
     l_ms = _time_calls(torch, plan.stream, run, 2, warm=1)
+    l_spec_ms = _time_calls(torch, plan.stream, run_spec, 2, warm=1)
     byt = count * schedule_bytes_gd(n_shape, m_shape, L)
-    return {"workload": f"{count} problems 256^2 -> 512^2, L=2, own masks and steps, {iters} GD steps",
+    return {"workload": f"{count} problems 256^2 -> 512^2, L=2, own masks and steps, {iters} GD steps; "
+                        f"{iters} power iterations",
             "stacked_ms": s_ms, "loop_ms": l_ms, "speedup_vs_loop": l_ms / s_ms,
             "stacked_problem_iters_per_s": count * iters / (s_ms * 1e-3),
             "stacked_GBps": byt * iters / (s_ms * 1e-3) / 1e9,
-            "bit_identical_to_loop": bool(torch.equal(xa, x))}
+            "bit_identical_to_loop": bool(torch.equal(xa, x)),
+            "spectral_stacked_ms": s_spec_ms, "spectral_loop_ms": l_spec_ms,
+            "spectral_speedup_vs_loop": l_spec_ms / s_spec_ms,
+            "spectral_bit_identical_to_loop": bool(torch.equal(ea, est))}
 
 
 def autograd(torch, srpr, sr_inputs, dev):

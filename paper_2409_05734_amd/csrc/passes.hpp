@@ -251,7 +251,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   float s_prev = 1.f;  // 1/||u_prev|| for the spectral update
   if constexpr (PRE == PRE_PHASE || POST_IS_SPEC) {  // the only shapes that take the previous norm
     if (part_in != nullptr) {
-      s_prev = inv_norm_from_partials<T::THREADS>(part_in, npart);
+      // a stack keeps each problem's partials together (npart apiece), and
+      // a pass that reads them has whole problems in each tile
+      const float* pin = a.stack > 1 ? part_in + (tile * B / a.ntr_p) * npart : part_in;
+      s_prev = inv_norm_from_partials<T::THREADS>(pin, npart);
       if (PRE == PRE_PHASE) s_pre *= s_prev;
     }
   }
@@ -318,7 +321,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
         acc += m_in(T::elem(t, j)) ? poisson_term(z2[j], yv[j], a.loss_eps) : 0.f;
     }
   } else if constexpr (MID == MID_SPEC) {
-    const float ybar = (float)(*a.ysum * (double)a.inv_m);
+    const float ybar = (float)(a.ysum[active ? sp : 0] * (double)a.inv_m);  // the problem's sum(y) (a stack: one each)
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       float2 z = cscale(v[j], a.scale_mid);

@@ -208,6 +208,7 @@ sr_plan_s::~sr_plan_s() {
   if (stk_buf) hipFree(stk_buf);
   if (stk_gth) hipFree(stk_gth);
   if (stk_steps) hipFree(stk_steps);
+  if (stk_part) hipFree(stk_part);
   if (batch) sr::destroy_batch_state(batch);
   if (ws) hipFree(ws);
 }

@@ -108,6 +108,8 @@ struct sr_plan_s {
   size_t stk_elems = 0;
   float* stk_gth = nullptr;   // per-problem phase cotangents of a stack sharing its phases
   size_t stk_gth_elems = 0;
+  float* stk_part = nullptr;           // squared-norm partials of a stacked spectral solve (2 sets)
+  size_t stk_part_elems = 0;
   float* stk_steps = nullptr;          // device: per-problem GD steps of a stack
   std::vector<float> stk_steps_host;   // their upload's source (kept alive while it is in flight)
   sr::BatchState* batch = nullptr;  // batched-schedule state (built on first batched solve)
@@ -147,10 +149,11 @@ namespace sr {
 
 // util_kernels.hip
 sr_status reduce_partials(sr_plan_s* p, const float* part, int n, float* out);
-sr_status sum_floats(sr_plan_s* p, const float* y, int64_t n, double* out);
-sr_status norm2_partial(sr_plan_s* p, const float2* x, int64_t n, float* out);
+// (count > 1: that many arrays of n elements end to end, each on its own)
+sr_status sum_floats(sr_plan_s* p, const float* y, int64_t n, double* out, int count = 1);
+sr_status norm2_partial(sr_plan_s* p, const float2* x, int64_t n, float* out, int count = 1);
 sr_status final_scale(sr_plan_s* p, float2* x, int64_t n, const float* part, int npart, const double* ysum,
-                      float inv_mc);
+                      float inv_mc, int count = 1);
 sr_status fill_phase_table(sr_plan_s* p);
 
 // dense.hip (i.i.d. complex Gaussian baseline)

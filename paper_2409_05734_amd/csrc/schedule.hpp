@@ -135,6 +135,20 @@ inline sr_status ensure_stack_bufs(sr_plan_s* p, size_t elems) {
   return SR_OK;
 }
 
+inline sr_status ensure_stack_parts(sr_plan_s* p, size_t elems) {
+  if (elems <= p->stk_part_elems) return SR_OK;
+  if (p->stk_part) {
+    hipStreamSynchronize(p->stream);
+    hipFree(p->stk_part);
+    p->stk_part = nullptr;
+    p->stk_part_elems = 0;
+  }
+  hipError_t e = hipMalloc(&p->stk_part, elems * sizeof(float));
+  if (e != hipSuccess) return fail(SR_E_NOMEM, "stacked partial-sum allocation failed");
+  p->stk_part_elems = elems;
+  return SR_OK;
+}
+
 // Runs a stack for the lifetime of the object: the plan's ping-pong buffers
 // are the stacked ones (registered with stride mg), restored afterwards.
 struct StackScope {
@@ -191,6 +205,12 @@ inline sr_status launch(sr_plan_s* p, const Geo& g, int k, int kind, const PassA
       return fail(SR_E_STATE, "stacked pass: a buffer without a per-problem stride");
     a.s_win = std::max(sy, std::max(sz, syo));  // measurement-shaped buffers share one stride
     a.step_v = p->stk.steps;
+    if (a.part_in != nullptr || a.part_out != nullptr) {  // per-problem partial sums: whole problems per tile
+      int bt = p->tile(pass_len(g, k), pass_col(k));
+      if (bt <= 0) bt = default_tile(pass_len(g, k), pass_col(k));
+      bt &= kSingleBuffer - 1;
+      if (a.ntr_p % bt != 0) return fail(SR_E_STATE, "stacked pass with partial sums: a tile spans two problems");
+    }
   }
   if (g_recording != nullptr) {
     g_recording->push_back({k, kind, a});

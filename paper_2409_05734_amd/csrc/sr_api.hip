@@ -838,6 +838,64 @@ sr_status sr_gd_solve(sr_plan p, const float* y, void* x_inout, int32_t iters, c
   return flush_1d(p, F1_GD, b1);
 }
 
+// Whether a stack's spectral passes keep each tile inside one problem (the
+// passes that read and write per-problem norm partials need it).
+static bool stack_spectral_ok(const sr_plan_s* p, const Geo& g) {
+  int bt = p->tile(g.M1, true);
+  if (bt <= 0) bt = default_tile(g.M1, true);
+  bt &= kSingleBuffer - 1;
+  return g.N2 % bt == 0;
+}
+
+// Power iteration on a stack: problem 0's schedule, each pass launched once
+// for all problems; each problem keeps its own sum(y) and norm partials.
+static sr_status spectral_stacked(sr_plan_s* p, int P, int ths, const float* y, const float2* v0, int iters,
+                                  float lambda, float2* x) {
+  const Geo& g = p->geo[0];
+  const float inv_mc = (float)((double)g.mg / (double)g.m);
+  const int nq = last_pass_groups(p, g);
+  const size_t pstride = (size_t)P * (size_t)std::max(nq, 1);
+  SR_CHECK(ensure_stack_bufs(p, 2 * (size_t)P * g.mg));
+  SR_CHECK(ensure_stack_parts(p, 2 * pstride));
+  float* parts[2] = {p->stk_part, p->stk_part + pstride};
+  // sum(y) and the start vector's squared norm, per problem (one partial each)
+  SR_HIP(hipMemcpyAsync(x, v0, sizeof(float2) * g.n * P, hipMemcpyDeviceToDevice, p->stream));
+  SR_CHECK(sum_floats(p, y, g.m, p->ysum, P));
+  SR_CHECK(norm2_partial(p, x, g.n, parts[0], P));
+  int npart = 1;
+  {
+    StackScope sc(p, P, ths);
+    p->stk.add(x, g.n, sizeof(float2), (int)g.n);
+    p->stk.add(y, g.m, sizeof(float), (int)g.m);
+    int it = 0;
+    if (iters > 0) SR_CHECK(first_pass(p, g, x, 1.f, nullptr, 0));
+    if (iters > 1) {
+      SR_CHECK(spec_steady(p, g, y, x, lambda, inv_mc, p->ysum, parts[0], npart, parts[1], false));
+      npart = nq;
+      it = 1;
+    }
+    if (graphs_enabled(p) && iters - 1 - it >= kGraphChunk) {
+      const std::string key = "specstack:" + std::to_string(P) + ":" + ptr_key(y) + ":" + ptr_key(x) + ":" +
+                              ptr_key(p->stk_buf) + ":" + ptr_key(p->stk_part) + ":" + float_key(lambda);
+      for (; it + kGraphChunk <= iters - 1; it += kGraphChunk)
+        SR_CHECK(launch_captured(p, key, [&]() -> sr_status {
+          for (int c = 0; c < kGraphChunk; ++c) {
+            const int q = it + c;
+            SR_CHECK(spec_steady(p, g, y, x, lambda, inv_mc, p->ysum, parts[q & 1], nq, parts[(q + 1) & 1], false));
+          }
+          return SR_OK;
+        }));
+    }
+    for (; it < iters; ++it) {
+      SR_CHECK(spec_steady(p, g, y, x, lambda, inv_mc, p->ysum, parts[it & 1], npart, parts[(it + 1) & 1],
+                           it == iters - 1));
+      npart = nq;
+    }
+  }
+  // x0 = sqrt(sum(y)/(m c)) u / ||u||, per problem
+  return final_scale(p, x, g.n, parts[iters & 1], npart, p->ysum, inv_mc, P);
+}
+
 sr_status sr_spectral_init(sr_plan p, const float* y, const void* v0, int32_t iters, float lambda, void* x0_out) {
   if (p == nullptr || y == nullptr || v0 == nullptr || x0_out == nullptr) return fail(SR_E_ARG, "NULL argument");
   if (iters < 0) return fail(SR_E_ARG, "iters must be >= 0");
@@ -846,6 +904,13 @@ sr_status sr_spectral_init(sr_plan p, const float* y, const void* v0, int32_t it
   const float2* vs = (const float2*)v0;
   float2* xs = (float2*)x0_out;
   if (p->kind == SR_DENSE) return dense_spectral(p, y, vs, iters, lambda, xs);
+  // a uniform plan runs as one stack (unless the LDS-resident solver is
+  // asked for by name, or the level launches are)
+  if (p->schedule == SR_SCHED_AUTO && !fused2d_enabled(false)) {
+    int ths = 0;
+    const int P = stack_size(p, &ths);
+    if (P > 1 && stack_spectral_ok(p, p->geo[0])) return spectral_stacked(p, P, ths, y, vs, iters, lambda, xs);
+  }
   // batched plans: problems whose grid fits one workgroup's LDS run their
   // whole iteration in the LDS-resident solver (by default: the others run
   // one problem after another), beside the others' passes

@@ -39,9 +39,12 @@ __global__ void reduce_partials_kernel(const float* __restrict__ part, int n, fl
 constexpr int kRedGroups = 1024;
 constexpr int kRedStage1 = 256;
 
+// (blockIdx.y: one of several equal-length arrays laid end to end)
 __global__ void __launch_bounds__(kRedStage1) sum_floats_stage1(const float* __restrict__ y, long long n,
                                                                 long long chunk, double* part) {
   __shared__ double red[kRedStage1];
+  y += blockIdx.y * n;
+  part += blockIdx.y * gridDim.x;
   const long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
   double acc = 0.0;
   for (long long i = lo + threadIdx.x; i < hi; i += kRedStage1) acc += (double)y[i];
@@ -52,6 +55,8 @@ __global__ void __launch_bounds__(kRedStage1) sum_floats_stage1(const float* __r
 __global__ void __launch_bounds__(kRedStage1) norm2_stage1(const float2* __restrict__ x, long long n, long long chunk,
                                                            double* part) {
   __shared__ double red[kRedStage1];
+  x += blockIdx.y * n;
+  part += blockIdx.y * gridDim.x;
   const long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
   double acc = 0.0;
   for (long long i = lo + threadIdx.x; i < hi; i += kRedStage1) {
@@ -63,12 +68,14 @@ __global__ void __launch_bounds__(kRedStage1) norm2_stage1(const float2* __restr
 }
 
 // stage 2: out = sum of part[0..g) in index order; as double or as float
-__global__ void reduce_stage2(const double* __restrict__ part, int g, double* out_d, float* out_f) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+// (thread t: the t-th of `count` arrays, whose partials follow one another)
+__global__ void reduce_stage2(const double* __restrict__ part, int g, double* out_d, float* out_f, int count) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) {
     double acc = 0.0;
-    for (int i = 0; i < g; ++i) acc += part[i];
-    if (out_d) *out_d = acc;
-    if (out_f) *out_f = (float)acc;
+    for (int i = 0; i < g; ++i) acc += part[(long long)t * g + i];
+    if (out_d) out_d[t] = acc;
+    if (out_f) out_f[t] = (float)acc;
   }
 }
 
@@ -81,8 +88,12 @@ void red_shape(long long n, int* groups, long long* chunk) {
 }
 
 // x *= sqrt(sum(y) * inv_mc) / ||x||, ||x||^2 = sum of the partials
+// (blockIdx.y: one of several problems, each with its x, partials and sum)
 __global__ void final_scale_kernel(float2* x, long long n, const float* __restrict__ part, int npart,
                                    const double* __restrict__ ysum, float inv_mc) {
+  x += blockIdx.y * n;
+  part += blockIdx.y * npart;
+  ysum += blockIdx.y;
   double acc = 0.0;
   for (int i = 0; i < npart; ++i) acc += (double)part[i];
   const float sc = (float)(sqrt(*ysum * (double)inv_mc) / sqrt(acc));
@@ -113,31 +124,46 @@ sr_status reduce_partials(sr_plan_s* p, const float* part, int n, float* out) {
   return e == hipSuccess ? SR_OK : hip_fail(e, "reduce_partials");
 }
 
-sr_status sum_floats(sr_plan_s* p, const float* y, int64_t n, double* out) {
+// `count` arrays of n elements laid end to end, each reduced on its own (the
+// same chunks and order as alone), as many per launch as the kRedGroups
+// stage-1 partials hold.
+sr_status sum_floats(sr_plan_s* p, const float* y, int64_t n, double* out, int count) {
   int g;
   long long chunk;
   red_shape(n, &g, &chunk);
-  hipLaunchKernelGGL(sum_floats_stage1, dim3(g), dim3(kRedStage1), 0, p->stream, y, (long long)n, chunk, p->red_ws);
-  hipLaunchKernelGGL(reduce_stage2, dim3(1), dim3(64), 0, p->stream, p->red_ws, g, out, (float*)nullptr);
+  const int per = std::max(1, kRedGroups / g);
+  for (int c0 = 0; c0 < count; c0 += per) {
+    const int c = std::min(per, count - c0);
+    hipLaunchKernelGGL(sum_floats_stage1, dim3(g, c), dim3(kRedStage1), 0, p->stream, y + (int64_t)c0 * n,
+                       (long long)n, chunk, p->red_ws);
+    hipLaunchKernelGGL(reduce_stage2, dim3((c + 63) / 64), dim3(64), 0, p->stream, p->red_ws, g, out + c0,
+                       (float*)nullptr, c);
+  }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SR_OK : hip_fail(e, "sum_floats");
 }
 
-sr_status norm2_partial(sr_plan_s* p, const float2* x, int64_t n, float* out) {
+sr_status norm2_partial(sr_plan_s* p, const float2* x, int64_t n, float* out, int count) {
   int g;
   long long chunk;
   red_shape(n, &g, &chunk);
-  hipLaunchKernelGGL(norm2_stage1, dim3(g), dim3(kRedStage1), 0, p->stream, x, (long long)n, chunk, p->red_ws);
-  hipLaunchKernelGGL(reduce_stage2, dim3(1), dim3(64), 0, p->stream, p->red_ws, g, (double*)nullptr, out);
+  const int per = std::max(1, kRedGroups / g);
+  for (int c0 = 0; c0 < count; c0 += per) {
+    const int c = std::min(per, count - c0);
+    hipLaunchKernelGGL(norm2_stage1, dim3(g, c), dim3(kRedStage1), 0, p->stream, x + (int64_t)c0 * n, (long long)n,
+                       chunk, p->red_ws);
+    hipLaunchKernelGGL(reduce_stage2, dim3((c + 63) / 64), dim3(64), 0, p->stream, p->red_ws, g, (double*)nullptr,
+                       out + c0, c);
+  }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SR_OK : hip_fail(e, "norm2");
 }
 
 sr_status final_scale(sr_plan_s* p, float2* x, int64_t n, const float* part, int npart, const double* ysum,
-                      float inv_mc) {
+                      float inv_mc, int count) {
   int groups = (int)std::min<int64_t>((n + 255) / 256, 1024);
-  hipLaunchKernelGGL(final_scale_kernel, dim3(groups), dim3(256), 0, p->stream, x, (long long)n, part, npart, ysum,
-                     inv_mc);
+  hipLaunchKernelGGL(final_scale_kernel, dim3(groups, count), dim3(256), 0, p->stream, x, (long long)n, part, npart,
+                     ysum, inv_mc);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SR_OK : hip_fail(e, "final_scale");
 }

@@ -147,3 +147,47 @@ def test_stacked_gd_matches_loop_and_oracle(gpu, n_shape, m_shape, L, P, shared)
         for i in (0, P - 1):
             xr = oracle.gd_solve(ops[i], ys[i], x0s[i], k, float(etas[i]))
             assert aligned(xh[i * n:(i + 1) * n].reshape(n_shape), xr) <= 1e-4, (i, k)
+
+
+@pytest.mark.parametrize("force", [None, "2,1,1"])
+@pytest.mark.parametrize("n_shape,m_shape,L,P,shared", CASES)
+def test_stacked_spectral_matches_loop_and_oracle(gpu, monkeypatch, n_shape, m_shape, L, P, shared, force):
+    """Power iteration on a stack (each problem with its own sum(y) and norm
+    partials): bit-identical to the problem-by-problem loop (1 and 6
+    iterations, and past one replayed graph chunk), first and last problems
+    within 1e-4 of the oracle (Eq. (3)-(4)).  A stack runs it only where the
+    last pass's tiles hold whole problems (support columns a multiple of the
+    column tile): with the default tiles, some of these shapes fall back to
+    the loop; with two-column tiles, all of them stack."""
+    import torch
+    import paper_2409_05734_amd as srpr
+    if force is not None:
+        monkeypatch.setenv("SR_TUNE_FORCE", force)
+    rng = np.random.default_rng(hash((n_shape, m_shape, L, P, "spec")) % 2**32)
+    g = _grid(n_shape, m_shape)
+    nblk = 1 if shared else P
+    th_blocks = [rng.uniform(0, 2 * np.pi, (L,) + g).astype(np.float32) for _ in range(nblk)]
+    ops, ys, v0s = [], [], []
+    for i in range(P):
+        op = oracle.StructuredOperator(th_blocks[0 if shared else i], n_shape, m_shape)
+        ops.append(op)
+        ys.append((np.abs(op.A(sr_inputs.complex_gaussian(rng, n_shape))) ** 2).astype(np.float32))
+        v0s.append(sr_inputs.complex_gaussian(rng, n_shape))
+    yd = to_dev(np.concatenate([y.ravel() for y in ys]), gpu)
+    v0 = to_dev(np.concatenate([v.ravel() for v in v0s]), gpu)
+    plans = {s: _plan(n_shape, m_shape, L, P, shared, th_blocks, s) for s in (srpr.SR_SCHED_AUTO, srpr.SR_SCHED_LOOP)}
+    n = int(np.prod(n_shape))
+    for k in (1, 6, 60):
+        out = {}
+        for s, plan in plans.items():
+            x = torch.empty_like(v0)
+            srpr.sr_spectral_init(plan, yd, v0, k, -1.0, x)
+            srpr.sr_plan_sync(plan)
+            out[s] = x
+        assert torch.equal(out[srpr.SR_SCHED_AUTO], out[srpr.SR_SCHED_LOOP]), k
+        if k == 60:
+            continue
+        xh = to_host(out[srpr.SR_SCHED_AUTO])
+        for i in (0, P - 1):
+            xr = oracle.spectral_init(ops[i], ys[i], v0s[i], k, -1.0)
+            assert rel_l2(xh[i * n:(i + 1) * n].reshape(n_shape), xr) <= 1e-4, (i, k)
