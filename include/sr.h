@@ -66,8 +66,16 @@ typedef enum {
   SR_LOSS_POISSON = 1      /* Poisson negative log-likelihood of the intensities (see sr_plan_set_loss) */
 } sr_loss;
 
+/* SR_SCHED_AUTO: a structured plan whose problems share one 2D geometry
+ * (phase blocks all one block, or evenly spaced at least one block apart) runs
+ * as a stack: each fused pass of every problem in one launch, with results
+ * bitwise equal to SR_SCHED_LOOP (A, A^H, both VJPs, GD without a loss trace,
+ * and power iteration where the support-column count is a multiple of the
+ * column tile); the first stacked call allocates two grids per problem (plus
+ * small per-problem arrays) beside the workspace, kept until sr_plan_destroy.
+ * Other plans of 8 or more problems take the batched launches.             */
 typedef enum {
-  SR_SCHED_AUTO = 0,       /* library's choice */
+  SR_SCHED_AUTO = 0,       /* library's choice (above) */
   SR_SCHED_LOOP = 1,       /* one problem after another, one launch per fused pass */
   SR_SCHED_BATCHED = 2     /* all problems together (persistent batched launches) */
 } sr_schedule;
