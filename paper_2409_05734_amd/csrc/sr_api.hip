@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -278,7 +279,9 @@ static int turn_groups(const sr_plan_s* p, const Geo& g) {
 // steady-state GD iteration of each 2D problem shape for every combination of
 // the compiled column- and row-tile widths and phase sources (on zeroed
 // stand-in data in the plan's spare buffers; best of three runs), keeping the
-// fastest.  SR_TUNE=0 keeps the defaults;
+// fastest.  A plan that runs as a stack is timed as a stack: there the
+// bandwidth of the wider tiles beats the latency of the narrower ones that a
+// single problem prefers.  SR_TUNE=0 keeps the defaults;
 // SR_TUNE_CACHE=<file> reuses and records decisions across processes.
 
 static std::string tune_key(const Geo& g) {
@@ -340,10 +343,36 @@ static sr_status tune_plan(sr_plan_s* p) {
   const char* env = std::getenv("SR_TUNE");
   if (env != nullptr && std::atoi(env) == 0) return SR_OK;
   const char* cache = std::getenv("SR_TUNE_CACHE");
+  // a plan that runs as a stack is timed as one (up to 2^23 grid points:
+  // enough to fill the GPU), on zeroed stand-ins of that many problems
+  int ths = 0;
+  const int P_all = stack_size(p, &ths);
+  const int P = P_all > 1 ? std::max(2, std::min<int>(P_all, (int)((1 << 23) / p->geo[0].mg))) : 1;
+  float2* st_x = nullptr;
+  float* st_y = nullptr;
+  if (P > 1) {
+    const Geo& g = p->geo[0];
+    SR_CHECK(ensure_stack_bufs(p, 2 * (size_t)P * g.mg));
+    SR_HIP(hipMalloc(&st_x, sizeof(float2) * g.n * P));
+    SR_HIP(hipMalloc(&st_y, sizeof(float) * g.m * P));
+    SR_HIP(hipMemsetAsync(st_x, 0, sizeof(float2) * g.n * P, p->stream));
+    SR_HIP(hipMemsetAsync(st_y, 0, sizeof(float) * g.m * P, p->stream));
+  }
+  struct Standins {  // released once the timings are done
+    sr_plan_s* p;
+    float2* x;
+    float* y;
+    ~Standins() {
+      if (x == nullptr && y == nullptr) return;
+      hipStreamSynchronize(p->stream);
+      if (x) hipFree(x);
+      if (y) hipFree(y);
+    }
+  } standins{p, st_x, st_y};
   std::vector<std::string> done;
   for (const Geo& g : p->geo) {
     if (g.ndim != 2) continue;
-    const std::string key = tune_key(g);
+    const std::string key = tune_key(g) + (P > 1 ? ":stack" + std::to_string(P) : std::string());
     if (std::find(done.begin(), done.end(), key) != done.end()) continue;
     done.push_back(key);
     if (p->tiles.count({g.M1, 1}) && p->tiles.count({g.M2, 0})) continue;  // decided by an earlier shape
@@ -356,8 +385,14 @@ static sr_status tune_plan(sr_plan_s* p) {
       hipEvent_t e0, e1;
       SR_HIP(hipEventCreate(&e0));
       SR_HIP(hipEventCreate(&e1));
-      float2* x = p->bufC;
-      const float* y = (const float*)p->bufD;
+      float2* x = P > 1 ? st_x : p->bufC;
+      const float* y = P > 1 ? st_y : (const float*)p->bufD;
+      std::unique_ptr<StackScope> scope;
+      if (P > 1) {
+        scope.reset(new StackScope(p, P, ths));
+        p->stk.add(x, g.n, sizeof(float2), (int)g.n);
+        p->stk.add(y, g.m, sizeof(float), (int)g.m);
+      }
       const char* tab_env = std::getenv("SR_PHASE_TABLE");
       const int tab_lo = tab_env ? std::atoi(tab_env) : 0;
       const int tab_hi = tab_env ? std::atoi(tab_env) : 1;
