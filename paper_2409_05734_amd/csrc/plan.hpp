@@ -111,7 +111,7 @@ struct sr_plan_s {
   float* stk_part = nullptr;           // squared-norm partials of a stacked spectral solve (2 sets)
   size_t stk_part_elems = 0;
   float* stk_steps = nullptr;          // device: per-problem GD steps of a stack
-  std::vector<float> stk_steps_host;   // their upload's source (kept alive while it is in flight)
+  int stk_steps_cap = 0;
   sr::BatchState* batch = nullptr;  // batched-schedule state (built on first batched solve)
   size_t vjp_elems = 0;
 
@@ -155,6 +155,9 @@ sr_status norm2_partial(sr_plan_s* p, const float2* x, int64_t n, float* out, in
 sr_status final_scale(sr_plan_s* p, float2* x, int64_t n, const float* part, int npart, const double* ysum,
                       float inv_mc, int count = 1);
 sr_status fill_phase_table(sr_plan_s* p);
+// count host floats into device memory, stream-ordered, through kernel
+// arguments (the host array is free on return; no wait on the stream)
+sr_status put_floats(sr_plan_s* p, float* dst, const float* host, int count);
 
 // dense.hip (i.i.d. complex Gaussian baseline)
 size_t dense_split_floats(int m, int n, int nb);

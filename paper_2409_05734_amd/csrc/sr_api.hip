@@ -779,25 +779,24 @@ static sr_status gd_stacked(sr_plan_s* p, int P, int ths, const float* y, float2
                             const float* eta_host) {
   const Geo& g = p->geo[0];
   SR_CHECK(ensure_stack_bufs(p, 2 * (size_t)P * g.mg));
-  if (p->stk_steps_host.size() < (size_t)P) {
+  if (p->stk_steps_cap < P) {
     if (p->stk_steps) {
-      SR_HIP(hipStreamSynchronize(p->stream));
+      SR_HIP(hipStreamSynchronize(p->stream));  // queued work may still read the old array
       SR_HIP(hipFree(p->stk_steps));
       p->stk_steps = nullptr;
+      p->stk_steps_cap = 0;
     }
-    SR_HIP(hipMalloc(&p->stk_steps, sizeof(float) * P));
-  } else {
-    SR_HIP(hipStreamSynchronize(p->stream));  // the previous upload has left the host array
+    if (hipMalloc(&p->stk_steps, sizeof(float) * P) != hipSuccess) return fail(SR_E_NOMEM, "step array allocation failed");
+    p->stk_steps_cap = P;
   }
-  p->stk_steps_host.assign(P, 0.f);
-  for (int i = 0; i < P; ++i) p->stk_steps_host[i] = eta_host[i] / (float)p->geo[i].m;
-  SR_HIP(hipMemcpyAsync(p->stk_steps, p->stk_steps_host.data(), sizeof(float) * P, hipMemcpyHostToDevice,
-                        p->stream));
+  std::vector<float> steps(P);
+  for (int i = 0; i < P; ++i) steps[i] = eta_host[i] / (float)p->geo[i].m;
+  SR_CHECK(put_floats(p, p->stk_steps, steps.data(), P));
   StackScope sc(p, P, ths);
   p->stk.steps = p->stk_steps;
   p->stk.add(x, g.n, sizeof(float2), (int)g.n);
   p->stk.add(y, g.m, sizeof(float), (int)g.m);
-  const float step = p->stk_steps_host[0];  // (unused by the stacked update, which reads the array)
+  const float step = steps[0];  // (unused by the stacked update, which reads the array)
   SR_CHECK(first_pass(p, g, x, 1.f, nullptr, 0));
   int it = 0;
   if (graphs_enabled(p) && iters - 1 >= kGraphChunk) {

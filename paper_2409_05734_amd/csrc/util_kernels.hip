@@ -3,6 +3,9 @@
 // of the spectral estimate (section II-B.2, Eq. (4)).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
+
 #include "fft_core.hpp"
 #include "plan.hpp"
 
@@ -107,7 +110,29 @@ __global__ void phase_table_kernel(const float* __restrict__ th, long long n, fl
     out[i] = phase<false>(th[i], 1.f);
 }
 
+// dst[i] = v.v[i] for i < count: host values that travel as kernel
+// arguments (copied at launch), so the caller's array is free on return and
+// nothing waits for the stream
+constexpr int kArgFloats = 256;
+struct ArgFloats {
+  float v[kArgFloats];
+};
+__global__ void __launch_bounds__(kArgFloats) put_floats_kernel(float* dst, ArgFloats v, int count) {
+  if ((int)threadIdx.x < count) dst[threadIdx.x] = v.v[threadIdx.x];
+}
+
 }  // namespace
+
+sr_status put_floats(sr_plan_s* p, float* dst, const float* host, int count) {
+  for (int lo = 0; lo < count; lo += kArgFloats) {
+    ArgFloats v;
+    const int c = std::min(kArgFloats, count - lo);
+    std::memcpy(v.v, host + lo, sizeof(float) * c);
+    hipLaunchKernelGGL(put_floats_kernel, dim3(1), dim3(kArgFloats), 0, p->stream, dst + lo, v, c);
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SR_OK : hip_fail(e, "put_floats");
+}
 
 sr_status fill_phase_table(sr_plan_s* p) {
   if (p->eph == nullptr || p->theta_len <= 0) return SR_OK;

@@ -191,3 +191,36 @@ def test_stacked_spectral_matches_loop_and_oracle(gpu, monkeypatch, n_shape, m_s
         for i in (0, P - 1):
             xr = oracle.spectral_init(ops[i], ys[i], v0s[i], k, -1.0)
             assert rel_l2(xh[i * n:(i + 1) * n].reshape(n_shape), xr) <= 1e-4, (i, k)
+
+
+def test_stacked_gd_calls_queued_back_to_back(gpu):
+    """Two GD calls on one stacked plan queued without a wait in between,
+    each with its own steps (the steps travel with the launches): each result
+    equals the loop's for its own steps."""
+    import torch
+    import paper_2409_05734_amd as srpr
+    n_shape, m_shape, L, P = (48, 40), (96, 64), 2, 4
+    rng = np.random.default_rng(91)
+    th_blocks = [rng.uniform(0, 2 * np.pi, (L,) + m_shape).astype(np.float32) for _ in range(P)]
+    ys, x0s, base = [], [], []
+    for i in range(P):
+        op = oracle.StructuredOperator(th_blocks[i], n_shape, m_shape)
+        xs = sr_inputs.complex_gaussian(rng, n_shape)
+        ys.append((np.abs(op.A(xs)) ** 2).astype(np.float32))
+        x0s.append((xs + 0.4 * sr_inputs.complex_gaussian(rng, n_shape)).astype(np.complex64))
+        base.append(oracle.default_step(op, ys[-1], 1.0))
+    yd = to_dev(np.concatenate([y.ravel() for y in ys]), gpu)
+    x0 = to_dev(np.concatenate([x.ravel() for x in x0s]), gpu)
+    etas = [np.array([b * (0.05 + 0.01 * i) for i, b in enumerate(base)], np.float32),
+            np.array([b * (0.09 - 0.01 * i) for i, b in enumerate(base)], np.float32)]
+    stk = _plan(n_shape, m_shape, L, P, False, th_blocks, srpr.SR_SCHED_AUTO)
+    loop = _plan(n_shape, m_shape, L, P, False, th_blocks, srpr.SR_SCHED_LOOP)
+    xa = [x0.clone(), x0.clone()]
+    for x, eta in zip(xa, etas):
+        srpr.sr_gd_solve(stk, yd, x, 5, eta)
+    srpr.sr_plan_sync(stk)
+    for x, eta in zip(xa, etas):
+        xl = x0.clone()
+        srpr.sr_gd_solve(loop, yd, xl, 5, eta)
+        srpr.sr_plan_sync(loop)
+        assert torch.equal(x, xl)
