@@ -69,9 +69,10 @@ typedef enum {
 /* SR_SCHED_AUTO: a structured plan whose problems share one 2D geometry
  * (phase blocks all one block, or evenly spaced at least one block apart) runs
  * as a stack: each fused pass of every problem in one launch, with results
- * bitwise equal to SR_SCHED_LOOP (A, A^H, both VJPs, GD without a loss trace,
- * and power iteration where the support-column count is a multiple of the
- * column tile); the first stacked call allocates two grids per problem (plus
+ * bitwise equal to SR_SCHED_LOOP (A, A^H, both VJPs, GD, and power
+ * iteration; GD with a loss trace and power iteration only where the tiles of
+ * the pass that sums per-problem partials hold whole problems, else the
+ * loop); the first stacked call allocates two grids per problem (plus
  * small per-problem arrays) beside the workspace, kept until sr_plan_destroy.
  * Other plans of 8 or more problems take the batched launches.             */
 typedef enum {

@@ -148,7 +148,9 @@ struct sr_plan_s {
 namespace sr {
 
 // util_kernels.hip
-sr_status reduce_partials(sr_plan_s* p, const float* part, int n, float* out);
+// sum of n partials into *out (count > 1: that many sets of n end to end,
+// set t into out[t * ostride])
+sr_status reduce_partials(sr_plan_s* p, const float* part, int n, float* out, int count = 1, int ostride = 0);
 // (count > 1: that many arrays of n elements end to end, each on its own)
 sr_status sum_floats(sr_plan_s* p, const float* y, int64_t n, double* out, int count = 1);
 sr_status norm2_partial(sr_plan_s* p, const float2* x, int64_t n, float* out, int count = 1);

@@ -773,12 +773,26 @@ sr_status sr_adjoint(sr_plan p, const void* r, void* x_out) {
   return flush_1d(p, F1_ADJOINT, b1);
 }
 
-// GD on a stack (no loss trace): problem 0's schedule, each pass launched
-// once for all problems, each with its own step.
+// Whether a stack's turnaround pass keeps each tile inside one problem (its
+// loss partials are then each problem's own).
+static bool stack_trace_ok(const sr_plan_s* p, const Geo& g) {
+  const int k = g.L + 1;
+  const int ntr = (k == 2) ? g.M1 : (pass_col(k) ? g.M2 : g.M1);
+  int bt = p->tile(pass_len(g, k), pass_col(k));
+  if (bt <= 0) bt = default_tile(pass_len(g, k), pass_col(k));
+  bt &= kSingleBuffer - 1;
+  return ntr % bt == 0;
+}
+
+// GD on a stack: problem 0's schedule, each pass launched once for all
+// problems, each with its own step; with a loss trace, each problem's loss
+// partials (whole problems per turnaround tile) reduced in one launch.
 static sr_status gd_stacked(sr_plan_s* p, int P, int ths, const float* y, float2* x, int iters,
-                            const float* eta_host) {
+                            const float* eta_host, float* loss_trace) {
   const Geo& g = p->geo[0];
   SR_CHECK(ensure_stack_bufs(p, 2 * (size_t)P * g.mg));
+  const int nparts = turn_groups(p, g);
+  if (loss_trace != nullptr) SR_CHECK(ensure_stack_parts(p, (size_t)P * nparts));
   if (p->stk_steps_cap < P) {
     if (p->stk_steps) {
       SR_HIP(hipStreamSynchronize(p->stream));  // queued work may still read the old array
@@ -799,6 +813,13 @@ static sr_status gd_stacked(sr_plan_s* p, int P, int ths, const float* y, float2
   const float step = steps[0];  // (unused by the stacked update, which reads the array)
   SR_CHECK(first_pass(p, g, x, 1.f, nullptr, 0));
   int it = 0;
+  if (loss_trace != nullptr) {
+    for (; it < iters; ++it) {
+      SR_CHECK(gd_steady(p, g, y, x, step, p->stk_part, it == iters - 1));
+      SR_CHECK(reduce_partials(p, p->stk_part, nparts, loss_trace + it, P, iters));
+    }
+    return SR_OK;
+  }
   if (graphs_enabled(p) && iters - 1 >= kGraphChunk) {
     const std::string key = "gdstack:" + std::to_string(P) + ":" + ptr_key(y) + ":" + ptr_key(x) + ":" +
                             ptr_key(p->stk_buf) + ":" + ptr_key(p->stk_steps);
@@ -824,10 +845,11 @@ sr_status sr_gd_solve(sr_plan p, const float* y, void* x_inout, int32_t iters, c
   if (p->kind == SR_DENSE) return dense_gd(p, y, xs, iters, eta_host, loss_trace);
   // a uniform plan runs as one stack (unless the level launches or the
   // LDS-resident solver are asked for)
-  if (p->schedule == SR_SCHED_AUTO && loss_trace == nullptr && !fused2d_enabled(false)) {
+  if (p->schedule == SR_SCHED_AUTO && !fused2d_enabled(false)) {
     int ths = 0;
     const int P = stack_size(p, &ths);
-    if (P > 1) return gd_stacked(p, P, ths, y, xs, iters, eta_host);
+    if (P > 1 && (loss_trace == nullptr || stack_trace_ok(p, p->geo[0])))
+      return gd_stacked(p, P, ths, y, xs, iters, eta_host, loss_trace);
   }
   const bool want_batched = p->schedule == SR_SCHED_BATCHED || (p->schedule == SR_SCHED_AUTO && p->geo.size() >= 8);
   if (want_batched && loss_trace == nullptr && batched_supported(p)) return batched_gd(p, y, xs, iters, eta_host);

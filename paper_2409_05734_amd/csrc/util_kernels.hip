@@ -27,12 +27,14 @@ __device__ double block_sum_d(double v, double* red) {
   return r;
 }
 
-// out = sum of part[0..n) in index order (one thread: order is fixed)
-__global__ void reduce_partials_kernel(const float* __restrict__ part, int n, float* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+// out = sum of part[0..n) in index order (one thread: order is fixed);
+// thread t does the t-th of `count` sets of n partials, into out[t * ostride]
+__global__ void reduce_partials_kernel(const float* __restrict__ part, int n, float* out, int count, int ostride) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) {
     double acc = 0.0;
-    for (int i = 0; i < n; ++i) acc += (double)part[i];
-    *out = (float)acc;
+    for (int i = 0; i < n; ++i) acc += (double)part[(long long)t * n + i];
+    out[(long long)t * ostride] = (float)acc;
   }
 }
 
@@ -143,8 +145,9 @@ sr_status fill_phase_table(sr_plan_s* p) {
   return e == hipSuccess ? SR_OK : hip_fail(e, "phase table");
 }
 
-sr_status reduce_partials(sr_plan_s* p, const float* part, int n, float* out) {
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(64), 0, p->stream, part, n, out);
+sr_status reduce_partials(sr_plan_s* p, const float* part, int n, float* out, int count, int ostride) {
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((count + 63) / 64), dim3(64), 0, p->stream, part, n, out, count,
+                     ostride);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SR_OK : hip_fail(e, "reduce_partials");
 }

@@ -224,3 +224,46 @@ def test_stacked_gd_calls_queued_back_to_back(gpu):
         srpr.sr_gd_solve(loop, yd, xl, 5, eta)
         srpr.sr_plan_sync(loop)
         assert torch.equal(x, xl)
+
+
+@pytest.mark.parametrize("force", [None, "2,1,1"])
+@pytest.mark.parametrize("loss", ["l2", "poisson"])
+def test_stacked_gd_loss_trace(gpu, monkeypatch, force, loss):
+    """GD with a loss trace on a stack (per-problem loss partials where the
+    turnaround tiles hold whole problems, else the loop): iterates and traces
+    bit-identical to the loop, traces within 1e-4 of the oracle's."""
+    import torch
+    import paper_2409_05734_amd as srpr
+    if force is not None:
+        monkeypatch.setenv("SR_TUNE_FORCE", force)
+    n_shape, m_shape, L, P = (48, 40), (96, 64), 2, 5
+    rng = np.random.default_rng(92)
+    th_blocks = [rng.uniform(0, 2 * np.pi, (L,) + m_shape).astype(np.float32) for _ in range(P)]
+    ops, ys, x0s, etas = [], [], [], []
+    for i in range(P):
+        op = oracle.StructuredOperator(th_blocks[i], n_shape, m_shape)
+        xs = sr_inputs.complex_gaussian(rng, n_shape)
+        ys.append((np.abs(op.A(xs)) ** 2).astype(np.float32))
+        ops.append(op)
+        x0s.append((xs + 0.4 * sr_inputs.complex_gaussian(rng, n_shape)).astype(np.complex64))
+        etas.append(np.float32(oracle.default_step(op, ys[-1], 0.05 + 0.01 * i)))
+    eps = float(1e-2 * np.mean(np.concatenate([y.ravel() for y in ys])))
+    yd = to_dev(np.concatenate([y.ravel() for y in ys]), gpu)
+    k = 12
+    out = {}
+    for s in (srpr.SR_SCHED_AUTO, srpr.SR_SCHED_LOOP):
+        plan = _plan(n_shape, m_shape, L, P, False, th_blocks, s)
+        if loss == "poisson":
+            srpr.sr_plan_set_loss(plan, srpr.SR_LOSS_POISSON, eps)
+        x = to_dev(np.concatenate([x.ravel() for x in x0s]), gpu)
+        lt = torch.zeros(k * P, dtype=torch.float32, device=gpu)
+        srpr.sr_gd_solve(plan, yd, x, k, np.array(etas, np.float32), lt)
+        srpr.sr_plan_sync(plan)
+        out[s] = (x, lt)
+    assert torch.equal(out[srpr.SR_SCHED_AUTO][0], out[srpr.SR_SCHED_LOOP][0])
+    assert torch.equal(out[srpr.SR_SCHED_AUTO][1], out[srpr.SR_SCHED_LOOP][1])
+    lt = to_host(out[srpr.SR_SCHED_AUTO][1]).reshape(P, k)
+    for i in (0, P - 1):
+        kw = dict(loss="poisson", eps=eps) if loss == "poisson" else {}
+        _, lr = oracle.gd_solve(ops[i], ys[i], x0s[i], k, float(etas[i]), return_loss=True, **kw)
+        assert np.max(np.abs(lt[i] - lr) / np.abs(lr)) <= 1e-4, i
