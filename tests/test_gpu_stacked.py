@@ -267,3 +267,60 @@ def test_stacked_gd_loss_trace(gpu, monkeypatch, force, loss):
         kw = dict(loss="poisson", eps=eps) if loss == "poisson" else {}
         _, lr = oracle.gd_solve(ops[i], ys[i], x0s[i], k, float(etas[i]), return_loss=True, **kw)
         assert np.max(np.abs(lt[i] - lr) / np.abs(lr)) <= 1e-4, i
+
+
+@pytest.mark.parametrize("n_shape,m_shape,L,P,shared", [((12, 10), (16, 16), 1, 2, False),
+                                                         ((20, 24), (32, 32), 2, 300, False),
+                                                         ((16, 16), (32, 16), 3, 257, True)])
+def test_stacked_extremes(gpu, monkeypatch, n_shape, m_shape, L, P, shared):
+    """The smallest stack (two problems) and stacks of hundreds of small
+    problems: A with only z or only |z|^2 stored, A^H, 3 and 55 GD steps
+    (past one graph chunk) and 3 power iterations, each bit-identical to the
+    loop; the last problem against the oracle.  (Power iteration on shapes a
+    stack cannot take falls back to the LDS-resident solver on plans of 8 or
+    more problems, which rounds differently: switched off here so that the
+    fallback is the loop.)"""
+    import torch
+    import paper_2409_05734_amd as srpr
+    monkeypatch.setenv("SR_LDS_RESIDENT", "0")
+    rng = np.random.default_rng(hash((n_shape, m_shape, L, P, "ext")) % 2**32)
+    g = _grid(n_shape, m_shape)
+    nblk = 1 if shared else P
+    th_blocks = [rng.uniform(0, 2 * np.pi, (L,) + g).astype(np.float32) for _ in range(nblk)]
+    n, m = int(np.prod(n_shape)), int(np.prod(m_shape))
+    xs = np.concatenate([sr_inputs.complex_gaussian(rng, n_shape).ravel() for _ in range(P)])
+    r = to_dev(np.concatenate([sr_inputs.complex_gaussian(rng, m_shape).ravel() for _ in range(P)]), gpu)
+    v0 = to_dev(np.concatenate([sr_inputs.complex_gaussian(rng, n_shape).ravel() for _ in range(P)]), gpu)
+    x0 = to_dev((xs + 0.3 * np.concatenate([sr_inputs.complex_gaussian(rng, n_shape).ravel()
+                                            for _ in range(P)])).astype(np.complex64), gpu)
+    xd = to_dev(xs, gpu)
+    res = {}
+    for s in (srpr.SR_SCHED_AUTO, srpr.SR_SCHED_LOOP):
+        plan = _plan(n_shape, m_shape, L, P, shared, th_blocks, s)
+        z = torch.empty(P * m, dtype=torch.complex64, device=gpu)
+        y = torch.empty(P * m, dtype=torch.float32, device=gpu)
+        v = torch.empty(P * n, dtype=torch.complex64, device=gpu)
+        srpr.sr_forward(plan, xd, z, None)
+        srpr.sr_forward(plan, xd, None, y)
+        srpr.sr_adjoint(plan, r, v)
+        eta = np.float32(0.05 * m) / y.reshape(P, m).double().mean(dim=1).cpu().numpy().astype(np.float32)
+        out = [z, y, v]
+        for k in (3, 55):
+            x = x0.clone()
+            srpr.sr_gd_solve(plan, y, x, k, eta)
+            out.append(x)
+        est = torch.empty_like(v0)
+        srpr.sr_spectral_init(plan, y, v0, 3, -1.0, est)
+        out.append(est)
+        srpr.sr_plan_sync(plan)
+        res[s] = out
+    for name, a, b in zip(("z", "y", "v", "gd3", "gd55", "spec3"), res[srpr.SR_SCHED_AUTO], res[srpr.SR_SCHED_LOOP]):
+        assert torch.equal(a, b), name
+    i = P - 1
+    th = th_blocks[0 if shared else i]
+    z, y, v = [to_host(t) for t in res[srpr.SR_SCHED_AUTO][:3]]
+    zr = oracle.forward(xs[i * n:(i + 1) * n].reshape(n_shape), th, m_shape)
+    assert rel_l2(z[i * m:(i + 1) * m].reshape(m_shape), zr) <= 2e-5
+    assert rel_l2(y[i * m:(i + 1) * m].reshape(m_shape), np.abs(zr) ** 2) <= 4e-5
+    assert rel_l2(v[i * n:(i + 1) * n].reshape(n_shape),
+                  oracle.adjoint(to_host(r)[i * m:(i + 1) * m].reshape(m_shape), th, n_shape)) <= 2e-5
