@@ -326,6 +326,9 @@ static bool tile_offered(int N, bool col, int b) {
   return false;
 }
 
+static bool stack_spectral_ok(const sr_plan_s* p, const Geo& g);
+static bool stack_trace_ok(const sr_plan_s* p, const Geo& g);
+
 static sr_status tune_plan(sr_plan_s* p) {
   const char* force = std::getenv("SR_TUNE_FORCE");
   if (force != nullptr) {
@@ -382,6 +385,7 @@ static sr_status tune_plan(sr_plan_s* p) {
       const int nc = tile_options(g.M1, true, copt, 16);
       const int nr = tile_options(g.M2, false, ropt, 16);
       float best = 1e30f;
+      bool best_whole_found = false;
       hipEvent_t e0, e1;
       SR_HIP(hipEventCreate(&e0));
       SR_HIP(hipEventCreate(&e1));
@@ -415,11 +419,16 @@ static sr_status tune_plan(sr_plan_s* p) {
             SR_HIP(hipEventElapsedTime(&t, e0, e1));
             ms = std::min(ms, t);
           }
-          if (ms < best) {
+          // a stack prefers tiles that hold whole problems in the passes that
+          // sum per-problem partials (power iteration and loss traces stack too)
+          const bool whole = P > 1 && stack_spectral_ok(p, g) && stack_trace_ok(p, g);
+          if (whole && !best_whole_found) best = 1e30f;
+          if ((whole || !best_whole_found) && ms < best) {
             best = ms;
             cb = copt[i];
             rb = ropt[j];
             tb = tab;
+            best_whole_found = best_whole_found || whole;
           }
         }
       hipEventDestroy(e0);
