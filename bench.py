@@ -62,6 +62,31 @@ def schedule_bytes_gd(n_shape, m_shape, L):
     return b
 
 
+def compulsory_bytes_gd(n_shape, m_shape, L):
+    """The floor of one GD iteration's HBM traffic if every intermediate stayed
+    on chip: x read and written, y, theta_1 on the signal's support (D_1 only
+    meets U x) and theta_2..theta_L on the whole grid."""
+    N1, N2 = n_shape
+    M1, M2 = m_shape
+    n, m = N1 * N2, M1 * M2
+    return 8 * n + 8 * n + 4 * m + 4 * n + 4 * m * (L - 1)
+
+
+_CEILING = [None]  # the copy ceiling the headline measured, for the side workloads' fractions
+
+
+def copy_ceiling_gbps(torch, dev, mib=512, reps=5):
+    """Device-to-device copy rate (bytes read + written per second) of a
+    `mib` MiB buffer: the practical HBM ceiling beside the 8 TB/s peak."""
+    src = torch.empty(mib * 1024 * 1024 // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    ms = _time_calls(torch, s, lambda: dst.copy_(src), reps)
+    gbps = 2 * src.numel() * 4 / (ms * 1e-3) / 1e9
+    del src, dst
+    return gbps
+
+
 def schedule_bytes_op(n_shape, m_shape, L):
     """Algorithmic bytes of one A (or A^H) application (x in, z out)."""
     N1, N2 = n_shape
@@ -213,6 +238,9 @@ def headline(torch, srpr, sr_inputs, dev, steps, warmup):
     cos = float(abs(np.vdot(xh, xt)) / (np.linalg.norm(xh) * np.linalg.norm(xt)))
     it_us = solve_ms * 1e3 / GD_ITERS
     achieved = gd_bytes / (it_us * 1e-6) / 1e9
+    comp_bytes = compulsory_bytes_gd(n_shape, m_shape, L)
+    ceiling = copy_ceiling_gbps(torch, dev)
+    _CEILING[0] = ceiling
     traffic = stored_traffic()
     return {
         "value": GD_ITERS * steps / wall,
@@ -222,7 +250,10 @@ def headline(torch, srpr, sr_inputs, dev, steps, warmup):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "one fused GD iteration (2L = 4 pass kernels in steady state, graph-replayed)",
-                     "bytes_per_unit": gd_bytes, "unit_of_work": "GD iteration"},
+                     "bytes_per_unit": gd_bytes, "unit_of_work": "GD iteration",
+                     "copy_ceiling_GBps": ceiling, "frac_of_copy_ceiling": achieved / ceiling,
+                     "compulsory_bytes_per_unit": comp_bytes,
+                     "compulsory_GBps": comp_bytes / (it_us * 1e-6) / 1e9},
         "operator": {"A_us": fwd_ms * 1e3, "AH_us": adj_ms * 1e3,
                      "A_GBps": op_bytes / (fwd_ms * 1e-3) / 1e9, "AH_GBps": op_bytes / (adj_ms * 1e-3) / 1e9,
                      "bytes_per_application": op_bytes},
@@ -259,6 +290,7 @@ def large_2d(torch, srpr, sr_inputs, dev):
     return {"workload": "1024^2 -> 2048^2 (alpha=4), L=3, Poisson 1000 photons",
             "gd_iters_per_s": d["gd_iters"] / (gd_ms * 1e-3), "gd_iteration_us": it_us,
             "gd_GBps": gd_bytes / (it_us * 1e-6) / 1e9, "gd_frac_hbm": gd_bytes / (it_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "gd_frac_copy_ceiling": gd_bytes / (it_us * 1e-6) / 1e9 / _CEILING[0] if _CEILING[0] else None,
             "bytes_per_gd_iteration": gd_bytes,
             "spectral_iters_per_s": d["pi_iters"] / (pi_ms * 1e-3),
             "A_us": fwd_ms * 1e3, "AH_us": adj_ms * 1e3,
@@ -336,6 +368,61 @@ def batched(torch, srpr, sr_inputs, dev, iters=300):
             "max_err_gap_finite": float(np.max(np.abs((eb - el)[np.isfinite(eb) & np.isfinite(el)])))}
 
 
+def library_loop(torch, srpr, sr_inputs, dev, iters=200):
+    """The headline's GD iteration written with PyTorch's FFT (rocFFT) and
+    elementwise ops on the same GPU, one library call at a time (pad, L x
+    [phase, 2D FFT], residual, L x [inverse FFT, conjugate phase], crop,
+    update): the plain loop the fused passes replace.  Same inputs and step;
+    reports both times per iteration and the relative difference of the
+    iterates after the run."""
+    d = sr_inputs.image_2d(1)
+    n_shape, m_shape, L = d["n_shape"], d["m_shape"], d["layers"]
+    (N1, N2), (M1, M2) = n_shape, m_shape
+    n, m = N1 * N2, M1 * M2
+    o1, o2 = (M1 - N1) // 2, (M2 - N2) // 2
+    plan = srpr.Plan([srpr.Problem(n_shape, m_shape, L)], d["theta"])
+    xs = torch.from_numpy(d["x_star"].ravel()).to(dev)
+    y = torch.empty(m, dtype=torch.float32, device=dev)
+    srpr.sr_forward(plan, xs, None, y)
+    th = torch.from_numpy(d["theta"]).to(dev)
+    D = torch.polar(torch.ones_like(th), th)
+    Dc = D.conj().resolve_conj()
+    y2 = y.reshape(m_shape)
+    step = float(d["mu"] * m / float(y.double().mean().item())) / m
+    x0 = (xs + 0.3 * torch.randn_like(xs)).reshape(n_shape).contiguous()
+
+    def lib_step(x):
+        w = torch.zeros(m_shape, dtype=torch.complex64, device=dev)
+        w[o1:o1 + N1, o2:o2 + N2] = x
+        for l in range(L):
+            w = torch.fft.fft2(D[l] * w, norm="ortho")
+        r = (w.real * w.real + w.imag * w.imag - y2) * w
+        for l in reversed(range(L)):
+            r = Dc[l] * torch.fft.ifft2(r, norm="ortho")
+        return x - step * r[o1:o1 + N1, o2:o2 + N2]
+
+    xl = x0.clone()
+
+    def run_lib():
+        nonlocal xl
+        xl = x0.clone()
+        for _ in range(iters):
+            xl = lib_step(xl)
+    s = torch.cuda.current_stream()
+    lib_ms = _time_calls(torch, s, run_lib, 2, warm=1)
+    xf = torch.empty(n, dtype=torch.complex64, device=dev)
+    eta = np.float32(step * m)
+
+    def run_fused():
+        xf.copy_(x0.ravel())
+        srpr.sr_gd_solve(plan, y, xf, iters, eta)
+    fused_ms = _time_calls(torch, plan.stream, run_fused, 3, warm=1)
+    rel = float(((xf - xl.ravel()).abs().pow(2).sum() / xl.abs().pow(2).sum()).sqrt())
+    return {"workload": f"256^2 -> 512^2, L=2, {iters} GD steps: torch.fft + elementwise ops vs the fused passes",
+            "library_iteration_us": lib_ms * 1e3 / iters, "fused_iteration_us": fused_ms * 1e3 / iters,
+            "speedup_vs_library_loop": lib_ms / fused_ms, "rel_diff_of_iterates": rel}
+
+
 def stacked_gd(torch, srpr, sr_inputs, dev, count=16, iters=300):
     """A uniform batch at the headline shape (256^2 -> 512^2, L = 2, each
     problem with its own masks and step): every pass launched once for the
@@ -375,6 +462,7 @@ def stacked_gd(torch, srpr, sr_inputs, dev, count=16, iters=300):
             "stacked_ms": s_ms, "loop_ms": l_ms, "speedup_vs_loop": l_ms / s_ms,
             "stacked_problem_iters_per_s": count * iters / (s_ms * 1e-3),
             "stacked_GBps": byt * iters / (s_ms * 1e-3) / 1e9,
+            "stacked_frac_copy_ceiling": byt * iters / (s_ms * 1e-3) / 1e9 / _CEILING[0] if _CEILING[0] else None,
             "bit_identical_to_loop": bool(torch.equal(xa, x)),
             "spectral_stacked_ms": s_spec_ms, "spectral_loop_ms": l_spec_ms,
             "spectral_speedup_vs_loop": l_spec_ms / s_spec_ms,
@@ -773,7 +861,7 @@ def main():
     if not args.quick:
         extras = {}
         side = (("large_2d", large_2d), ("dense_baseline", dense), ("batched", batched),
-                ("stacked_gd", stacked_gd), ("autograd", autograd), ("lds_resident_2d", lds_resident), ("forward_time_sweep", forward_time_sweep),
+                ("library_loop", library_loop), ("stacked_gd", stacked_gd), ("autograd", autograd), ("lds_resident_2d", lds_resident), ("forward_time_sweep", forward_time_sweep),
                 ("layer_study", layer_study), ("poisson_loss", poisson_loss), ("tiny_1d", tiny_1d),
                 ("accuracy_sweep", accuracy_sweep))
         on_request = {"accuracy_sweep"}  # about a minute of GPU time: run only when named
