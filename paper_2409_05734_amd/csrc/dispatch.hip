@@ -53,7 +53,7 @@ int pass_groups(int N, bool col, int B, int ntr) {
 namespace {
 template <int N, int OP>
 void go1d_batch_op(const Fused1DArgs* as, int count, hipStream_t s) {
-  hipLaunchKernelGGL((fused1d_batch_kernel<N, OP>), dim3(count), dim3(Tile<N, 1, false>::THREADS), 0, s, as);
+  hipLaunchKernelGGL((fused1d_batch_kernel<N, OP>), dim3(count), dim3(F1Tile<N>::THREADS), 0, s, as);
 }
 
 template <int N>
@@ -70,7 +70,7 @@ hipError_t go1d_batch(int op, const Fused1DArgs* as, int count, hipStream_t s) {
 
 template <int N>
 hipError_t go1d(int op, const Fused1DArgs& a, hipStream_t s) {
-  constexpr int NT = Tile<N, 1, false>::THREADS;
+  constexpr int NT = F1Tile<N>::THREADS;
   switch (op) {
     case F1_FORWARD:
       hipLaunchKernelGGL((fused1d_kernel<N, F1_FORWARD>), dim3(1), dim3(NT), 0, s, a);

@@ -37,9 +37,20 @@ struct Fused1DArgs {
   float* gth;                // derivatives: phase-cotangent accumulator (L*m)
 };
 
+// The transform shape of the 1D kernels: the narrow shape (four elements per
+// thread, twice the threads) where the length has one.  A single 1D problem
+// is one workgroup whose whole solve is a chain of dependent transforms, so
+// its time is the chain's latency: halving each lane's arithmetic shortens
+// it more than the extra exchange stage lengthens it (the default shape of
+// the shorter lengths does not even fill one wave).
+// (The host passes the matching twiddle table: the narrow one where the
+// length has it.)
+template <int N>
+using F1Tile = TileV<N, 1, false, true, HasNarrow<N>::value ? 1 : 0>;
+
 template <int N, int OP>
 __device__ __forceinline__ void fused1d_body(const Fused1DArgs& a) {
-  using T = Tile<N, 1, false>;
+  using T = F1Tile<N>;
   constexpr int E = T::E;
   constexpr int NT = T::THREADS;
   __shared__ float2 lds[2 * T::BUF];
@@ -291,13 +302,13 @@ __device__ __forceinline__ void fused1d_body(const Fused1DArgs& a) {
 
 // One problem per launch.
 template <int N, int OP>
-__global__ void __launch_bounds__((Tile<N, 1, false>::THREADS)) fused1d_kernel(const Fused1DArgs a) {
+__global__ void __launch_bounds__((F1Tile<N>::THREADS)) fused1d_kernel(const Fused1DArgs a) {
   fused1d_body<N, OP>(a);
 }
 
 // Many problems of one length per launch, one workgroup each.
 template <int N, int OP>
-__global__ void __launch_bounds__((Tile<N, 1, false>::THREADS)) fused1d_batch_kernel(const Fused1DArgs* __restrict__ as) {
+__global__ void __launch_bounds__((F1Tile<N>::THREADS)) fused1d_batch_kernel(const Fused1DArgs* __restrict__ as) {
   const Fused1DArgs a = as[blockIdx.x];
   fused1d_body<N, OP>(a);
 }

@@ -509,7 +509,7 @@ static Fused1DArgs args_1d(const sr_plan_s* p, const Geo& g, Fused1DArgs a) {
   a.mw = g.W1;
   a.moff = g.c1;
   a.theta = p->theta_l(g, 1);
-  a.tw = p->twiddles(g.M1);
+  a.tw = p->twiddles(g.M1, 1) ? p->twiddles(g.M1, 1) : p->twiddles(g.M1, 0);  // the 1D kernels' shape
   a.loss = p->loss;
   a.loss_eps = p->loss_eps;
   return a;

@@ -85,7 +85,7 @@ sr_status fused1d_vjp(sr_plan_s* p, const Geo& g, int op, Fused1DArgs a) {
   a.mw = g.W1;
   a.moff = g.c1;
   a.theta = p->theta_l(g, 1);
-  a.tw = p->twiddles(g.M1);
+  a.tw = p->twiddles(g.M1, 1) ? p->twiddles(g.M1, 1) : p->twiddles(g.M1, 0);  // the 1D kernels' shape
   hipError_t e = launch_fused1d(g.M1, op, a, p->stream);
   if (e != hipSuccess) return hip_fail(e, "fused 1D derivative launch");
   return SR_OK;
