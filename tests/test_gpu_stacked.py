@@ -177,7 +177,7 @@ def test_stacked_spectral_matches_loop_and_oracle(gpu, monkeypatch, n_shape, m_s
     v0 = to_dev(np.concatenate([v.ravel() for v in v0s]), gpu)
     plans = {s: _plan(n_shape, m_shape, L, P, shared, th_blocks, s) for s in (srpr.SR_SCHED_AUTO, srpr.SR_SCHED_LOOP)}
     n = int(np.prod(n_shape))
-    for k in (1, 6, 60):
+    for k in (0, 1, 6, 60):
         out = {}
         for s, plan in plans.items():
             x = torch.empty_like(v0)
