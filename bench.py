@@ -337,11 +337,20 @@ def batched(torch, srpr, sr_inputs, dev, iters=300):
     def run():
         x.copy_(x0)
         srpr.sr_gd_solve(plan, y, x, iters, eta)
+    v0 = torch.randn_like(x0)
+    est = torch.empty_like(x0)
+
+    def run_spec():
+        srpr.sr_spectral_init(plan, y, v0, 100, -1.0, est)
     srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_BATCHED)
     b_ms = _time_calls(torch, s, run, 3, warm=1)
     xb = x.clone()
+    bs_ms = _time_calls(torch, s, run_spec, 3, warm=1)
+    eb_spec = est.clone()
     srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_LOOP)
     l_ms = _time_calls(torch, s, run, 1, warm=1)
+    ls_ms = _time_calls(torch, s, run_spec, 1, warm=1)
+    spec_rel = float(((eb_spec - est).abs().pow(2).sum() / est.abs().pow(2).sum()).sqrt())
     # accuracy of both schedules per problem: phase-aligned relative error to x*
     xbh, xlh = xb.cpu().numpy().astype(np.complex128), x.cpu().numpy().astype(np.complex128)
 
@@ -358,6 +367,8 @@ def batched(torch, srpr, sr_inputs, dev, iters=300):
     byt = sum(schedule_bytes_gd(p["n_shape"], p["m_shape"], p["layers"]) for p in probs)
     return {"workload": "256 problems, N in {32,64,96,128}^2, alpha in {2,4,8}, L in {1,2,3}, 300 GD steps",
             "batched_ms": b_ms, "loop_ms": l_ms, "speedup_vs_loop": l_ms / b_ms,
+            "spectral_100_batched_ms": bs_ms, "spectral_100_loop_ms": ls_ms,
+            "spectral_speedup_vs_loop": ls_ms / bs_ms, "spectral_rel_diff_vs_loop": spec_rel,
             "batched_gd_iters_per_s": iters / (b_ms * 1e-3),
             "batched_GBps": byt * iters / (b_ms * 1e-3) / 1e9, "bytes_per_batched_iteration": byt,
             "recovered_batched": int((eb < 1e-3).sum()), "recovered_loop": int((el < 1e-3).sum()),

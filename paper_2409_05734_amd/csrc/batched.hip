@@ -44,7 +44,7 @@ constexpr int batch_b() {
 }
 
 template <int N, bool COL>
-__device__ __forceinline__ void run_kind(const PassArgs& a, int kind, int tile, float2* lds, float* red) {
+__device__ __forceinline__ void run_kind_gd(const PassArgs& a, int kind, int tile, float2* lds, float* red) {
   constexpr int B = batch_b<N>();
   if constexpr (COL) {
     switch (kind) {
@@ -84,19 +84,69 @@ __device__ __forceinline__ void run_kind(const PassArgs& a, int kind, int tile, 
   }
 }
 
+
+// The passes of a power iteration (deferred normalisation: the last pass
+// reads the previous iterate's squared-norm partials and writes the new
+// ones, each problem's own, through its descriptor).
+template <int N, bool COL>
+__device__ __forceinline__ void run_kind_spec(const PassArgs& a, int kind, int tile, float2* lds, float* red) {
+  constexpr int B = batch_b<N>();
+  if constexpr (COL) {
+    switch (kind) {
+      case PK_FIRST_FWD:
+        pass_tile_rt<N, B, COL, PRE_PHASE, MID_NONE, false, false, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
+                                                                                   nullptr);
+        return;
+      case PK_LAST_SPEC:
+        pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_SPEC>(a, tile, lds, red, a.part_in, a.npart,
+                                                                                a.part_out);
+        return;
+      case PK_LAST_SPEC_FWD:
+        pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_SPEC_FWD>(a, tile, lds, red, a.part_in,
+                                                                                    a.npart, a.part_out);
+        return;
+      default:
+        break;
+    }
+  }
+  switch (kind) {
+    case PK_MID_FWD:
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE, true, false, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
+                                                                                nullptr);
+      return;
+    case PK_TURN_SPEC:
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_SPEC, true, false, true, POST_STORE>(a, tile, lds, red, nullptr, 0, nullptr);
+      return;
+    case PK_MID_ADJ:
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE_CONJ, true, true, true, POST_STORE>(a, tile, lds, red, nullptr, 0,
+                                                                                   nullptr);
+      return;
+    default:
+      return;
+  }
+}
+
 constexpr size_t kBatchLds = 2 * sizeof(float2) * kBatchThreads * 12;  // covers 2 * B * NP elements for E <= 12
 
-template <int N>
+template <int N, bool SPEC>
 __device__ __forceinline__ void run_len(const BatchDesc& d, int tile, float2* lds, float* red) {
   static_assert(Tile<N, batch_b<N>(), true>::THREADS == kBatchThreads, "batched tiles are 256 threads");
   static_assert(2 * sizeof(float2) * Tile<N, batch_b<N>(), true>::BUF <= kBatchLds, "batched LDS budget");
-  if (d.col) run_kind<N, true>(d.a, d.kind, tile, lds, red);
-  else run_kind<N, false>(d.a, d.kind, tile, lds, red);
+  if constexpr (SPEC) {
+    if (d.col) run_kind_spec<N, true>(d.a, d.kind, tile, lds, red);
+    else run_kind_spec<N, false>(d.a, d.kind, tile, lds, red);
+  } else {
+    if (d.col) run_kind_gd<N, true>(d.a, d.kind, tile, lds, red);
+    else run_kind_gd<N, false>(d.a, d.kind, tile, lds, red);
+  }
 }
 
 // Three workgroups per CU (the LDS budget's limit): the compiler fits the
 // kernel in 168 VGPRs (a small spill on the twelve-element lengths) instead of
 // 197, which held it to two; measured 71 -> 62.5 ms on 256 uneven problems.
+// (SPEC: the power-iteration pass set, a kernel of its own so that the GD
+// kernel's registers are not those of both sets)
+template <bool SPEC>
 __global__ void __launch_bounds__(kBatchThreads, 3) batched_level_kernel(const BatchItem* __restrict__ items,
                                                                       const BatchDesc* __restrict__ descs) {
   extern __shared__ float2 lds[];
@@ -104,15 +154,15 @@ __global__ void __launch_bounds__(kBatchThreads, 3) batched_level_kernel(const B
   const BatchItem it = items[xcd_tile(blockIdx.x, gridDim.x)];
   const BatchDesc& d = descs[it.desc];
   switch (d.N) {
-    case 16: run_len<16>(d, it.tile, lds, red); break;
-    case 32: run_len<32>(d, it.tile, lds, red); break;
-    case 64: run_len<64>(d, it.tile, lds, red); break;
-    case 96: run_len<96>(d, it.tile, lds, red); break;
-    case 128: run_len<128>(d, it.tile, lds, red); break;
-    case 192: run_len<192>(d, it.tile, lds, red); break;
-    case 256: run_len<256>(d, it.tile, lds, red); break;
-    case 384: run_len<384>(d, it.tile, lds, red); break;
-    case 512: run_len<512>(d, it.tile, lds, red); break;
+    case 16: run_len<16, SPEC>(d, it.tile, lds, red); break;
+    case 32: run_len<32, SPEC>(d, it.tile, lds, red); break;
+    case 64: run_len<64, SPEC>(d, it.tile, lds, red); break;
+    case 96: run_len<96, SPEC>(d, it.tile, lds, red); break;
+    case 128: run_len<128, SPEC>(d, it.tile, lds, red); break;
+    case 192: run_len<192, SPEC>(d, it.tile, lds, red); break;
+    case 256: run_len<256, SPEC>(d, it.tile, lds, red); break;
+    case 384: run_len<384, SPEC>(d, it.tile, lds, red); break;
+    case 512: run_len<512, SPEC>(d, it.tile, lds, red); break;
     default: break;
   }
 }
@@ -136,6 +186,7 @@ int batch_tile_width(int N) {
 
 // Level lists of one recorded pass sequence (device descriptors and items).
 struct LevelSet {
+  bool spec = false;  // power-iteration passes (the other kernel)
   BatchDesc* d_descs = nullptr;
   BatchItem* d_items = nullptr;
   std::vector<int> level_off, level_cnt;  // item ranges per level
@@ -280,8 +331,12 @@ static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const fl
 static sr_status run_levels(sr_plan_s* p, const LevelSet& ls) {
   for (size_t q = 0; q < ls.level_cnt.size(); ++q) {
     if (ls.level_cnt[q] == 0) continue;
-    hipLaunchKernelGGL(batched_level_kernel, dim3(ls.level_cnt[q]), dim3(kBatchThreads), kBatchLds, p->stream,
-                       ls.d_items + ls.level_off[q], ls.d_descs);
+    if (ls.spec)
+      hipLaunchKernelGGL(batched_level_kernel<true>, dim3(ls.level_cnt[q]), dim3(kBatchThreads), kBatchLds, p->stream,
+                         ls.d_items + ls.level_off[q], ls.d_descs);
+    else
+      hipLaunchKernelGGL(batched_level_kernel<false>, dim3(ls.level_cnt[q]), dim3(kBatchThreads), kBatchLds,
+                         p->stream, ls.d_items + ls.level_off[q], ls.d_descs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "batched level launch");
   }
@@ -336,6 +391,172 @@ static sr_status batched_levels_gd(sr_plan_s* p, const float* y, float2* x, int 
     if (s != SR_OK) return s;
   }
   return run_levels(p, st->last);
+}
+
+// ------------------------------------------------------------ power iteration
+// The same level launches for the power iteration of the problems that are
+// not LDS-resident: each problem's recorded passes carry its own sum(y) and
+// its own two sets of squared-norm partials (the last pass of iteration it
+// reads set it & 1 and writes the other), so one launch per level serves
+// every problem.  Seven recordings: the first pass, iteration 0 (reading the
+// start vector's single partial), odd and even iterations, each also as the
+// final iteration (plain update).
+
+sr_status spec_steady_public(sr_plan_s* p, const Geo& g, const float* y, float2* u, float lam, float inv_mc,
+                             const double* ysum, const float* part_in, int npart_in, float* part_out, bool last);
+
+struct SpecBatchState {
+  std::string key;
+  float2* bufs = nullptr;              // per problem of the plan: two full grids
+  float* parts = nullptr;              // per problem of the plan: two partial sets
+  std::vector<size_t> buf_off, part_off;
+  std::vector<int> nq;                 // partials per set (tiles of the last pass)
+  LevelSet first, it0, it0_last, odd, odd_last, even, even_last;
+  ~SpecBatchState() {
+    if (bufs) hipFree(bufs);
+    if (parts) hipFree(parts);
+  }
+};
+
+void destroy_spec_batch_state(SpecBatchState* s) { delete s; }
+
+bool batch_level_capable(const Geo& g) {
+  return g.ndim == 2 && batch_tile_width(g.M1) != 0 && batch_tile_width(g.M2) != 0;
+}
+
+static float spec_inv_mc(const Geo& g) { return (float)((double)g.mg / (double)g.m); }  // c = 1/(grid size)
+
+static sr_status spec_prepare(sr_plan_s* p, const std::vector<int>& which, const float* y, float2* x, float lam,
+                              SpecBatchState** out) {
+  std::string key = std::to_string((uintptr_t)y) + ":" + std::to_string((uintptr_t)x);
+  {
+    uint32_t u;
+    std::memcpy(&u, &lam, 4);
+    key += ":" + std::to_string(u);
+  }
+  for (int i : which) key += "," + std::to_string(i);
+  SpecBatchState* st = p->spec_batch;
+  if (st != nullptr && st->key == key) {
+    *out = st;
+    return SR_OK;
+  }
+  const size_t np = p->geo.size();
+  if (st == nullptr) {
+    st = new SpecBatchState();
+    p->spec_batch = st;
+    size_t elems = 0, pelems = 0;
+    st->buf_off.assign(np, 0);
+    st->part_off.assign(np, 0);
+    st->nq.assign(np, 0);
+    for (size_t i = 0; i < np; ++i) {
+      const Geo& g = p->geo[i];
+      st->buf_off[i] = elems;
+      st->part_off[i] = pelems;
+      if (!batch_level_capable(g)) continue;
+      st->nq[i] = (g.N2 + batch_tile_width(g.M1) - 1) / batch_tile_width(g.M1);
+      elems += 2 * (size_t)g.mg;
+      pelems += 2 * (size_t)std::max(st->nq[i], 1);
+    }
+    hipError_t e = hipMalloc(&st->bufs, std::max<size_t>(elems, 1) * sizeof(float2));
+    if (e == hipSuccess) e = hipMalloc(&st->parts, std::max<size_t>(pelems, 1) * sizeof(float));
+    if (e != hipSuccess) return fail(SR_E_NOMEM, "batched power-iteration workspace allocation failed");
+  }
+  st->key.clear();
+  std::vector<std::vector<PassRecord>> r_first(np), r_it0(np), r_it0l(np), r_odd(np), r_oddl(np), r_even(np),
+      r_evenl(np);
+  float2* saveA = p->bufA;
+  float2* saveB = p->bufB;
+  sr_status status = SR_OK;
+  for (int i : which) {
+    if (status != SR_OK) break;
+    const Geo& g = p->geo[i];
+    p->bufA = st->bufs + st->buf_off[i];  // each problem's private ping-pong buffers
+    p->bufB = st->bufs + st->buf_off[i] + g.mg;
+    const float* yi = y + p->yoff[i];
+    float2* xi = x + p->xoff[i];
+    const double* ys = p->ysum + i;
+    float* P0 = st->parts + st->part_off[i];
+    float* P1 = P0 + std::max(st->nq[i], 1);
+    const float imc = spec_inv_mc(g);
+    const int nq = st->nq[i];
+    struct Rec {
+      std::vector<PassRecord>* r;
+      const float* in;
+      int npart;
+      float* out;
+      bool last;
+    } recs[6] = {{&r_it0[i], P0, 1, P1, false}, {&r_it0l[i], P0, 1, P1, true}, {&r_odd[i], P1, nq, P0, false},
+                 {&r_oddl[i], P1, nq, P0, true}, {&r_even[i], P0, nq, P1, false}, {&r_evenl[i], P0, nq, P1, true}};
+    g_recording = &r_first[i];
+    status = gd_first_pass_public(p, g, xi);
+    for (const Rec& r : recs) {
+      if (status != SR_OK) break;
+      g_recording = r.r;
+      status = spec_steady_public(p, g, yi, xi, lam, imc, ys, r.in, r.npart, r.out, r.last);
+    }
+    g_recording = nullptr;
+  }
+  p->bufA = saveA;
+  p->bufB = saveB;
+  if (status != SR_OK) return status;
+  LevelSet* sets[7] = {&st->first, &st->it0, &st->it0_last, &st->odd, &st->odd_last, &st->even, &st->even_last};
+  std::vector<std::vector<PassRecord>>* recsets[7] = {&r_first, &r_it0, &r_it0l, &r_odd, &r_oddl, &r_even, &r_evenl};
+  for (int k = 0; k < 7; ++k) {
+    sets[k]->spec = true;
+    if ((status = build_levels(p, *recsets[k], *sets[k])) != SR_OK) return status;
+  }
+  st->key = key;
+  *out = st;
+  return SR_OK;
+}
+
+sr_status batched_spectral(sr_plan_s* p, const std::vector<int>& which, const float* y, const float2* v0, int iters,
+                           float lam, float2* x) {
+  SpecBatchState* st = nullptr;
+  sr_status s = spec_prepare(p, which, y, x, lam, &st);
+  if (s != SR_OK) return s;
+  // sum(y), u_0 = v0 and its squared norm (one partial), per problem
+  for (int i : which) {
+    const Geo& g = p->geo[i];
+    if ((s = sum_floats(p, y + p->yoff[i], g.m, p->ysum + i)) != SR_OK) return s;
+    hipError_t e = hipMemcpyAsync(x + p->xoff[i], v0 + p->xoff[i], sizeof(float2) * g.n, hipMemcpyDeviceToDevice,
+                                  p->stream);
+    if (e != hipSuccess) return hip_fail(e, "start vector copy");
+    if ((s = norm2_partial(p, x + p->xoff[i], g.n, st->parts + st->part_off[i])) != SR_OK) return s;
+  }
+  if (iters > 0) {
+    if ((s = run_levels(p, st->first)) != SR_OK) return s;
+    if ((s = run_levels(p, iters == 1 ? st->it0_last : st->it0)) != SR_OK) return s;
+  }
+  int it = 1;
+  constexpr int kChunk = 50;  // even: every chunk starts on an odd iteration
+  if (iters - 1 - it >= kChunk && graphs_enabled(p)) {
+    const std::string gkey = "bspec:" + st->key;
+    for (; it + kChunk <= iters - 1; it += kChunk) {
+      s = launch_captured(p, gkey, [&]() -> sr_status {
+        for (int c = 0; c < kChunk; ++c) {
+          sr_status q = run_levels(p, ((it + c) & 1) ? st->odd : st->even);
+          if (q != SR_OK) return q;
+        }
+        return SR_OK;
+      });
+      if (s != SR_OK) return s;
+    }
+  }
+  for (; it < iters; ++it) {
+    const bool last = it == iters - 1;
+    const LevelSet& ls = (it & 1) ? (last ? st->odd_last : st->odd) : (last ? st->even_last : st->even);
+    if ((s = run_levels(p, ls)) != SR_OK) return s;
+  }
+  // x0 = sqrt(sum(y)/(m c)) u / ||u||
+  for (int i : which) {
+    const Geo& g = p->geo[i];
+    const float* P = st->parts + st->part_off[i] + ((iters & 1) ? std::max(st->nq[i], 1) : 0);
+    if ((s = final_scale(p, x + p->xoff[i], g.n, P, iters == 0 ? 1 : st->nq[i], p->ysum + i, spec_inv_mc(g))) !=
+        SR_OK)
+      return s;
+  }
+  return SR_OK;
 }
 
 }  // namespace sr

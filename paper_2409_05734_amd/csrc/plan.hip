@@ -210,5 +210,6 @@ sr_plan_s::~sr_plan_s() {
   if (stk_steps) hipFree(stk_steps);
   if (stk_part) hipFree(stk_part);
   if (batch) sr::destroy_batch_state(batch);
+  if (spec_batch) sr::destroy_spec_batch_state(spec_batch);
   if (ws) hipFree(ws);
 }

@@ -38,6 +38,8 @@ sr_status hip_fail(hipError_t e, const char* what);
 namespace sr {
 struct BatchState;
 void destroy_batch_state(BatchState* s);
+struct SpecBatchState;
+void destroy_spec_batch_state(SpecBatchState* s);
 
 // A stack of problems of one geometry run as one: every fused pass of the
 // first problem's schedule is launched once for all P problems, each buffer
@@ -113,6 +115,7 @@ struct sr_plan_s {
   float* stk_steps = nullptr;          // device: per-problem GD steps of a stack
   int stk_steps_cap = 0;
   sr::BatchState* batch = nullptr;  // batched-schedule state (built on first batched solve)
+  sr::SpecBatchState* spec_batch = nullptr;  // the same for batched power iteration
   size_t vjp_elems = 0;
 
   // LDS-resident small-problem solver (fused2d.hip): device descriptors, their
@@ -186,6 +189,11 @@ sr_status aux_join(sr_plan_s* p);
 // batched.hip (many problems advanced one pass level per launch)
 bool batched_supported(const sr_plan_s* p);
 sr_status batched_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta);
+// power iteration of the listed problems by level launches (2D problems
+// whose lengths the level kernel covers)
+bool batch_level_capable(const Geo& g);
+sr_status batched_spectral(sr_plan_s* p, const std::vector<int>& which, const float* y, const float2* v0, int iters,
+                           float lam, float2* x);
 
 // vjp.hip (reverse-mode derivatives of A and A^H)
 sr_status vjp_forward(sr_plan_s* p, const float2* x, const float2* gz, float2* gx, float* gtheta);

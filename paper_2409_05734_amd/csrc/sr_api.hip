@@ -264,6 +264,10 @@ sr_status gd_first_pass_public(sr_plan_s* p, const Geo& g, const float2* x) { re
 sr_status gd_steady_public(sr_plan_s* p, const Geo& g, const float* y, float2* x, float step, bool last) {
   return gd_steady(p, g, y, x, step, nullptr, last);
 }
+sr_status spec_steady_public(sr_plan_s* p, const Geo& g, const float* y, float2* u, float lam, float inv_mc,
+                             const double* ysum, const float* part_in, int npart_in, float* part_out, bool last) {
+  return spec_steady(p, g, y, u, lam, inv_mc, ysum, part_in, npart_in, part_out, last);
+}
 }  // namespace sr
 
 static int last_pass_groups(const sr_plan_s* p, const Geo& g) { return pass_groups(g.M1, true, p->tile(g.M1, true), g.N2); }
@@ -996,6 +1000,16 @@ sr_status sr_spectral_init(sr_plan p, const float* y, const void* v0, int32_t it
       s2 = p->aux_stream;
     }
     SR_CHECK(fused2d_spectral(p, small, y, vs, iters, lambda, xs, s2));
+  }
+  // the other 2D problems of a batched plan: one launch per pass level
+  if (want_batched) {
+    std::vector<int> lvl;
+    for (size_t i = 0; i < p->geo.size(); ++i)
+      if (!resident[i] && batch_level_capable(p->geo[i])) lvl.push_back((int)i);
+    if (lvl.size() >= 2) {
+      SR_CHECK(batched_spectral(p, lvl, y, vs, iters, lambda, xs));
+      for (int i : lvl) resident[i] = 1;  // done
+    }
   }
   Batch1D b1;
   for (size_t i = 0; i < p->geo.size(); ++i) {

@@ -115,3 +115,40 @@ def test_batched_workload_shapes(gpu, monkeypatch):
         sl = slice(plan.x_off[i], plan.x_off[i + 1])
         assert np.linalg.norm(xbh[sl] - xlh[sl]) <= 1e-5 * np.linalg.norm(xlh[sl]), i
     assert np.isfinite(xbh).all()
+
+
+@pytest.mark.parametrize("resident", ["0", ""])
+def test_batched_spectral_levels(gpu, monkeypatch, resident):
+    """Power iteration of a batched plan by level launches (each problem with
+    its own sum(y) and norm partials in its descriptors), with the LDS-resident
+    solver off (every problem on the levels) and on (its problems beside the
+    levels): 0, 1, 2, 7 and 61 iterations (past one replayed chunk, and twice
+    for the cached levels and graph), every problem within 1e-4 of the oracle
+    (Eq. (3)-(4)) and within 1e-5 of the per-problem loop."""
+    import torch
+    import paper_2409_05734_amd as srpr
+    monkeypatch.setenv("SR_LDS_RESIDENT", resident)
+    monkeypatch.setenv("SR_TUNE_FORCE", "8,1,1")
+    plan, probs, y, _, _ = _setup(20, 12, gpu)
+    rng = np.random.default_rng(13)
+    v0 = np.concatenate([sr_inputs.complex_gaussian(rng, p["n_shape"]).ravel() for p in probs])
+    v0d = to_dev(v0, gpu)
+    yh = to_host(y)
+    for k in (0, 1, 2, 7, 61, 61):
+        srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_BATCHED)
+        xb = torch.empty_like(v0d)
+        srpr.sr_spectral_init(plan, y, v0d, k, -1.0, xb)
+        srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_LOOP)
+        xl = torch.empty_like(v0d)
+        srpr.sr_spectral_init(plan, y, v0d, k, -1.0, xl)
+        srpr.sr_plan_sync(plan)
+        xbh, xlh = to_host(xb), to_host(xl)
+        for i, p in enumerate(probs):
+            a, b = plan.x_off[i], plan.x_off[i + 1]
+            d = np.linalg.norm(xbh[a:b] - xlh[a:b]) / np.linalg.norm(xlh[a:b])
+            assert d <= 1e-5, (k, i, d)
+            if k in (1, 7) and i % 4 == 0:
+                op = oracle.StructuredOperator(p["theta"], p["n_shape"])
+                xr = oracle.spectral_init(op, yh[plan.y_off[i]:plan.y_off[i + 1]].reshape(p["m_shape"]),
+                                          v0[a:b].reshape(p["n_shape"]), k, -1.0)
+                assert np.linalg.norm(xbh[a:b].reshape(p["n_shape"]) - xr) / np.linalg.norm(xr) <= 1e-4, (k, i)
