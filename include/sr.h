@@ -74,11 +74,15 @@ typedef enum {
  * the pass that sums per-problem partials hold whole problems, else the
  * loop); the first stacked call allocates two grids per problem (plus
  * small per-problem arrays) beside the workspace, kept until sr_plan_destroy.
- * Other plans of 8 or more problems take the batched launches.             */
+ * Other plans of 8 or more problems take the batched schedule.
+ * SR_SCHED_BATCHED: every 2D problem advances one fused pass per launch
+ * (one launch per pass level over all problems, GD and power iteration);
+ * problems whose grid fits one workgroup's LDS solve there instead (power
+ * iteration by default; GD with SR_LDS_RESIDENT=1), beside the levels.     */
 typedef enum {
   SR_SCHED_AUTO = 0,       /* library's choice (above) */
   SR_SCHED_LOOP = 1,       /* one problem after another, one launch per fused pass */
-  SR_SCHED_BATCHED = 2     /* all problems together (persistent batched launches) */
+  SR_SCHED_BATCHED = 2     /* all problems together (level launches, above) */
 } sr_schedule;
 
 /* One phase-retrieval problem.
