@@ -401,9 +401,10 @@ size_t f2_grid_bytes(int M1, int M2) {
 // L = 2: 12.2 ms against 13.9 ms; 256 problems on 128 x 128 grids: 29.4
 // against 26.4 ms (one workgroup per CU); 1024 problems on 64 x 32 grids,
 // L = 1: 12.2 against 9.2 ms (too little work per workgroup).  Not a win
-// often enough to be the default there.  The spectral iteration has no level
-// launches (its problems otherwise run one after another), so there it is
-// the default (SR_LDS_RESIDENT=0 turns it off).
+// often enough to be the default there.  For the power iteration it is the
+// default (SR_LDS_RESIDENT=0 turns it off): on 256 uneven problems, 100
+// iterations, the small ones here beside the level launches of the others
+// take 26.6 ms against 28.1 ms with every problem on the levels.
 bool fused2d_enabled(bool by_default) {
   const char* e = std::getenv("SR_LDS_RESIDENT");
   if (e == nullptr || *e == '\0') return by_default;

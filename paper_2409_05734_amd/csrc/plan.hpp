@@ -174,8 +174,8 @@ sr_status dense_spectral(sr_plan_s* p, const float* y, const float2* v0, int ite
 // fused2d.hip (LDS-resident solves of small 2D problems, one workgroup each)
 // SR_LDS_RESIDENT=1 / 0 turns the LDS-resident solver on / off for batched
 // plans; unset, the caller's default applies (off for GD, where the level
-// launches are as fast; on for the spectral iteration, whose alternative is
-// one problem after another).
+// launches are as fast; on for the power iteration, where it is slightly
+// faster beside the level launches of the larger problems).
 bool fused2d_enabled(bool by_default);
 bool fused2d_supported(const Geo& g);
 sr_status fused2d_gd(sr_plan_s* p, const std::vector<int>& which, const float* y, float2* x, int iters,

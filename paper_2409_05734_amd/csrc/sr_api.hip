@@ -981,8 +981,8 @@ sr_status sr_spectral_init(sr_plan p, const float* y, const void* v0, int32_t it
     if (P > 1 && stack_spectral_ok(p, p->geo[0])) return spectral_stacked(p, P, ths, y, vs, iters, lambda, xs);
   }
   // batched plans: problems whose grid fits one workgroup's LDS run their
-  // whole iteration in the LDS-resident solver (by default: the others run
-  // one problem after another), beside the others' passes
+  // whole solve in the LDS-resident solver (by default), beside the level
+  // launches of the others
   const bool want_batched = p->schedule == SR_SCHED_BATCHED || (p->schedule == SR_SCHED_AUTO && p->geo.size() >= 8);
   std::vector<char> resident(p->geo.size(), 0);
   std::vector<int> small;
