@@ -68,12 +68,13 @@ __device__ __forceinline__ void run_kind_gd(const PassArgs& a, int kind, int til
       pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE, true, false, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
                                                                                 nullptr);
       return;
-    case PK_TURN_GD:
-      pass_tile_rt<N, B, COL, PRE_NONE, MID_GD, true, false, true, POST_STORE>(a, tile, lds, red, nullptr, 0, nullptr);
+    case PK_TURN_GD:  // (loss partials where the descriptor asks for a trace)
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_GD, true, false, true, POST_STORE>(a, tile, lds, red, nullptr, 0,
+                                                                            a.part_out);
       return;
     case PK_TURN_GD_POIS:
       pass_tile_rt<N, B, COL, PRE_NONE, MID_GD_POIS, true, false, true, POST_STORE>(a, tile, lds, red, nullptr, 0,
-                                                                                 nullptr);
+                                                                                 a.part_out);
       return;
     case PK_MID_ADJ:
       pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE_CONJ, true, true, true, POST_STORE>(a, tile, lds, red, nullptr, 0,
@@ -204,7 +205,14 @@ struct BatchState {
   std::string key;
   float2* bufs = nullptr;  // per problem: two full grids
   LevelSet first, steady, last;
+  // with a loss trace: the turnaround of each problem writes its loss
+  // partials (nparts of them, at its own offset), summed per problem
+  bool trace = false;
+  float* parts = nullptr;
+  int2* d_pdesc = nullptr;  // per problem: (offset, count) of its partials
   ~BatchState() {
+    if (parts) hipFree(parts);
+    if (d_pdesc) hipFree(d_pdesc);
     if (bufs) hipFree(bufs);
   }
 };
@@ -215,6 +223,12 @@ void destroy_batch_state(BatchState* s) { delete s; }
 // solver (one launch for the whole solve); the others run as level launches.
 static bool lds_resident(const Geo& g) { return fused2d_enabled(false) && fused2d_supported(g); }
 
+bool batched_any_resident(const sr_plan_s* p) {
+  for (const Geo& g : p->geo)
+    if (lds_resident(g)) return true;
+  return false;
+}
+
 bool batched_supported(const sr_plan_s* p) {
   if (p->kind != SR_STRUCTURED || p->geo.size() < 2) return false;
   for (const Geo& g : p->geo)
@@ -224,7 +238,21 @@ bool batched_supported(const sr_plan_s* p) {
 }
 
 sr_status gd_first_pass_public(sr_plan_s* p, const Geo& g, const float2* x);
-sr_status gd_steady_public(sr_plan_s* p, const Geo& g, const float* y, float2* x, float step, bool last);
+sr_status gd_steady_public(sr_plan_s* p, const Geo& g, const float* y, float2* x, float step, bool last,
+                           float* loss_part = nullptr);
+
+// Loss trace: out[i * ostride] = sum of problem i's partials, in index order
+// (one thread per problem, the order of the single-problem reduction).
+__global__ void batch_loss_reduce(const float* __restrict__ parts, const int2* __restrict__ desc, int count,
+                                  float* out, int ostride) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) {
+    double acc = 0.0;
+    const int2 d = desc[i];
+    for (int k = 0; k < d.y; ++k) acc += (double)parts[d.x + k];
+    out[(long long)i * ostride] = (float)acc;
+  }
+}
 
 // Turn per-problem pass recordings into levels (level q = pass q of every
 // problem that has one) and upload them.
@@ -269,9 +297,11 @@ static sr_status build_levels(sr_plan_s* p, const std::vector<std::vector<PassRe
   return SR_OK;
 }
 
-// Build (or reuse) the level sets for GD on (y, x, eta).
-static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const float* eta, BatchState** out) {
-  std::string key = std::to_string((uintptr_t)y) + ":" + std::to_string((uintptr_t)x);
+// Build (or reuse) the level sets for GD on (y, x, eta), with or without the
+// loss partials of a trace.
+static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const float* eta, bool trace,
+                               BatchState** out) {
+  std::string key = std::to_string((uintptr_t)y) + ":" + std::to_string((uintptr_t)x) + (trace ? ":tr" : "");
   for (size_t i = 0; i < p->geo.size(); ++i) {
     uint32_t u;
     std::memcpy(&u, &eta[i], 4);
@@ -295,6 +325,38 @@ static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const fl
   }
   st->key.clear();
   const size_t np = p->geo.size();
+  std::vector<int> poff(np, 0);
+  if (trace && st->parts == nullptr) {
+    // the turnaround's tiles under the level kernel's widths
+    std::vector<int2> pd(np);
+    int tot = 0;
+    for (size_t i = 0; i < np; ++i) {
+      const Geo& g = p->geo[i];
+      const int k = g.L + 1;
+      const int ntr = (k == 2) ? g.M1 : (pass_col(k) ? g.M2 : g.M1);
+      const int bt = batch_tile_width(pass_len(g, k));
+      pd[i] = make_int2(tot, bt > 0 ? (ntr + bt - 1) / bt : 0);
+      tot += pd[i].y;
+    }
+    hipError_t e = hipMalloc(&st->parts, sizeof(float) * std::max(tot, 1));
+    if (e == hipSuccess) e = hipMalloc(&st->d_pdesc, sizeof(int2) * np);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(st->d_pdesc, pd.data(), sizeof(int2) * np, hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);  // pd goes out of scope
+    if (e != hipSuccess) return fail(SR_E_NOMEM, "loss-trace workspace allocation failed");
+  }
+  if (trace) {
+    int tot = 0;
+    for (size_t i = 0; i < np; ++i) {
+      const Geo& g = p->geo[i];
+      const int k = g.L + 1;
+      const int ntr = (k == 2) ? g.M1 : (pass_col(k) ? g.M2 : g.M1);
+      const int bt = batch_tile_width(pass_len(g, k));
+      poff[i] = tot;
+      tot += bt > 0 ? (ntr + bt - 1) / bt : 0;
+    }
+  }
+  st->trace = trace;
   std::vector<std::vector<PassRecord>> rec_first(np), rec_steady(np), rec_last(np);
   float2* saveA = p->bufA;
   float2* saveB = p->bufB;
@@ -312,9 +374,10 @@ static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const fl
     g_recording = &rec_first[i];
     status = gd_first_pass_public(p, g, xi);
     g_recording = &rec_steady[i];
-    if (status == SR_OK) status = gd_steady_public(p, g, yi, xi, step, false);
+    float* lp = trace ? st->parts + poff[i] : nullptr;
+    if (status == SR_OK) status = gd_steady_public(p, g, yi, xi, step, false, lp);
     g_recording = &rec_last[i];
-    if (status == SR_OK) status = gd_steady_public(p, g, yi, xi, step, true);
+    if (status == SR_OK) status = gd_steady_public(p, g, yi, xi, step, true, lp);
     g_recording = nullptr;
   }
   p->bufA = saveA;
@@ -345,8 +408,12 @@ static sr_status run_levels(sr_plan_s* p, const LevelSet& ls) {
 
 static sr_status batched_levels_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta);
 
-sr_status batched_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta) {
+static sr_status batched_levels_gd_trace(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta,
+                                        float* loss_trace);
+
+sr_status batched_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta, float* loss_trace) {
   if (iters <= 0) return SR_OK;
+  if (loss_trace != nullptr) return batched_levels_gd_trace(p, y, x, iters, eta, loss_trace);
   std::vector<int> small, rest;
   for (size_t i = 0; i < p->geo.size(); ++i) (lds_resident(p->geo[i]) ? small : rest).push_back((int)i);
   if (rest.empty()) return fused2d_gd(p, small, y, x, iters, eta, p->stream);
@@ -367,7 +434,7 @@ sr_status batched_gd(sr_plan_s* p, const float* y, float2* x, int iters, const f
 // GD of the problems that are not LDS-resident, one launch per pass level.
 static sr_status batched_levels_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta) {
   BatchState* st = nullptr;
-  sr_status s = batch_prepare(p, y, x, eta, &st);
+  sr_status s = batch_prepare(p, y, x, eta, false, &st);
   if (s != SR_OK) return s;
   constexpr int kChunk = 50;
   s = run_levels(p, st->first);
@@ -391,6 +458,27 @@ static sr_status batched_levels_gd(sr_plan_s* p, const float* y, float2* x, int 
     if (s != SR_OK) return s;
   }
   return run_levels(p, st->last);
+}
+
+// GD with a loss trace (no LDS-resident problems: the caller checks): the
+// steady iteration's turnaround writes each problem's loss partials, summed
+// per problem into the trace after every iteration (no graph: each
+// iteration writes another trace entry).
+static sr_status batched_levels_gd_trace(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta,
+                                        float* loss_trace) {
+  BatchState* st = nullptr;
+  sr_status s = batch_prepare(p, y, x, eta, true, &st);
+  if (s != SR_OK) return s;
+  if ((s = run_levels(p, st->first)) != SR_OK) return s;
+  const int np = (int)p->geo.size();
+  for (int it = 0; it < iters; ++it) {
+    if ((s = run_levels(p, it == iters - 1 ? st->last : st->steady)) != SR_OK) return s;
+    hipLaunchKernelGGL(batch_loss_reduce, dim3((np + 63) / 64), dim3(64), 0, p->stream, st->parts, st->d_pdesc, np,
+                       loss_trace + it, iters);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "loss-trace reduction");
+  }
+  return SR_OK;
 }
 
 // ------------------------------------------------------------ power iteration

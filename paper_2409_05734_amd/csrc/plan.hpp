@@ -188,7 +188,10 @@ sr_status aux_join(sr_plan_s* p);
 
 // batched.hip (many problems advanced one pass level per launch)
 bool batched_supported(const sr_plan_s* p);
-sr_status batched_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta);
+// (loss_trace: nullable; with it, no problem may be LDS-resident)
+sr_status batched_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta,
+                     float* loss_trace = nullptr);
+bool batched_any_resident(const sr_plan_s* p);
 // power iteration of the listed problems by level launches (2D problems
 // whose lengths the level kernel covers)
 bool batch_level_capable(const Geo& g);

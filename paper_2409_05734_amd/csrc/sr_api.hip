@@ -261,8 +261,9 @@ static sr_status spec_steady(sr_plan_s* p, const Geo& g, const float* y, float2*
 namespace sr {
 // Entry points for the batched schedule, which records these pass sequences.
 sr_status gd_first_pass_public(sr_plan_s* p, const Geo& g, const float2* x) { return first_pass(p, g, x, 1.f, nullptr, 0); }
-sr_status gd_steady_public(sr_plan_s* p, const Geo& g, const float* y, float2* x, float step, bool last) {
-  return gd_steady(p, g, y, x, step, nullptr, last);
+sr_status gd_steady_public(sr_plan_s* p, const Geo& g, const float* y, float2* x, float step, bool last,
+                           float* loss_part) {
+  return gd_steady(p, g, y, x, step, loss_part, last);
 }
 sr_status spec_steady_public(sr_plan_s* p, const Geo& g, const float* y, float2* u, float lam, float inv_mc,
                              const double* ysum, const float* part_in, int npart_in, float* part_out, bool last) {
@@ -865,7 +866,8 @@ sr_status sr_gd_solve(sr_plan p, const float* y, void* x_inout, int32_t iters, c
       return gd_stacked(p, P, ths, y, xs, iters, eta_host, loss_trace);
   }
   const bool want_batched = p->schedule == SR_SCHED_BATCHED || (p->schedule == SR_SCHED_AUTO && p->geo.size() >= 8);
-  if (want_batched && loss_trace == nullptr && batched_supported(p)) return batched_gd(p, y, xs, iters, eta_host);
+  if (want_batched && batched_supported(p) && (loss_trace == nullptr || !batched_any_resident(p)))
+    return batched_gd(p, y, xs, iters, eta_host, loss_trace);
   Batch1D b1;
   for (size_t i = 0; i < p->geo.size(); ++i) {
     const Geo& g = p->geo[i];

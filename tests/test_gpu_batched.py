@@ -152,3 +152,46 @@ def test_batched_spectral_levels(gpu, monkeypatch, resident):
                 xr = oracle.spectral_init(op, yh[plan.y_off[i]:plan.y_off[i + 1]].reshape(p["m_shape"]),
                                           v0[a:b].reshape(p["n_shape"]), k, -1.0)
                 assert np.linalg.norm(xbh[a:b].reshape(p["n_shape"]) - xr) / np.linalg.norm(xr) <= 1e-4, (k, i)
+
+
+@pytest.mark.parametrize("loss", ["l2", "poisson"])
+def test_batched_gd_loss_trace(gpu, monkeypatch, loss):
+    """GD with a loss trace on the batched levels (each problem's turnaround
+    writes its loss partials; one reduction per iteration for all problems):
+    over 8 steps, every problem's iterate within 1e-5 of the per-problem loop
+    and its trace within 1e-4 of the oracle's (and of the loop's)."""
+    import torch
+    import paper_2409_05734_amd as srpr
+    monkeypatch.setenv("SR_TUNE_FORCE", "8,1,1")
+    plan, probs, y, x0, eta = _setup(16, 14, gpu)
+    yh = to_host(y)
+    eps = float(1e-2 * np.mean(yh))
+    if loss == "poisson":
+        srpr.sr_plan_set_loss(plan, srpr.SR_LOSS_POISSON, eps)
+        eta = (eta * 0.25 * np.float32(np.mean(yh))).astype(np.float32)  # the Poisson gradient is O(1), not O(y)
+    k = 8
+    out = {}
+    for sched in (srpr.SR_SCHED_BATCHED, srpr.SR_SCHED_LOOP):
+        srpr.sr_plan_set_schedule(plan, sched)
+        x = to_dev(x0, gpu)
+        lt = torch.zeros(k * len(probs), dtype=torch.float32, device=gpu)
+        srpr.sr_gd_solve(plan, y, x, k, eta, lt)
+        srpr.sr_plan_sync(plan)
+        out[sched] = (to_host(x), to_host(lt).reshape(len(probs), k))
+    xb, lb = out[srpr.SR_SCHED_BATCHED]
+    xl, ll = out[srpr.SR_SCHED_LOOP]
+    finite = 0
+    for i, p in enumerate(probs):
+        a, b = plan.x_off[i], plan.x_off[i + 1]
+        if not (np.isfinite(xl[a:b]).all() and np.isfinite(ll[i]).all()):
+            continue  # a random start that diverges (the oracle's too) within these steps
+        finite += 1
+        assert np.linalg.norm(xb[a:b] - xl[a:b]) / np.linalg.norm(xl[a:b]) <= 1e-5, i
+        assert np.max(np.abs(lb[i] - ll[i]) / np.abs(ll[i])) <= 1e-4, i
+        if i % 5 == 0:
+            op = oracle.StructuredOperator(p["theta"], p["n_shape"])
+            kw = dict(loss="poisson", eps=eps) if loss == "poisson" else {}
+            _, lr = oracle.gd_solve(op, yh[plan.y_off[i]:plan.y_off[i + 1]].reshape(p["m_shape"]),
+                                    x0[a:b].reshape(p["n_shape"]), k, float(eta[i]), return_loss=True, **kw)
+            assert np.max(np.abs(lb[i] - lr) / np.abs(lr)) <= 1e-4, i
+    assert finite >= len(probs) - 2
