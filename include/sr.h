@@ -130,6 +130,21 @@ sr_status sr_plan_set_theta(sr_plan plan, const float* theta_dev, int64_t theta_
 /* Bytes of device workspace the plan uses (allocated by sr_plan_create).      */
 sr_status sr_plan_workspace_size(sr_plan plan, size_t* bytes);
 
+/* Move the plan's workspace (phases and their exp(i theta) table, twiddles,
+ * pass buffers, reduction scratch) into caller-owned device memory, e.g. a
+ * tensor of the caller's allocator.
+ *  dev_ptr  device pointer, 256-byte aligned, at least
+ *           sr_plan_workspace_size bytes, not overlapping the current
+ *           workspace; the caller keeps it alive until sr_plan_destroy (or
+ *           the next sr_plan_set_workspace) and frees it afterwards.
+ * Waits for the plan's queued work, copies the contents, releases the
+ * plan's own allocation (the caller's earlier memory is left alone) and
+ * drops recorded schedules and captured graphs (they are rebuilt on use).
+ * Memory the plan allocates on first use of some schedules (stacks, batched
+ * levels, derivatives) stays the plan's.  SR_E_ARG on NULL, short or
+ * misaligned memory.                                                       */
+sr_status sr_plan_set_workspace(sr_plan plan, void* dev_ptr, size_t bytes);
+
 /* Per-problem offsets (in complex elements) into concatenated signal arrays
  * (x_off, n-sized) and measurement arrays (y_off, m-sized).  Both are host
  * arrays of nprob + 1 entries; either may be NULL.                           */

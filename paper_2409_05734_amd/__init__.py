@@ -22,7 +22,7 @@ from ._lib import (SR_DENSE, SR_LOSS_L2, SR_LOSS_POISSON, SR_SCHED_AUTO, SR_SCHE
 
 __all__ = [
     "Problem", "Plan", "SrError",
-    "sr_plan_set_theta", "sr_plan_workspace_size", "sr_plan_offsets", "sr_plan_set_schedule", "sr_plan_set_loss",
+    "sr_plan_set_theta", "sr_plan_workspace_size", "sr_plan_set_workspace", "sr_plan_offsets", "sr_plan_set_schedule", "sr_plan_set_loss",
     "sr_plan_sync",
     "sr_forward", "sr_adjoint", "sr_spectral_init", "sr_gd_solve", "sr_forward_vjp", "sr_adjoint_vjp",
     "SR_STRUCTURED", "SR_DENSE", "SR_SCHED_AUTO", "SR_SCHED_LOOP", "SR_SCHED_BATCHED", "SR_LOSS_L2", "SR_LOSS_POISSON",
@@ -169,6 +169,19 @@ def sr_plan_workspace_size(plan: Plan) -> int:
     v = ctypes.c_size_t()
     _lib.call("sr_plan_workspace_size", plan.handle, ctypes.byref(v))
     return v.value
+
+
+def sr_plan_set_workspace(plan: Plan, workspace) -> None:
+    """Move the plan's workspace into `workspace`, a contiguous uint8 GPU
+    tensor of at least sr_plan_workspace_size bytes, 256-byte aligned; the
+    plan keeps a reference to it."""
+    torch = _torch()
+    if not isinstance(workspace, torch.Tensor) or workspace.device.type != "cuda":
+        raise TypeError("workspace must be a GPU tensor")
+    if workspace.dtype != torch.uint8 or not workspace.is_contiguous():
+        raise TypeError("workspace must be a contiguous uint8 tensor")
+    _lib.call("sr_plan_set_workspace", plan.handle, ctypes.c_void_p(workspace.data_ptr()), workspace.numel())
+    plan._workspace = workspace
 
 
 def sr_plan_offsets(plan: Plan):

@@ -48,6 +48,7 @@ SIGNATURES = {
     "sr_plan_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(SrProblem), _i32, _vp, _i64, _vp, _vp]),
     "sr_plan_set_theta": (ctypes.c_int, [_vp, _vp, _i64]),
     "sr_plan_workspace_size": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "sr_plan_set_workspace": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     "sr_plan_offsets": (ctypes.c_int, [_vp, _vp, _vp]),
     "sr_plan_set_schedule": (ctypes.c_int, [_vp, _i32]),
     "sr_plan_set_loss": (ctypes.c_int, [_vp, _i32, _f32]),

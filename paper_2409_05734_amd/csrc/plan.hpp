@@ -93,6 +93,7 @@ struct sr_plan_s {
   // workspace carved out of one allocation
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  bool ws_owned = true;  // false once the caller's memory holds the workspace
   float2* bufA = nullptr;  // ping-pong pass buffers (max m complex each)
   float2* bufB = nullptr;
   float2* bufC = nullptr;  // extra grid buffers for derivatives

@@ -12,6 +12,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/sr.h"
@@ -665,6 +666,49 @@ sr_status sr_plan_set_theta(sr_plan p, const float* theta_dev, int64_t theta_len
 sr_status sr_plan_workspace_size(sr_plan p, size_t* bytes) {
   if (p == nullptr || bytes == nullptr) return fail(SR_E_ARG, "NULL argument");
   *bytes = p->ws_bytes;
+  return SR_OK;
+}
+
+sr_status sr_plan_set_workspace(sr_plan p, void* dev_ptr, size_t bytes) {
+  if (p == nullptr || dev_ptr == nullptr) return fail(SR_E_ARG, "NULL argument");
+  if (bytes < p->ws_bytes) return fail(SR_E_ARG, "workspace smaller than sr_plan_workspace_size");
+  if (((uintptr_t)dev_ptr & 255) != 0) return fail(SR_E_ARG, "workspace must be 256-byte aligned");
+  if (dev_ptr == p->ws) return SR_OK;
+  const uintptr_t lo = (uintptr_t)dev_ptr, hi = lo + p->ws_bytes, olo = (uintptr_t)p->ws, ohi = olo + p->ws_bytes;
+  if (lo < ohi && olo < hi) return fail(SR_E_ARG, "workspace overlaps the current one");
+  // queued work still uses the old workspace: finish it, move the contents
+  SR_HIP(hipStreamSynchronize(p->stream));
+  if (p->aux_stream) SR_HIP(hipStreamSynchronize(p->aux_stream));
+  SR_HIP(hipMemcpyAsync(dev_ptr, p->ws, p->ws_bytes, hipMemcpyDeviceToDevice, p->stream));
+  SR_HIP(hipStreamSynchronize(p->stream));
+  const ptrdiff_t d = (char*)dev_ptr - (char*)p->ws;
+  auto mv = [d](auto*& q) {
+    if (q != nullptr) q = (std::remove_reference_t<decltype(q)>)((char*)q + d);
+  };
+  mv(p->theta);
+  mv(p->eph);
+  mv(p->twbuf);
+  mv(p->bufA);
+  mv(p->bufB);
+  mv(p->bufC);
+  mv(p->bufD);
+  mv(p->part);
+  mv(p->ysum);
+  mv(p->fscratch);
+  mv(p->sync);
+  mv(p->red_ws);
+  mv(p->dsplit);
+  for (auto& t : p->tw) mv(t.second);
+  // recorded schedules and captured graphs hold the old addresses
+  for (auto& g : p->graphs) hipGraphExecDestroy(g.second);
+  p->graphs.clear();
+  if (p->batch) destroy_batch_state(p->batch);
+  p->batch = nullptr;
+  if (p->spec_batch) destroy_spec_batch_state(p->spec_batch);
+  p->spec_batch = nullptr;
+  if (p->ws_owned) SR_HIP(hipFree(p->ws));
+  p->ws = dev_ptr;
+  p->ws_owned = false;
   return SR_OK;
 }
 

@@ -90,5 +90,6 @@ def test_null_and_kind_errors(lib):
     assert st == -1  # mixed kinds
     assert lib.sr_forward(None, None, None, None) == -1
     assert lib.sr_plan_set_loss(None, 0, 0.0) == -1
+    assert lib.sr_plan_set_workspace(None, None, 0) == -1
     assert lib.sr_plan_destroy(None) == 0
     assert lib.sr_status_string(-3).decode() == "unsupported configuration"
