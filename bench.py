@@ -379,6 +379,40 @@ def batched(torch, srpr, sr_inputs, dev, iters=300):
             "max_err_gap_finite": float(np.max(np.abs((eb - el)[np.isfinite(eb) & np.isfinite(el)])))}
 
 
+def latency_floor(torch, srpr, sr_inputs, dev, reps=400):
+    """What a kernel boundary costs at the headline's size, for comparison
+    with its passes (2L = 4 kernels per GD iteration): graph-replayed chains
+    of a one-element elementwise kernel (the launch floor) and of a 2 MiB
+    elementwise kernel (one 512^2 complex64 grid read and written, as a pass
+    does, without the FFTs), per kernel."""
+    out = {"workload": f"HIP graph of {reps} dependent elementwise kernels, replayed"}
+    s = torch.cuda.Stream()
+    for name, numel in (("tiny_kernel_us", 1), ("grid_2MiB_kernel_us", 512 * 512)):
+        a = torch.ones(numel, dtype=torch.complex64, device=dev)
+        b = torch.empty_like(a)
+        with torch.cuda.stream(s):
+            torch.add(a, 1.0, out=b)
+            torch.add(b, 1.0, out=a)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            for i in range(reps // 2):
+                torch.add(a, 1.0, out=b)
+                torch.add(b, 1.0, out=a)
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch, 2)
+        cur = torch.cuda.current_stream()  # replay() launches on the current stream
+        e0.record(cur)
+        for _ in range(3):
+            g.replay()
+        e1.record(cur)
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) * 1e3 / (3 * reps)
+        del g, a, b
+    return out
+
+
 def library_loop(torch, srpr, sr_inputs, dev, iters=200):
     """The headline's GD iteration written with PyTorch's FFT (rocFFT) and
     elementwise ops on the same GPU, one library call at a time (pad, L x
@@ -872,7 +906,7 @@ def main():
     if not args.quick:
         extras = {}
         side = (("large_2d", large_2d), ("dense_baseline", dense), ("batched", batched),
-                ("library_loop", library_loop), ("stacked_gd", stacked_gd), ("autograd", autograd), ("lds_resident_2d", lds_resident), ("forward_time_sweep", forward_time_sweep),
+                ("latency_floor", latency_floor), ("library_loop", library_loop), ("stacked_gd", stacked_gd), ("autograd", autograd), ("lds_resident_2d", lds_resident), ("forward_time_sweep", forward_time_sweep),
                 ("layer_study", layer_study), ("poisson_loss", poisson_loss), ("tiny_1d", tiny_1d),
                 ("accuracy_sweep", accuracy_sweep))
         on_request = {"accuracy_sweep"}  # about a minute of GPU time: run only when named
