@@ -325,6 +325,20 @@ struct Tile {
     }
   }
 
+  // Fence between the LDS writes of one stage and the reads of the next: a
+  // workgroup barrier, or, when the whole tile is one wavefront, only a
+  // wavefront-scope fence (the LDS operations of one wavefront complete in
+  // issue order, so nothing waits on other waves).
+  __device__ __forceinline__ static void xsync() {
+    if constexpr (THREADS <= 64) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+      __syncthreads();
+    }
+  }
+
   template <bool INV, int S>
   __device__ __forceinline__ static void stage(float2 (&v)[E], float2* lds, int& phase, const Twiddles& w, int t,
                                                int b) {
@@ -335,7 +349,7 @@ struct Tile {
       static_assert(E % R == 0, "radix must divide elements per thread");
       if constexpr (S > 0) {
         // inputs of this stage: canonical positions in the buffer written last
-        __syncthreads();
+        xsync();
         float2* src = DB ? lds + (phase ^ 1) * BUF : lds;
 #pragma unroll
         for (int j = 0; j < E; ++j) v[j] = src[lidx(b, elem(t, j))];
@@ -359,7 +373,7 @@ struct Tile {
           if constexpr (!DB) {
             // single buffer: every thread must be done reading it (this stage's
             // loads, or an earlier transform's) before anyone overwrites it
-            if (q == 0) __syncthreads();
+            if (q == 0) xsync();
           }
           float2* dst = DB ? lds + phase * BUF : lds;
           const int base = (i / P) * P * R + k;

@@ -276,13 +276,13 @@ def test_stacked_extremes(gpu, monkeypatch, n_shape, m_shape, L, P, shared):
     """The smallest stack (two problems) and stacks of hundreds of small
     problems: A with only z or only |z|^2 stored, A^H, 3 and 55 GD steps
     (past one graph chunk) and 3 power iterations, each bit-identical to the
-    loop; the last problem against the oracle.  (Power iteration on shapes a
-    stack cannot take falls back to the LDS-resident solver on plans of 8 or
-    more problems, which rounds differently: switched off here so that the
-    fallback is the loop.)"""
+    loop; the last problem against the oracle.  (Two-column tiles, so that
+    every stack here can take the power iteration too: where it cannot,
+    plans of 8 or more problems fall back to the batched schedule, which
+    rounds differently.)"""
     import torch
     import paper_2409_05734_amd as srpr
-    monkeypatch.setenv("SR_LDS_RESIDENT", "0")
+    monkeypatch.setenv("SR_TUNE_FORCE", "2,1,1")
     rng = np.random.default_rng(hash((n_shape, m_shape, L, P, "ext")) % 2**32)
     g = _grid(n_shape, m_shape)
     nblk = 1 if shared else P
