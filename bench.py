@@ -342,7 +342,13 @@ def batched(torch, srpr, sr_inputs, dev, iters=300):
 
     def run_spec():
         srpr.sr_spectral_init(plan, y, v0, 100, -1.0, est)
+    xsd = torch.from_numpy(xs).to(dev)
+    yop = torch.empty_like(y)
+
+    def run_fwd():
+        srpr.sr_forward(plan, xsd, None, yop)
     srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_BATCHED)
+    bf_ms = _time_calls(torch, s, run_fwd, 20, warm=2)
     b_ms = _time_calls(torch, s, run, 3, warm=1)
     xb = x.clone()
     bs_ms = _time_calls(torch, s, run_spec, 3, warm=1)
@@ -350,6 +356,7 @@ def batched(torch, srpr, sr_inputs, dev, iters=300):
     srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_LOOP)
     l_ms = _time_calls(torch, s, run, 1, warm=1)
     ls_ms = _time_calls(torch, s, run_spec, 1, warm=1)
+    lf_ms = _time_calls(torch, s, run_fwd, 5, warm=1)
     spec_rel = float(((eb_spec - est).abs().pow(2).sum() / est.abs().pow(2).sum()).sqrt())
     # accuracy of both schedules per problem: phase-aligned relative error to x*
     xbh, xlh = xb.cpu().numpy().astype(np.complex128), x.cpu().numpy().astype(np.complex128)
@@ -367,6 +374,7 @@ def batched(torch, srpr, sr_inputs, dev, iters=300):
     byt = sum(schedule_bytes_gd(p["n_shape"], p["m_shape"], p["layers"]) for p in probs)
     return {"workload": "256 problems, N in {32,64,96,128}^2, alpha in {2,4,8}, L in {1,2,3}, 300 GD steps",
             "batched_ms": b_ms, "loop_ms": l_ms, "speedup_vs_loop": l_ms / b_ms,
+            "forward_batched_us": bf_ms * 1e3, "forward_loop_us": lf_ms * 1e3,
             "spectral_100_batched_ms": bs_ms, "spectral_100_loop_ms": ls_ms,
             "spectral_speedup_vs_loop": ls_ms / bs_ms, "spectral_rel_diff_vs_loop": spec_rel,
             "batched_gd_iters_per_s": iters / (b_ms * 1e-3),

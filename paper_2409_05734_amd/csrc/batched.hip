@@ -127,15 +127,62 @@ __device__ __forceinline__ void run_kind_spec(const PassArgs& a, int kind, int t
   }
 }
 
+// The passes of A and A^H alone.
+template <int N, bool COL>
+__device__ __forceinline__ void run_kind_op(const PassArgs& a, int kind, int tile, float2* lds, float* red) {
+  constexpr int B = batch_b<N>();
+  if constexpr (COL) {
+    switch (kind) {
+      case PK_FIRST_FWD:
+        pass_tile_rt<N, B, COL, PRE_PHASE, MID_NONE, false, false, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
+                                                                                   nullptr);
+        return;
+      case PK_LAST_ADJ:
+        pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_PHASE_CONJ_STORE>(a, tile, lds, red,
+                                                                                            nullptr, 0, nullptr);
+        return;
+      default:
+        break;
+    }
+  }
+  switch (kind) {
+    case PK_MID_FWD:
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE, true, false, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
+                                                                                nullptr);
+      return;
+    case PK_LAST_STORE:
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_STORE, false, false, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
+                                                                                 nullptr);
+      return;
+    case PK_FIRST_ADJ:
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
+                                                                               nullptr);
+      return;
+    case PK_MID_ADJ:
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE_CONJ, true, true, true, POST_STORE>(a, tile, lds, red, nullptr, 0,
+                                                                                   nullptr);
+      return;
+    default:
+      return;
+  }
+}
+
 constexpr size_t kBatchLds = 2 * sizeof(float2) * kBatchThreads * 12;  // covers 2 * B * NP elements for E <= 12
 
-template <int N, bool SPEC>
+// Pass sets of the level kernel, one instantiation each (so that no set
+// carries the registers of the others).
+enum LevelSetKind : int { LS_GD = 0, LS_SPEC = 1, LS_OP = 2 };
+
+template <int N, int SET>
 __device__ __forceinline__ void run_len(const BatchDesc& d, int tile, float2* lds, float* red) {
   static_assert(Tile<N, batch_b<N>(), true>::THREADS == kBatchThreads, "batched tiles are 256 threads");
   static_assert(2 * sizeof(float2) * Tile<N, batch_b<N>(), true>::BUF <= kBatchLds, "batched LDS budget");
-  if constexpr (SPEC) {
+  if constexpr (SET == LS_SPEC) {
     if (d.col) run_kind_spec<N, true>(d.a, d.kind, tile, lds, red);
     else run_kind_spec<N, false>(d.a, d.kind, tile, lds, red);
+  } else if constexpr (SET == LS_OP) {
+    if (d.col) run_kind_op<N, true>(d.a, d.kind, tile, lds, red);
+    else run_kind_op<N, false>(d.a, d.kind, tile, lds, red);
   } else {
     if (d.col) run_kind_gd<N, true>(d.a, d.kind, tile, lds, red);
     else run_kind_gd<N, false>(d.a, d.kind, tile, lds, red);
@@ -145,9 +192,7 @@ __device__ __forceinline__ void run_len(const BatchDesc& d, int tile, float2* ld
 // Three workgroups per CU (the LDS budget's limit): the compiler fits the
 // kernel in 168 VGPRs (a small spill on the twelve-element lengths) instead of
 // 197, which held it to two; measured 71 -> 62.5 ms on 256 uneven problems.
-// (SPEC: the power-iteration pass set, a kernel of its own so that the GD
-// kernel's registers are not those of both sets)
-template <bool SPEC>
+template <int SET>
 __global__ void __launch_bounds__(kBatchThreads, 3) batched_level_kernel(const BatchItem* __restrict__ items,
                                                                       const BatchDesc* __restrict__ descs) {
   extern __shared__ float2 lds[];
@@ -155,15 +200,15 @@ __global__ void __launch_bounds__(kBatchThreads, 3) batched_level_kernel(const B
   const BatchItem it = items[xcd_tile(blockIdx.x, gridDim.x)];
   const BatchDesc& d = descs[it.desc];
   switch (d.N) {
-    case 16: run_len<16, SPEC>(d, it.tile, lds, red); break;
-    case 32: run_len<32, SPEC>(d, it.tile, lds, red); break;
-    case 64: run_len<64, SPEC>(d, it.tile, lds, red); break;
-    case 96: run_len<96, SPEC>(d, it.tile, lds, red); break;
-    case 128: run_len<128, SPEC>(d, it.tile, lds, red); break;
-    case 192: run_len<192, SPEC>(d, it.tile, lds, red); break;
-    case 256: run_len<256, SPEC>(d, it.tile, lds, red); break;
-    case 384: run_len<384, SPEC>(d, it.tile, lds, red); break;
-    case 512: run_len<512, SPEC>(d, it.tile, lds, red); break;
+    case 16: run_len<16, SET>(d, it.tile, lds, red); break;
+    case 32: run_len<32, SET>(d, it.tile, lds, red); break;
+    case 64: run_len<64, SET>(d, it.tile, lds, red); break;
+    case 96: run_len<96, SET>(d, it.tile, lds, red); break;
+    case 128: run_len<128, SET>(d, it.tile, lds, red); break;
+    case 192: run_len<192, SET>(d, it.tile, lds, red); break;
+    case 256: run_len<256, SET>(d, it.tile, lds, red); break;
+    case 384: run_len<384, SET>(d, it.tile, lds, red); break;
+    case 512: run_len<512, SET>(d, it.tile, lds, red); break;
     default: break;
   }
 }
@@ -187,7 +232,7 @@ int batch_tile_width(int N) {
 
 // Level lists of one recorded pass sequence (device descriptors and items).
 struct LevelSet {
-  bool spec = false;  // power-iteration passes (the other kernel)
+  int set = LS_GD;  // pass set (which instantiation of the level kernel)
   BatchDesc* d_descs = nullptr;
   BatchItem* d_items = nullptr;
   std::vector<int> level_off, level_cnt;  // item ranges per level
@@ -394,12 +439,14 @@ static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const fl
 static sr_status run_levels(sr_plan_s* p, const LevelSet& ls) {
   for (size_t q = 0; q < ls.level_cnt.size(); ++q) {
     if (ls.level_cnt[q] == 0) continue;
-    if (ls.spec)
-      hipLaunchKernelGGL(batched_level_kernel<true>, dim3(ls.level_cnt[q]), dim3(kBatchThreads), kBatchLds, p->stream,
-                         ls.d_items + ls.level_off[q], ls.d_descs);
+    const dim3 grid(ls.level_cnt[q]), block(kBatchThreads);
+    const BatchItem* items = ls.d_items + ls.level_off[q];
+    if (ls.set == LS_SPEC)
+      hipLaunchKernelGGL(batched_level_kernel<LS_SPEC>, grid, block, kBatchLds, p->stream, items, ls.d_descs);
+    else if (ls.set == LS_OP)
+      hipLaunchKernelGGL(batched_level_kernel<LS_OP>, grid, block, kBatchLds, p->stream, items, ls.d_descs);
     else
-      hipLaunchKernelGGL(batched_level_kernel<false>, dim3(ls.level_cnt[q]), dim3(kBatchThreads), kBatchLds,
-                         p->stream, ls.d_items + ls.level_off[q], ls.d_descs);
+      hipLaunchKernelGGL(batched_level_kernel<LS_GD>, grid, block, kBatchLds, p->stream, items, ls.d_descs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "batched level launch");
   }
@@ -479,6 +526,77 @@ static sr_status batched_levels_gd_trace(sr_plan_s* p, const float* y, float2* x
     if (e != hipSuccess) return hip_fail(e, "loss-trace reduction");
   }
   return SR_OK;
+}
+
+// ------------------------------------------------------------ A and A^H
+// One application of A (or A^H) to every listed problem, one launch per pass
+// level.  The recorded levels are kept per direction for the last pointers
+// they were built for.
+
+sr_status forward_2d_public(sr_plan_s* p, const Geo& g, const float2* x, float2* z, float* y);
+sr_status adjoint_2d_public(sr_plan_s* p, const Geo& g, const float2* r, float2* x);
+
+struct OpBatchState {
+  float2* bufs = nullptr;  // per problem of the plan: two full grids
+  std::vector<size_t> buf_off;
+  std::string key[2];
+  LevelSet ls[2];  // [0] A, [1] A^H
+  ~OpBatchState() {
+    if (bufs) hipFree(bufs);
+  }
+};
+
+void destroy_op_batch_state(OpBatchState* s) { delete s; }
+
+sr_status batched_operator(sr_plan_s* p, const std::vector<int>& which, bool adjoint, const float2* in, float2* out,
+                           float* y_out) {
+  OpBatchState* st = p->op_batch;
+  if (st == nullptr) {
+    st = new OpBatchState();
+    p->op_batch = st;
+    size_t elems = 0;
+    st->buf_off.assign(p->geo.size(), 0);
+    for (size_t i = 0; i < p->geo.size(); ++i) {
+      st->buf_off[i] = elems;
+      if (batch_level_capable(p->geo[i])) elems += 2 * (size_t)p->geo[i].mg;
+    }
+    if (hipMalloc(&st->bufs, std::max<size_t>(elems, 1) * sizeof(float2)) != hipSuccess) {
+      st->bufs = nullptr;
+      return fail(SR_E_NOMEM, "batched operator workspace allocation failed");
+    }
+  }
+  const int d = adjoint ? 1 : 0;
+  std::string key = std::to_string((uintptr_t)in) + ":" + std::to_string((uintptr_t)out) + ":" +
+                    std::to_string((uintptr_t)y_out);
+  for (int i : which) key += "," + std::to_string(i);
+  if (st->key[d] != key) {
+    st->key[d].clear();
+    const size_t np = p->geo.size();
+    std::vector<std::vector<PassRecord>> rec(np);
+    float2* saveA = p->bufA;
+    float2* saveB = p->bufB;
+    sr_status status = SR_OK;
+    for (int i : which) {
+      if (status != SR_OK) break;
+      const Geo& g = p->geo[i];
+      p->bufA = st->bufs + st->buf_off[i];  // each problem's private ping-pong buffers
+      p->bufB = st->bufs + st->buf_off[i] + g.mg;
+      g_recording = &rec[i];
+      if (adjoint)
+        status = adjoint_2d_public(p, g, in + p->yoff[i], out + p->xoff[i]);
+      else
+        status = forward_2d_public(p, g, in + p->xoff[i], out ? out + p->yoff[i] : nullptr,
+                                   y_out ? y_out + p->yoff[i] : nullptr);
+      g_recording = nullptr;
+    }
+    p->bufA = saveA;
+    p->bufB = saveB;
+    if (status != SR_OK) return status;
+    st->ls[d].set = LS_OP;
+    if ((status = build_levels(p, rec, st->ls[d])) != SR_OK) return status;
+    st->key[d] = key;
+  }
+  return run_levels(p, st->ls[d]);
 }
 
 // ------------------------------------------------------------ power iteration
@@ -590,7 +708,7 @@ static sr_status spec_prepare(sr_plan_s* p, const std::vector<int>& which, const
   LevelSet* sets[7] = {&st->first, &st->it0, &st->it0_last, &st->odd, &st->odd_last, &st->even, &st->even_last};
   std::vector<std::vector<PassRecord>>* recsets[7] = {&r_first, &r_it0, &r_it0l, &r_odd, &r_oddl, &r_even, &r_evenl};
   for (int k = 0; k < 7; ++k) {
-    sets[k]->spec = true;
+    sets[k]->set = LS_SPEC;
     if ((status = build_levels(p, *recsets[k], *sets[k])) != SR_OK) return status;
   }
   st->key = key;

@@ -40,6 +40,8 @@ struct BatchState;
 void destroy_batch_state(BatchState* s);
 struct SpecBatchState;
 void destroy_spec_batch_state(SpecBatchState* s);
+struct OpBatchState;
+void destroy_op_batch_state(OpBatchState* s);
 
 // A stack of problems of one geometry run as one: every fused pass of the
 // first problem's schedule is launched once for all P problems, each buffer
@@ -117,6 +119,7 @@ struct sr_plan_s {
   int stk_steps_cap = 0;
   sr::BatchState* batch = nullptr;  // batched-schedule state (built on first batched solve)
   sr::SpecBatchState* spec_batch = nullptr;  // the same for batched power iteration
+  sr::OpBatchState* op_batch = nullptr;      // and for batched A / A^H
   size_t vjp_elems = 0;
 
   // LDS-resident small-problem solver (fused2d.hip): device descriptors, their
@@ -196,6 +199,9 @@ bool batched_any_resident(const sr_plan_s* p);
 // power iteration of the listed problems by level launches (2D problems
 // whose lengths the level kernel covers)
 bool batch_level_capable(const Geo& g);
+// one application of A (adjoint: A^H) to the listed problems by level launches
+sr_status batched_operator(sr_plan_s* p, const std::vector<int>& which, bool adjoint, const float2* in, float2* out,
+                           float* y_out);
 sr_status batched_spectral(sr_plan_s* p, const std::vector<int>& which, const float* y, const float2* v0, int iters,
                            float lam, float2* x);
 

@@ -266,6 +266,10 @@ sr_status gd_steady_public(sr_plan_s* p, const Geo& g, const float* y, float2* x
                            float* loss_part) {
   return gd_steady(p, g, y, x, step, loss_part, last);
 }
+sr_status forward_2d_public(sr_plan_s* p, const Geo& g, const float2* x, float2* z, float* y) {
+  return forward_2d(p, g, x, z, y);
+}
+sr_status adjoint_2d_public(sr_plan_s* p, const Geo& g, const float2* r, float2* x) { return adjoint_2d(p, g, r, x); }
 sr_status spec_steady_public(sr_plan_s* p, const Geo& g, const float* y, float2* u, float lam, float inv_mc,
                              const double* ysum, const float* part_in, int npart_in, float* part_out, bool last) {
   return spec_steady(p, g, y, u, lam, inv_mc, ysum, part_in, npart_in, part_out, last);
@@ -706,6 +710,8 @@ sr_status sr_plan_set_workspace(sr_plan p, void* dev_ptr, size_t bytes) {
   p->batch = nullptr;
   if (p->spec_batch) destroy_spec_batch_state(p->spec_batch);
   p->spec_batch = nullptr;
+  if (p->op_batch) destroy_op_batch_state(p->op_batch);
+  p->op_batch = nullptr;
   if (p->ws_owned) SR_HIP(hipFree(p->ws));
   p->ws = dev_ptr;
   p->ws_owned = false;
@@ -780,6 +786,21 @@ static sr_status adjoint_stacked(sr_plan_s* p, int P, int ths, const float2* r, 
   return adjoint_2d(p, g, r, x);
 }
 
+// A batched plan applies A (A^H) to its 2D problems by level launches; the
+// rest (1D problems, lengths the level kernel lacks) stay with the loop.
+static sr_status batched_op_part(sr_plan_s* p, bool adjoint, const float2* in, float2* out, float* y,
+                                 std::vector<char>& done) {
+  const bool want_batched = p->schedule == SR_SCHED_BATCHED || (p->schedule == SR_SCHED_AUTO && p->geo.size() >= 8);
+  if (!want_batched) return SR_OK;
+  std::vector<int> lvl;
+  for (size_t i = 0; i < p->geo.size(); ++i)
+    if (batch_level_capable(p->geo[i])) lvl.push_back((int)i);
+  if (lvl.size() < 2) return SR_OK;
+  SR_CHECK(batched_operator(p, lvl, adjoint, in, out, y));
+  for (int i : lvl) done[i] = 1;
+  return SR_OK;
+}
+
 sr_status sr_forward(sr_plan p, const void* x, void* z, float* y) {
   if (p == nullptr || x == nullptr) return fail(SR_E_ARG, "NULL argument");
   if (z == nullptr && y == nullptr) return fail(SR_E_ARG, "need z or y");
@@ -789,8 +810,11 @@ sr_status sr_forward(sr_plan p, const void* x, void* z, float* y) {
   int ths = 0;
   const int P = stack_size(p, &ths);
   if (P > 1) return forward_stacked(p, P, ths, xs, zs, y);
+  std::vector<char> done(p->geo.size(), 0);
+  SR_CHECK(batched_op_part(p, false, xs, zs, y, done));
   Batch1D b1;
   for (size_t i = 0; i < p->geo.size(); ++i) {
+    if (done[i]) continue;
     const Geo& g = p->geo[i];
     const float2* xi = xs + p->xoff[i];
     float2* zi = zs ? zs + p->yoff[i] : nullptr;
@@ -816,8 +840,11 @@ sr_status sr_adjoint(sr_plan p, const void* r, void* x_out) {
   int ths = 0;
   const int P = stack_size(p, &ths);
   if (P > 1) return adjoint_stacked(p, P, ths, rs, xs);
+  std::vector<char> done(p->geo.size(), 0);
+  SR_CHECK(batched_op_part(p, true, rs, xs, nullptr, done));
   Batch1D b1;
   for (size_t i = 0; i < p->geo.size(); ++i) {
+    if (done[i]) continue;
     const Geo& g = p->geo[i];
     if (g.ndim == 1) {
       Fused1DArgs a{};

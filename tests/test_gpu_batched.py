@@ -195,3 +195,52 @@ def test_batched_gd_loss_trace(gpu, monkeypatch, loss):
                                     x0[a:b].reshape(p["n_shape"]), k, float(eta[i]), return_loss=True, **kw)
             assert np.max(np.abs(lb[i] - lr) / np.abs(lr)) <= 1e-4, i
     assert finite >= len(probs) - 2
+
+
+def test_batched_operator_levels(gpu):
+    """A and A^H of a batched plan by level launches (z and |z|^2 together
+    and apart, and A^H; each twice, for the cached levels): every problem
+    within 2e-5 of the per-problem loop, sampled problems against the oracle
+    (Eq. (5))."""
+    import torch
+    import paper_2409_05734_amd as srpr
+    probs = sr_inputs.batched_mixed(15, 20)
+    plan = srpr.Plan([srpr.Problem(p["n_shape"], p["m_shape"], p["layers"]) for p in probs],
+                     np.concatenate([p["theta"].ravel() for p in probs]))
+    rng = np.random.default_rng(16)
+    xs = np.concatenate([p["x_star"].ravel() for p in probs])
+    r = np.concatenate([sr_inputs.complex_gaussian(rng, p["m_shape"]).ravel() for p in probs])
+    xd, rd = to_dev(xs, gpu), to_dev(r, gpu)
+    out = {}
+    for sched in (srpr.SR_SCHED_BATCHED, srpr.SR_SCHED_LOOP):
+        srpr.sr_plan_set_schedule(plan, sched)
+        res = []
+        for _ in range(2):
+            z = torch.empty(plan.m_total, dtype=torch.complex64, device=gpu)
+            y = torch.empty(plan.m_total, dtype=torch.float32, device=gpu)
+            z2 = torch.empty_like(z)
+            y2 = torch.empty_like(y)
+            v = torch.empty(plan.n_total, dtype=torch.complex64, device=gpu)
+            srpr.sr_forward(plan, xd, z, y)
+            srpr.sr_forward(plan, xd, z2, None)
+            srpr.sr_forward(plan, xd, None, y2)
+            srpr.sr_adjoint(plan, rd, v)
+            srpr.sr_plan_sync(plan)
+            res.append([to_host(t) for t in (z, y, z2, y2, v)])
+        for a, b in zip(res[0], res[1]):
+            assert np.array_equal(a, b)  # repeat calls: the same launches
+        out[sched] = res[0]
+    zb, yb, z2b, y2b, vb = out[srpr.SR_SCHED_BATCHED]
+    zl, yl, _, _, vl = out[srpr.SR_SCHED_LOOP]
+    assert np.array_equal(zb, z2b) and np.array_equal(yb, y2b)
+    for i, p in enumerate(probs):
+        ya, yz = plan.y_off[i], plan.y_off[i + 1]
+        xa, xz = plan.x_off[i], plan.x_off[i + 1]
+        assert np.linalg.norm(zb[ya:yz] - zl[ya:yz]) / np.linalg.norm(zl[ya:yz]) <= 2e-5, i
+        assert np.linalg.norm(yb[ya:yz] - yl[ya:yz]) / np.linalg.norm(yl[ya:yz]) <= 4e-5, i
+        assert np.linalg.norm(vb[xa:xz] - vl[xa:xz]) / np.linalg.norm(vl[xa:xz]) <= 2e-5, i
+        if i % 4 == 0:
+            zr = oracle.forward(p["x_star"], p["theta"], p["m_shape"])
+            assert np.linalg.norm(zb[ya:yz].reshape(p["m_shape"]) - zr) / np.linalg.norm(zr) <= 2e-5, i
+            vr = oracle.adjoint(r[ya:yz].reshape(p["m_shape"]), p["theta"], p["n_shape"])
+            assert np.linalg.norm(vb[xa:xz].reshape(p["n_shape"]) - vr) / np.linalg.norm(vr) <= 2e-5, i
