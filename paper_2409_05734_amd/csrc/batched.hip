@@ -248,7 +248,6 @@ struct LevelSet {
 // next first pass), and the final iteration (plain update).
 struct BatchState {
   std::string key;
-  float2* bufs = nullptr;  // per problem: two full grids
   LevelSet first, steady, last;
   // with a loss trace: the turnaround of each problem writes its loss
   // partials (nparts of them, at its own offset), summed per problem
@@ -258,11 +257,32 @@ struct BatchState {
   ~BatchState() {
     if (parts) hipFree(parts);
     if (d_pdesc) hipFree(d_pdesc);
-    if (bufs) hipFree(bufs);
   }
 };
 
 void destroy_batch_state(BatchState* s) { delete s; }
+
+bool batch_level_capable(const Geo& g) {
+  return g.ndim == 2 && batch_tile_width(g.M1) != 0 && batch_tile_width(g.M2) != 0;
+}
+
+// The private ping-pong buffers (two grids) of every problem the level
+// kernel can take, shared by the GD, power-iteration and operator levels,
+// which all run in order on the plan's stream.
+static sr_status level_bufs(sr_plan_s* p) {
+  if (p->lvl_bufs != nullptr) return SR_OK;
+  size_t elems = 0;
+  p->lvl_off.assign(p->geo.size(), 0);
+  for (size_t i = 0; i < p->geo.size(); ++i) {
+    p->lvl_off[i] = elems;
+    if (batch_level_capable(p->geo[i])) elems += 2 * (size_t)p->geo[i].mg;
+  }
+  if (hipMalloc(&p->lvl_bufs, std::max<size_t>(elems, 1) * sizeof(float2)) != hipSuccess) {
+    p->lvl_bufs = nullptr;
+    return fail(SR_E_NOMEM, "batched workspace allocation failed");
+  }
+  return SR_OK;
+}
 
 // Problems whose whole grid fits one workgroup's LDS run in the LDS-resident
 // solver (one launch for the whole solve); the others run as level launches.
@@ -357,16 +377,10 @@ static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const fl
     *out = st;
     return SR_OK;
   }
+  if (sr_status lb = level_bufs(p); lb != SR_OK) return lb;
   if (st == nullptr) {
     st = new BatchState();
     p->batch = st;
-    size_t elems = 0;
-    for (const Geo& g : p->geo) elems += 2 * (size_t)g.mg;
-    hipError_t e = hipMalloc(&st->bufs, elems * sizeof(float2));
-    if (e != hipSuccess) {
-      st->bufs = nullptr;
-      return fail(SR_E_NOMEM, "batched workspace allocation failed");
-    }
   }
   st->key.clear();
   const size_t np = p->geo.size();
@@ -405,14 +419,12 @@ static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const fl
   std::vector<std::vector<PassRecord>> rec_first(np), rec_steady(np), rec_last(np);
   float2* saveA = p->bufA;
   float2* saveB = p->bufB;
-  size_t off = 0;
   sr_status status = SR_OK;
   for (size_t i = 0; i < np && status == SR_OK; ++i) {
     const Geo& g = p->geo[i];
-    p->bufA = st->bufs + off;  // each problem's private ping-pong buffers
-    p->bufB = st->bufs + off + g.mg;
-    off += 2 * (size_t)g.mg;
     if (lds_resident(g)) continue;  // solved by the LDS-resident kernel
+    p->bufA = p->lvl_bufs + p->lvl_off[i];  // each problem's private ping-pong buffers
+    p->bufB = p->lvl_bufs + p->lvl_off[i] + g.mg;
     const float* yi = y + p->yoff[i];
     float2* xi = x + p->xoff[i];
     const float step = eta[i] / (float)g.m;
@@ -537,33 +549,19 @@ sr_status forward_2d_public(sr_plan_s* p, const Geo& g, const float2* x, float2*
 sr_status adjoint_2d_public(sr_plan_s* p, const Geo& g, const float2* r, float2* x);
 
 struct OpBatchState {
-  float2* bufs = nullptr;  // per problem of the plan: two full grids
-  std::vector<size_t> buf_off;
   std::string key[2];
   LevelSet ls[2];  // [0] A, [1] A^H
-  ~OpBatchState() {
-    if (bufs) hipFree(bufs);
-  }
 };
 
 void destroy_op_batch_state(OpBatchState* s) { delete s; }
 
 sr_status batched_operator(sr_plan_s* p, const std::vector<int>& which, bool adjoint, const float2* in, float2* out,
                            float* y_out) {
+  if (sr_status lb = level_bufs(p); lb != SR_OK) return lb;
   OpBatchState* st = p->op_batch;
   if (st == nullptr) {
     st = new OpBatchState();
     p->op_batch = st;
-    size_t elems = 0;
-    st->buf_off.assign(p->geo.size(), 0);
-    for (size_t i = 0; i < p->geo.size(); ++i) {
-      st->buf_off[i] = elems;
-      if (batch_level_capable(p->geo[i])) elems += 2 * (size_t)p->geo[i].mg;
-    }
-    if (hipMalloc(&st->bufs, std::max<size_t>(elems, 1) * sizeof(float2)) != hipSuccess) {
-      st->bufs = nullptr;
-      return fail(SR_E_NOMEM, "batched operator workspace allocation failed");
-    }
   }
   const int d = adjoint ? 1 : 0;
   std::string key = std::to_string((uintptr_t)in) + ":" + std::to_string((uintptr_t)out) + ":" +
@@ -579,8 +577,8 @@ sr_status batched_operator(sr_plan_s* p, const std::vector<int>& which, bool adj
     for (int i : which) {
       if (status != SR_OK) break;
       const Geo& g = p->geo[i];
-      p->bufA = st->bufs + st->buf_off[i];  // each problem's private ping-pong buffers
-      p->bufB = st->bufs + st->buf_off[i] + g.mg;
+      p->bufA = p->lvl_bufs + p->lvl_off[i];  // each problem's private ping-pong buffers
+      p->bufB = p->lvl_bufs + p->lvl_off[i] + g.mg;
       g_recording = &rec[i];
       if (adjoint)
         status = adjoint_2d_public(p, g, in + p->yoff[i], out + p->xoff[i]);
@@ -613,22 +611,16 @@ sr_status spec_steady_public(sr_plan_s* p, const Geo& g, const float* y, float2*
 
 struct SpecBatchState {
   std::string key;
-  float2* bufs = nullptr;              // per problem of the plan: two full grids
   float* parts = nullptr;              // per problem of the plan: two partial sets
-  std::vector<size_t> buf_off, part_off;
+  std::vector<size_t> part_off;
   std::vector<int> nq;                 // partials per set (tiles of the last pass)
   LevelSet first, it0, it0_last, odd, odd_last, even, even_last;
   ~SpecBatchState() {
-    if (bufs) hipFree(bufs);
     if (parts) hipFree(parts);
   }
 };
 
 void destroy_spec_batch_state(SpecBatchState* s) { delete s; }
-
-bool batch_level_capable(const Geo& g) {
-  return g.ndim == 2 && batch_tile_width(g.M1) != 0 && batch_tile_width(g.M2) != 0;
-}
 
 static float spec_inv_mc(const Geo& g) { return (float)((double)g.mg / (double)g.m); }  // c = 1/(grid size)
 
@@ -647,25 +639,24 @@ static sr_status spec_prepare(sr_plan_s* p, const std::vector<int>& which, const
     return SR_OK;
   }
   const size_t np = p->geo.size();
+  if (sr_status lb = level_bufs(p); lb != SR_OK) return lb;
   if (st == nullptr) {
     st = new SpecBatchState();
     p->spec_batch = st;
-    size_t elems = 0, pelems = 0;
-    st->buf_off.assign(np, 0);
+    size_t pelems = 0;
     st->part_off.assign(np, 0);
     st->nq.assign(np, 0);
     for (size_t i = 0; i < np; ++i) {
       const Geo& g = p->geo[i];
-      st->buf_off[i] = elems;
       st->part_off[i] = pelems;
       if (!batch_level_capable(g)) continue;
       st->nq[i] = (g.N2 + batch_tile_width(g.M1) - 1) / batch_tile_width(g.M1);
-      elems += 2 * (size_t)g.mg;
       pelems += 2 * (size_t)std::max(st->nq[i], 1);
     }
-    hipError_t e = hipMalloc(&st->bufs, std::max<size_t>(elems, 1) * sizeof(float2));
-    if (e == hipSuccess) e = hipMalloc(&st->parts, std::max<size_t>(pelems, 1) * sizeof(float));
-    if (e != hipSuccess) return fail(SR_E_NOMEM, "batched power-iteration workspace allocation failed");
+    if (hipMalloc(&st->parts, std::max<size_t>(pelems, 1) * sizeof(float)) != hipSuccess) {
+      st->parts = nullptr;
+      return fail(SR_E_NOMEM, "batched power-iteration workspace allocation failed");
+    }
   }
   st->key.clear();
   std::vector<std::vector<PassRecord>> r_first(np), r_it0(np), r_it0l(np), r_odd(np), r_oddl(np), r_even(np),
@@ -676,8 +667,8 @@ static sr_status spec_prepare(sr_plan_s* p, const std::vector<int>& which, const
   for (int i : which) {
     if (status != SR_OK) break;
     const Geo& g = p->geo[i];
-    p->bufA = st->bufs + st->buf_off[i];  // each problem's private ping-pong buffers
-    p->bufB = st->bufs + st->buf_off[i] + g.mg;
+    p->bufA = p->lvl_bufs + p->lvl_off[i];  // each problem's private ping-pong buffers
+    p->bufB = p->lvl_bufs + p->lvl_off[i] + g.mg;
     const float* yi = y + p->yoff[i];
     float2* xi = x + p->xoff[i];
     const double* ys = p->ysum + i;

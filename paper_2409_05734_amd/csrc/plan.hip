@@ -212,5 +212,6 @@ sr_plan_s::~sr_plan_s() {
   if (batch) sr::destroy_batch_state(batch);
   if (spec_batch) sr::destroy_spec_batch_state(spec_batch);
   if (op_batch) sr::destroy_op_batch_state(op_batch);
+  if (lvl_bufs) hipFree(lvl_bufs);
   if (ws && ws_owned) hipFree(ws);
 }

@@ -120,6 +120,8 @@ struct sr_plan_s {
   sr::BatchState* batch = nullptr;  // batched-schedule state (built on first batched solve)
   sr::SpecBatchState* spec_batch = nullptr;  // the same for batched power iteration
   sr::OpBatchState* op_batch = nullptr;      // and for batched A / A^H
+  float2* lvl_bufs = nullptr;                // their shared per-problem ping-pong buffers
+  std::vector<size_t> lvl_off;
   size_t vjp_elems = 0;
 
   // LDS-resident small-problem solver (fused2d.hip): device descriptors, their
