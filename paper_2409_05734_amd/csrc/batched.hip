@@ -237,8 +237,8 @@ struct LevelSet {
   BatchItem* d_items = nullptr;
   std::vector<int> level_off, level_cnt;  // item ranges per level
   ~LevelSet() {
-    if (d_descs) hipFree(d_descs);
-    if (d_items) hipFree(d_items);
+    if (d_descs) (void)hipFree(d_descs);
+    if (d_items) (void)hipFree(d_items);
   }
 };
 
@@ -255,8 +255,8 @@ struct BatchState {
   float* parts = nullptr;
   int2* d_pdesc = nullptr;  // per problem: (offset, count) of its partials
   ~BatchState() {
-    if (parts) hipFree(parts);
-    if (d_pdesc) hipFree(d_pdesc);
+    if (parts) (void)hipFree(parts);
+    if (d_pdesc) (void)hipFree(d_pdesc);
   }
 };
 
@@ -347,8 +347,12 @@ static sr_status build_levels(sr_plan_s* p, const std::vector<std::vector<PassRe
     }
     ls.level_cnt[q] = (int)items.size() - ls.level_off[q];
   }
-  if (ls.d_descs) hipFree(ls.d_descs);
-  if (ls.d_items) hipFree(ls.d_items);
+  if (ls.d_descs != nullptr || ls.d_items != nullptr) {
+    // launches already queued may still read the old lists
+    if (hipError_t w = hipStreamSynchronize(p->stream); w != hipSuccess) return hip_fail(w, "stream wait");
+    if (ls.d_descs) (void)hipFree(ls.d_descs);
+    if (ls.d_items) (void)hipFree(ls.d_items);
+  }
   ls.d_descs = nullptr;
   ls.d_items = nullptr;
   hipError_t e = hipMalloc(&ls.d_descs, std::max<size_t>(descs.size(), 1) * sizeof(BatchDesc));
@@ -616,7 +620,7 @@ struct SpecBatchState {
   std::vector<int> nq;                 // partials per set (tiles of the last pass)
   LevelSet first, it0, it0_last, odd, odd_last, even, even_last;
   ~SpecBatchState() {
-    if (parts) hipFree(parts);
+    if (parts) (void)hipFree(parts);
   }
 };
 

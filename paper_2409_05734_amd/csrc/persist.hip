@@ -26,8 +26,8 @@ hipError_t go(const PersistArgs& pa, int grid, hipStream_t s) {
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds);
   if (e != hipSuccess) return e;
   int dev = 0, cus = 0;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
   const int cap = per_cu * cus;
   if (cap <= 0) return hipErrorInvalidConfiguration;
   if (grid > cap) grid = cap;

@@ -194,24 +194,24 @@ sr_status sr::aux_join(sr_plan_s* p) {
 }
 
 sr_plan_s::~sr_plan_s() {
-  for (auto& g : graphs) hipGraphExecDestroy(g.second);
+  for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
   if (aux_stream) {
-    hipStreamSynchronize(aux_stream);
-    hipStreamDestroy(aux_stream);
+    (void)hipStreamSynchronize(aux_stream);
+    (void)hipStreamDestroy(aux_stream);
   }
-  if (ev_fork) hipEventDestroy(ev_fork);
-  if (ev_join) hipEventDestroy(ev_join);
-  if (f2_descs) hipFree(f2_descs);
-  if (f1_args) hipFree(f1_args);
-  if (cap_stream) hipStreamDestroy(cap_stream);
-  if (vjp_buf) hipFree(vjp_buf);
-  if (stk_buf) hipFree(stk_buf);
-  if (stk_gth) hipFree(stk_gth);
-  if (stk_steps) hipFree(stk_steps);
-  if (stk_part) hipFree(stk_part);
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
+  if (f2_descs) (void)hipFree(f2_descs);
+  if (f1_args) (void)hipFree(f1_args);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  if (vjp_buf) (void)hipFree(vjp_buf);
+  if (stk_buf) (void)hipFree(stk_buf);
+  if (stk_gth) (void)hipFree(stk_gth);
+  if (stk_steps) (void)hipFree(stk_steps);
+  if (stk_part) (void)hipFree(stk_part);
   if (batch) sr::destroy_batch_state(batch);
   if (spec_batch) sr::destroy_spec_batch_state(spec_batch);
   if (op_batch) sr::destroy_op_batch_state(op_batch);
-  if (lvl_bufs) hipFree(lvl_bufs);
-  if (ws && ws_owned) hipFree(ws);
+  if (lvl_bufs) (void)hipFree(lvl_bufs);
+  if (ws && ws_owned) (void)hipFree(ws);
 }

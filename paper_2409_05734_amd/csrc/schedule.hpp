@@ -124,8 +124,9 @@ inline int stack_size(const sr_plan_s* p, int* th_stride) {
 inline sr_status ensure_stack_bufs(sr_plan_s* p, size_t elems) {
   if (elems <= p->stk_elems) return SR_OK;
   if (p->stk_buf) {
-    hipStreamSynchronize(p->stream);
-    hipFree(p->stk_buf);
+    // queued work may still use the old buffer
+    if (hipError_t w = hipStreamSynchronize(p->stream); w != hipSuccess) return hip_fail(w, "stream wait");
+    (void)hipFree(p->stk_buf);
     p->stk_buf = nullptr;
     p->stk_elems = 0;
   }
@@ -138,8 +139,9 @@ inline sr_status ensure_stack_bufs(sr_plan_s* p, size_t elems) {
 inline sr_status ensure_stack_parts(sr_plan_s* p, size_t elems) {
   if (elems <= p->stk_part_elems) return SR_OK;
   if (p->stk_part) {
-    hipStreamSynchronize(p->stream);
-    hipFree(p->stk_part);
+    // queued work may still use the old buffer
+    if (hipError_t w = hipStreamSynchronize(p->stream); w != hipSuccess) return hip_fail(w, "stream wait");
+    (void)hipFree(p->stk_part);
     p->stk_part = nullptr;
     p->stk_part_elems = 0;
   }
@@ -265,16 +267,16 @@ sr_status launch_captured(sr_plan_s* p, const std::string& key, F&& enqueue) {
   e = hipStreamEndCapture(p->cap_stream, &graph);
   p->stream = user;
   if (st != SR_OK) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     return st;
   }
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
   hipGraphExec_t ex = nullptr;
   e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
   if (p->graphs.size() >= kGraphCacheSize) {
-    hipGraphExecDestroy(p->graphs.front().second);
+    (void)hipGraphExecDestroy(p->graphs.front().second);
     p->graphs.erase(p->graphs.begin());
   }
   p->graphs.push_back({key, ex});

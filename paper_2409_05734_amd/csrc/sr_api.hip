@@ -377,9 +377,9 @@ static sr_status tune_plan(sr_plan_s* p) {
     float* y;
     ~Standins() {
       if (x == nullptr && y == nullptr) return;
-      hipStreamSynchronize(p->stream);
-      if (x) hipFree(x);
-      if (y) hipFree(y);
+      (void)hipStreamSynchronize(p->stream);  // (a failure surfaces at the next call)
+      if (x) (void)hipFree(x);
+      if (y) (void)hipFree(y);
     }
   } standins{p, st_x, st_y};
   std::vector<std::string> done;
@@ -441,8 +441,8 @@ static sr_status tune_plan(sr_plan_s* p) {
             best_whole_found = best_whole_found || whole;
           }
         }
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
       tune_cache_store(cache, key, cb, rb, tb);
     }
     p->tiles[{g.M1, 1}] = cb;
@@ -704,7 +704,7 @@ sr_status sr_plan_set_workspace(sr_plan p, void* dev_ptr, size_t bytes) {
   mv(p->dsplit);
   for (auto& t : p->tw) mv(t.second);
   // recorded schedules and captured graphs hold the old addresses
-  for (auto& g : p->graphs) hipGraphExecDestroy(g.second);
+  for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.second);
   p->graphs.clear();
   if (p->batch) destroy_batch_state(p->batch);
   p->batch = nullptr;
@@ -752,7 +752,7 @@ sr_status sr_plan_sync(sr_plan p) {
   SR_HIP(hipMemcpy(&err, p->sync + 1, sizeof(int), hipMemcpyDeviceToHost));
   if (err != 0) {
     int zero = 0;
-    hipMemcpy(p->sync + 1, &zero, sizeof(int), hipMemcpyHostToDevice);
+    (void)hipMemcpy(p->sync + 1, &zero, sizeof(int), hipMemcpyHostToDevice);
     return fail(SR_E_HIP, "a grid-wide barrier wait exceeded its bound; results of that solve are invalid");
   }
   return SR_OK;
@@ -760,7 +760,7 @@ sr_status sr_plan_sync(sr_plan p) {
 
 sr_status sr_plan_destroy(sr_plan p) {
   if (p == nullptr) return SR_OK;
-  hipStreamSynchronize(p->stream);
+  (void)hipStreamSynchronize(p->stream);  // the plan's work ends before its memory goes
   delete p;
   return SR_OK;
 }

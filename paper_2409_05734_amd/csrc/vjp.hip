@@ -52,8 +52,9 @@ sr_status ensure_vjp_buf(sr_plan_s* p, int P = 1) {
     if (g.ndim == 2) need = std::max(need, (size_t)P * ((size_t)std::max(g.L - 1, 1) * (size_t)g.mg + (size_t)g.n));
   if (need <= p->vjp_elems) return SR_OK;
   if (p->vjp_buf) {
-    hipStreamSynchronize(p->stream);
-    hipFree(p->vjp_buf);
+    // queued work may still use the old buffer
+    if (hipError_t w = hipStreamSynchronize(p->stream); w != hipSuccess) return hip_fail(w, "stream wait");
+    (void)hipFree(p->vjp_buf);
     p->vjp_buf = nullptr;
     p->vjp_elems = 0;
   }
@@ -199,8 +200,9 @@ sr_status stack_vjp_setup(sr_plan_s* p, int P, float* gtheta) {
     const size_t need = (size_t)P * block;
     if (need > p->stk_gth_elems) {
       if (p->stk_gth) {
-        hipStreamSynchronize(p->stream);
-        hipFree(p->stk_gth);
+        // queued work may still use the old scratch
+        if (hipError_t w = hipStreamSynchronize(p->stream); w != hipSuccess) return hip_fail(w, "stream wait");
+        (void)hipFree(p->stk_gth);
         p->stk_gth = nullptr;
         p->stk_gth_elems = 0;
       }
