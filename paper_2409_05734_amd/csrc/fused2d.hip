@@ -419,7 +419,13 @@ static sr_status f2_launch(sr_plan_s* p, const std::vector<F2Desc>& descs, size_
   if (descs.empty()) return SR_OK;
   const size_t bytes = descs.size() * sizeof(F2Desc);
   if (p->f2_desc_cap < descs.size()) {
-    if (p->f2_descs) (void)hipFree(p->f2_descs);
+    if (p->f2_descs) {
+      // launches already queued (on either of the plan's streams) may still read the old ones
+      if (hipError_t w = hipStreamSynchronize(p->stream); w != hipSuccess) return hip_fail(w, "stream wait");
+      if (p->aux_stream != nullptr)
+        if (hipError_t w = hipStreamSynchronize(p->aux_stream); w != hipSuccess) return hip_fail(w, "stream wait");
+      (void)hipFree(p->f2_descs);
+    }
     p->f2_descs = nullptr;
     hipError_t e = hipMalloc(&p->f2_descs, bytes);
     if (e != hipSuccess) return fail(SR_E_NOMEM, "descriptor allocation failed");

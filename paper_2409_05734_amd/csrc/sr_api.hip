@@ -540,7 +540,11 @@ static sr_status flush_1d(sr_plan_s* p, int op, Batch1D& items) {
                    [](const std::pair<int, Fused1DArgs>& a, const std::pair<int, Fused1DArgs>& b) { return a.first < b.first; });
   const size_t bytes = items.size() * sizeof(Fused1DArgs);
   if (p->f1_cap < items.size()) {
-    if (p->f1_args) (void)hipFree(p->f1_args);
+    if (p->f1_args) {
+      // launches already queued may still read the old arguments
+      if (hipError_t w = hipStreamSynchronize(p->stream); w != hipSuccess) return hip_fail(w, "stream wait");
+      (void)hipFree(p->f1_args);
+    }
     p->f1_args = nullptr;
     p->f1_cap = 0;
     hipError_t e = hipMalloc(&p->f1_args, bytes);
