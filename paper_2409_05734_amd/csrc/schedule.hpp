@@ -234,7 +234,7 @@ inline sr_status launch(sr_plan_s* p, const Geo& g, int k, int kind, const PassA
 // cached by the call's pointers and scalars; SR_GRAPH=0 disables them.
 
 constexpr int kGraphChunk = 50;  // iterations per captured graph (even)
-constexpr int kGraphTail = 8;    // GD: a remainder of at least this many steady iterations gets a graph too
+constexpr int kGraphTail = 8;    // a remainder of at least this many steady iterations gets a graph too
 constexpr size_t kGraphCacheSize = 8;
 
 inline bool graphs_enabled(const sr_plan_s* p) {

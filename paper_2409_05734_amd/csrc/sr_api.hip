@@ -1159,6 +1159,19 @@ sr_status sr_spectral_init(sr_plan p, const float* y, const void* v0, int32_t it
             }
             return SR_OK;
           }));
+        // the remainder short of a chunk (it starts on an odd iteration too)
+        const int rest = iters - 1 - it;
+        if (rest >= kGraphTail) {
+          SR_CHECK(launch_captured(p, key + ":" + std::to_string(rest), [&]() -> sr_status {
+            for (int c = 0; c < rest; ++c) {
+              const int q = it + c;
+              SR_CHECK(spec_steady(p, g, yi, xi, lambda, inv_mc, p->ysum, parts[q & 1], nq, parts[(q + 1) & 1],
+                                   false));
+            }
+            return SR_OK;
+          }));
+          it += rest;
+        }
       }
       for (; it < iters; ++it) {
         SR_CHECK(spec_steady(p, g, yi, xi, lambda, inv_mc, p->ysum, parts[it & 1], npart, parts[(it + 1) & 1],
