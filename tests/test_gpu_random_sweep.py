@@ -105,3 +105,63 @@ def test_random_configuration(gpu, monkeypatch, case):
             n = shapes[i][0]
             xr = oracle.gd_solve(ops[i], ys[i], xk[i], 1, float(etas[i]))
             assert rel_l2(x1[plan.x_off[i]:plan.x_off[i + 1]].reshape(n), xr) <= 2e-5, ("gd one step", i)
+
+
+@pytest.mark.parametrize("case", range(20))
+def test_random_derivatives(gpu, case):
+    """Both reverse-mode products on random plans (1D and 2D, padded and
+    trimmed, shared or separate phases, every schedule): signal cotangents
+    per problem and phase cotangents summed over the problems that share a
+    block, within 1e-4 of the oracle."""
+    import torch
+    import paper_2409_05734_amd as srpr
+    rng = np.random.default_rng(777 + case)
+    uniform = rng.random() < 0.6
+    P = int(rng.integers(1, 9))
+
+    def pick():
+        if rng.random() < 0.2:
+            M = int(rng.choice([64, 128, 256, 512]))
+            return (int(rng.integers(1, M + 1)),), (M,), int(rng.integers(1, 4))
+        return _pick(rng)
+    base = pick()
+    shapes = [base] * P if uniform else [pick() for _ in range(P)]
+    shared = uniform and rng.random() < 0.5
+    sched = [srpr.SR_SCHED_AUTO, srpr.SR_SCHED_LOOP, srpr.SR_SCHED_BATCHED][int(rng.integers(0, 3))]
+    grids = [tuple(max(a, b) for a, b in zip(n, m)) for n, m, _ in shapes]
+    ths, offs, off = [], [], 0
+    for i, (n, m, L) in enumerate(shapes):
+        if shared and i > 0:
+            ths.append(ths[0])
+            offs.append(0)
+            continue
+        th = rng.uniform(0, 2 * np.pi, (L,) + grids[i]).astype(np.float32)
+        ths.append(th)
+        offs.append(off)
+        off += th.size
+    theta = np.concatenate([ths[i].ravel() for i in range(P) if not (shared and i > 0)])
+    plan = srpr.Plan([srpr.Problem(n, m, L, theta_offset=offs[i]) for i, (n, m, L) in enumerate(shapes)], theta)
+    srpr.sr_plan_set_schedule(plan, sched)
+    xs = [sr_inputs.complex_gaussian(rng, n) for n, _, _ in shapes]
+    gzs = [sr_inputs.complex_gaussian(rng, m) for _, m, _ in shapes]
+    rs = [sr_inputs.complex_gaussian(rng, m) for _, m, _ in shapes]
+    gvs = [sr_inputs.complex_gaussian(rng, n) for n, _, _ in shapes]
+    cat = lambda arrs: torch.from_numpy(np.concatenate([np.asarray(a).ravel() for a in arrs])).to(gpu)  # noqa: E731
+    gx = torch.empty(plan.n_total, dtype=torch.complex64, device=gpu)
+    gr = torch.empty(plan.m_total, dtype=torch.complex64, device=gpu)
+    g1 = torch.zeros(theta.size, dtype=torch.float32, device=gpu)
+    g2 = torch.zeros(theta.size, dtype=torch.float32, device=gpu)
+    srpr.sr_forward_vjp(plan, cat(xs), cat(gzs), gx, g1)
+    srpr.sr_adjoint_vjp(plan, cat(rs), cat(gvs), gr, g2)
+    srpr.sr_plan_sync(plan)
+    gxh, grh = gx.cpu().numpy(), gr.cpu().numpy()
+    t1, t2 = np.zeros(theta.size), np.zeros(theta.size)
+    for i, (n, m, _) in enumerate(shapes):
+        gxr, a1 = oracle.forward_vjp(xs[i], ths[i], gzs[i])
+        grr, a2 = oracle.adjoint_vjp(rs[i], ths[i], n, gvs[i], m)
+        t1[offs[i]:offs[i] + ths[i].size] += np.asarray(a1).ravel()
+        t2[offs[i]:offs[i] + ths[i].size] += np.asarray(a2).ravel()
+        assert rel_l2(gxh[plan.x_off[i]:plan.x_off[i + 1]].reshape(n), gxr) <= 1e-4, ("gx", i)
+        assert rel_l2(grh[plan.y_off[i]:plan.y_off[i + 1]].reshape(m), grr) <= 1e-4, ("gr", i)
+    assert rel_l2(g1.cpu().numpy(), t1) <= 1e-4
+    assert rel_l2(g2.cpu().numpy(), t2) <= 1e-4
