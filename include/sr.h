@@ -76,8 +76,9 @@ typedef enum {
  * small per-problem arrays) beside the workspace, kept until sr_plan_destroy.
  * Other plans of 8 or more problems take the batched schedule.
  * SR_SCHED_BATCHED: every 2D problem advances one fused pass per launch
- * (one launch per pass level over all problems: A, A^H, GD and power
- * iteration; the derivatives run problem by problem);
+ * (one launch per pass level over all problems: A, A^H, GD, power
+ * iteration and both derivatives, the latter where no two problems share
+ * a phase block);
  * problems whose grid fits one workgroup's LDS solve there instead (power
  * iteration by default; GD with SR_LDS_RESIDENT=1), beside the levels.     */
 typedef enum {

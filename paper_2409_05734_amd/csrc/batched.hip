@@ -167,11 +167,64 @@ __device__ __forceinline__ void run_kind_op(const PassArgs& a, int kind, int til
   }
 }
 
+// The passes of both reverse-mode products (recomputation with saved
+// intermediates, phase cotangents accumulated at each diagonal).
+template <int N, bool COL>
+__device__ __forceinline__ void run_kind_vjp(const PassArgs& a, int kind, int tile, float2* lds, float* red) {
+  constexpr int B = batch_b<N>();
+  if constexpr (COL) {
+    switch (kind) {
+      case PK_FIRST_FWD:
+        pass_tile_rt<N, B, COL, PRE_PHASE, MID_NONE, false, false, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
+                                                                                   nullptr);
+        return;
+      case PK_LAST_ADJ:
+        pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_PHASE_CONJ_STORE>(a, tile, lds, red,
+                                                                                            nullptr, 0, nullptr);
+        return;
+      case PK_LAST_ADJ_GT:
+        pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_PHASE_CONJ_GT>(a, tile, lds, red,
+                                                                                         nullptr, 0, nullptr);
+        return;
+      default:
+        break;
+    }
+  }
+  switch (kind) {
+    case PK_MID_FWD_SAVE:
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE_SAVE, true, false, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
+                                                                                     nullptr);
+      return;
+    case PK_MID_FWD_GT:
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE_GT, true, false, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
+                                                                                   nullptr);
+      return;
+    case PK_MID_ADJ_GT:
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE_CONJ_GT, true, true, true, POST_STORE>(a, tile, lds, red, nullptr,
+                                                                                      0, nullptr);
+      return;
+    case PK_MID_ADJ_SAVE:
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE_CONJ_SAVE, true, true, true, POST_STORE>(a, tile, lds, red, nullptr,
+                                                                                        0, nullptr);
+      return;
+    case PK_FIRST_ADJ:
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
+                                                                               nullptr);
+      return;
+    case PK_LAST_STORE:
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_STORE, false, false, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
+                                                                                 nullptr);
+      return;
+    default:
+      return;
+  }
+}
+
 constexpr size_t kBatchLds = 2 * sizeof(float2) * kBatchThreads * 12;  // covers 2 * B * NP elements for E <= 12
 
 // Pass sets of the level kernel, one instantiation each (so that no set
 // carries the registers of the others).
-enum LevelSetKind : int { LS_GD = 0, LS_SPEC = 1, LS_OP = 2 };
+enum LevelSetKind : int { LS_GD = 0, LS_SPEC = 1, LS_OP = 2, LS_VJP = 3 };
 
 template <int N, int SET>
 __device__ __forceinline__ void run_len(const BatchDesc& d, int tile, float2* lds, float* red) {
@@ -183,6 +236,9 @@ __device__ __forceinline__ void run_len(const BatchDesc& d, int tile, float2* ld
   } else if constexpr (SET == LS_OP) {
     if (d.col) run_kind_op<N, true>(d.a, d.kind, tile, lds, red);
     else run_kind_op<N, false>(d.a, d.kind, tile, lds, red);
+  } else if constexpr (SET == LS_VJP) {
+    if (d.col) run_kind_vjp<N, true>(d.a, d.kind, tile, lds, red);
+    else run_kind_vjp<N, false>(d.a, d.kind, tile, lds, red);
   } else {
     if (d.col) run_kind_gd<N, true>(d.a, d.kind, tile, lds, red);
     else run_kind_gd<N, false>(d.a, d.kind, tile, lds, red);
@@ -461,6 +517,8 @@ static sr_status run_levels(sr_plan_s* p, const LevelSet& ls) {
       hipLaunchKernelGGL(batched_level_kernel<LS_SPEC>, grid, block, kBatchLds, p->stream, items, ls.d_descs);
     else if (ls.set == LS_OP)
       hipLaunchKernelGGL(batched_level_kernel<LS_OP>, grid, block, kBatchLds, p->stream, items, ls.d_descs);
+    else if (ls.set == LS_VJP)
+      hipLaunchKernelGGL(batched_level_kernel<LS_VJP>, grid, block, kBatchLds, p->stream, items, ls.d_descs);
     else
       hipLaunchKernelGGL(batched_level_kernel<LS_GD>, grid, block, kBatchLds, p->stream, items, ls.d_descs);
     hipError_t e = hipGetLastError();
@@ -543,6 +601,21 @@ static sr_status batched_levels_gd_trace(sr_plan_s* p, const float* y, float2* x
   }
   return SR_OK;
 }
+
+// ------------------------------------------------------- derivative levels
+// Level lists of recorded derivative passes, for the reverse-mode driver.
+
+struct LevelLists {
+  LevelSet ls;
+};
+LevelLists* level_lists_new() { return new LevelLists(); }
+void level_lists_delete(LevelLists* l) { delete l; }
+sr_status level_lists_build(sr_plan_s* p, const std::vector<std::vector<PassRecord>>& recs, LevelLists* l) {
+  l->ls.set = LS_VJP;
+  return build_levels(p, recs, l->ls);
+}
+sr_status level_lists_run(sr_plan_s* p, const LevelLists* l) { return run_levels(p, l->ls); }
+sr_status level_bufs_alloc(sr_plan_s* p) { return level_bufs(p); }
 
 // ------------------------------------------------------------ A and A^H
 // One application of A (or A^H) to every listed problem, one launch per pass

@@ -212,6 +212,7 @@ sr_plan_s::~sr_plan_s() {
   if (batch) sr::destroy_batch_state(batch);
   if (spec_batch) sr::destroy_spec_batch_state(spec_batch);
   if (op_batch) sr::destroy_op_batch_state(op_batch);
+  if (vjp_batch) sr::destroy_vjp_batch_state(vjp_batch);
   if (lvl_bufs) (void)hipFree(lvl_bufs);
   if (ws && ws_owned) (void)hipFree(ws);
 }

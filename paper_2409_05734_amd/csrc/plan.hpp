@@ -42,6 +42,8 @@ struct SpecBatchState;
 void destroy_spec_batch_state(SpecBatchState* s);
 struct OpBatchState;
 void destroy_op_batch_state(OpBatchState* s);
+struct VjpBatchState;
+void destroy_vjp_batch_state(VjpBatchState* s);
 
 // A stack of problems of one geometry run as one: every fused pass of the
 // first problem's schedule is launched once for all P problems, each buffer
@@ -120,6 +122,7 @@ struct sr_plan_s {
   sr::BatchState* batch = nullptr;  // batched-schedule state (built on first batched solve)
   sr::SpecBatchState* spec_batch = nullptr;  // the same for batched power iteration
   sr::OpBatchState* op_batch = nullptr;      // and for batched A / A^H
+  sr::VjpBatchState* vjp_batch = nullptr;    // and for the batched derivatives
   float2* lvl_bufs = nullptr;                // their shared per-problem ping-pong buffers
   std::vector<size_t> lvl_off;
   size_t vjp_elems = 0;

@@ -716,6 +716,8 @@ sr_status sr_plan_set_workspace(sr_plan p, void* dev_ptr, size_t bytes) {
   p->spec_batch = nullptr;
   if (p->op_batch) destroy_op_batch_state(p->op_batch);
   p->op_batch = nullptr;
+  if (p->vjp_batch) destroy_vjp_batch_state(p->vjp_batch);
+  p->vjp_batch = nullptr;
   if (p->ws_owned) SR_HIP(hipFree(p->ws));
   p->ws = dev_ptr;
   p->ws_owned = false;

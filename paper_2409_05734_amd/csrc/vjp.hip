@@ -14,6 +14,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <string>
+#include <vector>
 
 #include "fft_core.hpp"
 #include "fused1d.hpp"
@@ -284,14 +286,193 @@ sr_status vjp_adjoint_stacked(sr_plan_s* p, int P, int ths, const float2* r, con
 
 }  // namespace
 
+// ------------------------------------------------ on the batched levels
+// Both products for the 2D problems of a batched plan, one launch per pass
+// level over all of them: each problem's passes are recorded with its own
+// ping-pong buffers and its own saved intermediates, and (the problems'
+// phase blocks being disjoint, so no two tiles of a level add into the same
+// cotangent) its own slice of the phase cotangents.  The adjoint product's
+// first-layer term between its two halves is one small launch per problem.
+
+struct LevelLists;
+LevelLists* level_lists_new();
+void level_lists_delete(LevelLists* l);
+sr_status level_lists_build(sr_plan_s* p, const std::vector<std::vector<PassRecord>>& recs, LevelLists* l);
+sr_status level_lists_run(sr_plan_s* p, const LevelLists* l);
+sr_status level_bufs_alloc(sr_plan_s* p);
+
+struct VjpBatchState {
+  std::string key[2];
+  LevelLists* lists[3] = {nullptr, nullptr, nullptr};  // A's product; A^H's two halves
+  float2* save = nullptr;                               // per problem: its saved grids and an n-sized scratch
+  std::vector<size_t> save_off;
+  ~VjpBatchState() {
+    for (LevelLists* l : lists)
+      if (l) level_lists_delete(l);
+    if (save) (void)hipFree(save);
+  }
+};
+
+void destroy_vjp_batch_state(VjpBatchState* s) { delete s; }
+
+namespace {
+
+// the 2D problems the levels take, if there are at least two and their phase
+// blocks are pairwise disjoint
+std::vector<int> vjp_level_problems(const sr_plan_s* p) {
+  std::vector<int> lvl;
+  const bool want = p->schedule == SR_SCHED_BATCHED || (p->schedule == SR_SCHED_AUTO && p->geo.size() >= 8);
+  if (!want) return lvl;
+  for (size_t i = 0; i < p->geo.size(); ++i)
+    if (batch_level_capable(p->geo[i])) lvl.push_back((int)i);
+  if (lvl.size() < 2) return {};
+  std::vector<std::pair<int64_t, int64_t>> iv;
+  for (int i : lvl) iv.push_back({p->geo[i].th_off, p->geo[i].th_off + (int64_t)p->geo[i].L * p->geo[i].mg});
+  std::sort(iv.begin(), iv.end());
+  for (size_t k = 1; k < iv.size(); ++k)
+    if (iv[k].first < iv[k - 1].second) return {};
+  return lvl;
+}
+
+sr_status vjp_batch_prepare(sr_plan_s* p, VjpBatchState** out) {
+  VJ_CHECK(level_bufs_alloc(p));
+  VjpBatchState* st = p->vjp_batch;
+  if (st == nullptr) {
+    st = new VjpBatchState();
+    p->vjp_batch = st;
+    size_t elems = 0;
+    st->save_off.assign(p->geo.size(), 0);
+    for (size_t i = 0; i < p->geo.size(); ++i) {
+      const Geo& g = p->geo[i];
+      st->save_off[i] = elems;
+      if (batch_level_capable(g)) elems += (size_t)std::max(g.L - 1, 1) * g.mg + (size_t)g.n;
+    }
+    if (hipMalloc(&st->save, std::max<size_t>(elems, 1) * sizeof(float2)) != hipSuccess) {
+      st->save = nullptr;
+      return fail(SR_E_NOMEM, "batched derivative workspace allocation failed");
+    }
+    for (LevelLists*& l : st->lists) l = level_lists_new();
+  }
+  *out = st;
+  return SR_OK;
+}
+
+// Points the plan's pass buffers and derivative scratch at problem i's own.
+struct ProblemBuffers {
+  sr_plan_s* p;
+  float2 *a0, *b0, *v0;
+  ProblemBuffers(sr_plan_s* pl, const VjpBatchState* st, int i)
+      : p(pl), a0(pl->bufA), b0(pl->bufB), v0(pl->vjp_buf) {
+    const Geo& g = p->geo[i];
+    p->bufA = p->lvl_bufs + p->lvl_off[i];
+    p->bufB = p->lvl_bufs + p->lvl_off[i] + g.mg;
+    p->vjp_buf = st->save + st->save_off[i];
+  }
+  ~ProblemBuffers() {
+    p->bufA = a0;
+    p->bufB = b0;
+    p->vjp_buf = v0;
+  }
+};
+
+std::string vjp_key(const std::vector<int>& lvl, std::initializer_list<const void*> ptrs) {
+  std::string k;
+  for (const void* q : ptrs) k += ptr_key(q) + ":";
+  for (int i : lvl) k += std::to_string(i) + ",";
+  return k;
+}
+
+sr_status vjp_forward_levels(sr_plan_s* p, const std::vector<int>& lvl, const float2* x, const float2* gz,
+                             float2* gx, float* gtheta) {
+  VjpBatchState* st = nullptr;
+  VJ_CHECK(vjp_batch_prepare(p, &st));
+  const std::string key = vjp_key(lvl, {x, gz, gx, gtheta});
+  if (st->key[0] != key) {
+    st->key[0].clear();
+    std::vector<std::vector<PassRecord>> recs(p->geo.size());
+    sr_status status = SR_OK;
+    for (int i : lvl) {
+      const Geo& g = p->geo[i];
+      ProblemBuffers pb(p, st, i);
+      const float2* xi = x + p->xoff[i];
+      float2* gxi = gx ? gx + p->xoff[i] : nscratch(p, g);
+      g_recording = &recs[i];
+      float2* cur = nullptr;
+      if (g.L >= 2) status = fwd_passes(p, g, xi, PK_MID_FWD_SAVE, gtheta, &cur);
+      if (status == SR_OK) status = adj_passes(p, g, gz + p->yoff[i], PK_MID_ADJ_GT, PK_LAST_ADJ_GT, gtheta, xi, gxi);
+      g_recording = nullptr;
+      if (status != SR_OK) return status;
+    }
+    VJ_CHECK(level_lists_build(p, recs, st->lists[0]));
+    st->key[0] = key;
+  }
+  return level_lists_run(p, st->lists[0]);
+}
+
+sr_status vjp_adjoint_levels(sr_plan_s* p, const std::vector<int>& lvl, const float2* r, const float2* gv,
+                             float2* gr, float* gtheta) {
+  VjpBatchState* st = nullptr;
+  VJ_CHECK(vjp_batch_prepare(p, &st));
+  const std::string key = vjp_key(lvl, {r, gv, gr, gtheta});
+  if (st->key[1] != key) {
+    st->key[1].clear();
+    std::vector<std::vector<PassRecord>> ra(p->geo.size()), rb(p->geo.size());
+    sr_status status = SR_OK;
+    for (int i : lvl) {
+      const Geo& g = p->geo[i];
+      ProblemBuffers pb(p, st, i);
+      g_recording = &ra[i];
+      status = adj_passes(p, g, r + p->yoff[i], PK_MID_ADJ_SAVE, PK_LAST_ADJ, gtheta, nullptr, nscratch(p, g));
+      g_recording = &rb[i];
+      float2* cur = nullptr;
+      if (status == SR_OK) status = fwd_passes(p, g, gv + p->xoff[i], PK_MID_FWD_GT, gtheta, &cur);
+      if (status == SR_OK && gr != nullptr) {
+        const int k = g.L + 1;
+        PassArgs a = base_args(p, g, k);
+        set_in(a, g, k, cur);
+        a.scale_mid = 1.f / std::sqrt((float)pass_len(g, k));
+        a.z_out = gr + p->yoff[i];
+        status = launch(p, g, k, PK_LAST_STORE, a);
+      }
+      g_recording = nullptr;
+      if (status != SR_OK) return status;
+    }
+    VJ_CHECK(level_lists_build(p, ra, st->lists[1]));
+    VJ_CHECK(level_lists_build(p, rb, st->lists[2]));
+    st->key[1] = key;
+  }
+  VJ_CHECK(level_lists_run(p, st->lists[1]));
+  // first layer: gth_1 += Im(conj(gv) v) on each problem's support
+  for (int i : lvl) {
+    const Geo& g = p->geo[i];
+    const float2* v = st->save + st->save_off[i] + (size_t)std::max(g.L - 1, 1) * g.mg;  // the problem's scratch
+    const long long n = g.n;
+    const int groups = (int)std::min<long long>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(gth_support_kernel, dim3(groups), dim3(256), 0, p->stream, gv + p->xoff[i], v,
+                       gtheta + g.th_off, g.N1, g.N2, g.o1, g.o2, (long long)g.M2, 1, 0LL);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "gth_support");
+  }
+  return level_lists_run(p, st->lists[2]);
+}
+
+}  // namespace
+
 sr_status vjp_forward(sr_plan_s* p, const float2* x, const float2* gz, float2* gx, float* gtheta) {
   {
     int ths = 0;
     const int P = stack_size(p, &ths);
     if (P > 1) return vjp_forward_stacked(p, P, ths, x, gz, gx, gtheta);
   }
+  const std::vector<int> lvl = vjp_level_problems(p);
+  std::vector<char> done(p->geo.size(), 0);
+  if (!lvl.empty()) {
+    VJ_CHECK(vjp_forward_levels(p, lvl, x, gz, gx, gtheta));
+    for (int i : lvl) done[i] = 1;
+  }
   VJ_CHECK(ensure_vjp_buf(p));
   for (size_t i = 0; i < p->geo.size(); ++i) {
+    if (done[i]) continue;
     const Geo& g = p->geo[i];
     const float2* xi = x + p->xoff[i];
     const float2* gzi = gz + p->yoff[i];
@@ -318,8 +499,15 @@ sr_status vjp_adjoint(sr_plan_s* p, const float2* r, const float2* gv, float2* g
     const int P = stack_size(p, &ths);
     if (P > 1) return vjp_adjoint_stacked(p, P, ths, r, gv, gr, gtheta);
   }
+  const std::vector<int> lvl = vjp_level_problems(p);
+  std::vector<char> done(p->geo.size(), 0);
+  if (!lvl.empty()) {
+    VJ_CHECK(vjp_adjoint_levels(p, lvl, r, gv, gr, gtheta));
+    for (int i : lvl) done[i] = 1;
+  }
   VJ_CHECK(ensure_vjp_buf(p));
   for (size_t i = 0; i < p->geo.size(); ++i) {
+    if (done[i]) continue;
     const Geo& g = p->geo[i];
     const float2* ri = r + p->yoff[i];
     const float2* gvi = gv + p->xoff[i];

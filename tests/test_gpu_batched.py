@@ -244,3 +244,69 @@ def test_batched_operator_levels(gpu):
             assert np.linalg.norm(zb[ya:yz].reshape(p["m_shape"]) - zr) / np.linalg.norm(zr) <= 2e-5, i
             vr = oracle.adjoint(r[ya:yz].reshape(p["m_shape"]), p["theta"], p["n_shape"])
             assert np.linalg.norm(vb[xa:xz].reshape(p["n_shape"]) - vr) / np.linalg.norm(vr) <= 2e-5, i
+
+
+@pytest.mark.parametrize("share", [False, True])
+def test_batched_derivatives_levels(gpu, share):
+    """Both reverse-mode products on a batched plan of uneven problems by
+    level launches (separate phase blocks); with two problems sharing a
+    block, the plan falls back to problem-by-problem launches (the levels
+    would add into one cotangent from two tiles at once).  Signal
+    cotangents per problem and the phase cotangents against the oracle
+    (1e-4) and the loop."""
+    import torch
+    import paper_2409_05734_amd as srpr
+    probs = sr_inputs.batched_mixed(17, 12)
+    offs, blocks, off = [], [], 0
+    for i, p in enumerate(probs):
+        if share and i == 1 and probs[0]["m_shape"] == probs[1]["m_shape"] and probs[0]["layers"] == probs[1]["layers"]:
+            offs.append(offs[0])
+            blocks.append(None)
+            continue
+        offs.append(off)
+        blocks.append(p["theta"])
+        off += p["theta"].size
+    if share and blocks[1] is not None:  # make problem 1 share problem 0's block outright
+        probs[1] = dict(probs[1], n_shape=probs[0]["n_shape"], m_shape=probs[0]["m_shape"],
+                        layers=probs[0]["layers"], theta=probs[0]["theta"],
+                        x_star=probs[0]["x_star"])
+        off -= blocks[1].size
+        offs = [0, 0] + [o - blocks[1].size for o in offs[2:]]
+        blocks[1] = None
+    theta = np.concatenate([b.ravel() for b in blocks if b is not None])
+    plan = srpr.Plan([srpr.Problem(p["n_shape"], p["m_shape"], p["layers"], theta_offset=offs[i])
+                      for i, p in enumerate(probs)], theta)
+    rng = np.random.default_rng(18)
+    xs = [p["x_star"] for p in probs]
+    gzs = [sr_inputs.complex_gaussian(rng, p["m_shape"]) for p in probs]
+    rs = [sr_inputs.complex_gaussian(rng, p["m_shape"]) for p in probs]
+    gvs = [sr_inputs.complex_gaussian(rng, p["n_shape"]) for p in probs]
+    cat = lambda arrs: to_dev(np.concatenate([np.asarray(a).ravel() for a in arrs]), gpu)  # noqa: E731
+    out = {}
+    for sched in (srpr.SR_SCHED_BATCHED, srpr.SR_SCHED_LOOP):
+        srpr.sr_plan_set_schedule(plan, sched)
+        gx = torch.empty(plan.n_total, dtype=torch.complex64, device=gpu)
+        gr = torch.empty(plan.m_total, dtype=torch.complex64, device=gpu)
+        g1 = torch.zeros(theta.size, dtype=torch.float32, device=gpu)
+        g2 = torch.zeros(theta.size, dtype=torch.float32, device=gpu)
+        for _ in range(2):  # twice: cached levels, cotangents accumulate
+            srpr.sr_forward_vjp(plan, cat(xs), cat(gzs), gx, g1)
+            srpr.sr_adjoint_vjp(plan, cat(rs), cat(gvs), gr, g2)
+        srpr.sr_plan_sync(plan)
+        out[sched] = [to_host(t) for t in (gx, gr, g1, g2)]
+    gxb, grb, g1b, g2b = out[srpr.SR_SCHED_BATCHED]
+    gxl, grl, g1l, g2l = out[srpr.SR_SCHED_LOOP]
+    t1, t2 = np.zeros(theta.size), np.zeros(theta.size)
+    for i, p in enumerate(probs):
+        th = probs[i]["theta"]
+        gxr, a1 = oracle.forward_vjp(xs[i], th, gzs[i])
+        grr, a2 = oracle.adjoint_vjp(rs[i], th, p["n_shape"], gvs[i], p["m_shape"])
+        t1[offs[i]:offs[i] + th.size] += 2 * np.asarray(a1).ravel()
+        t2[offs[i]:offs[i] + th.size] += 2 * np.asarray(a2).ravel()
+        xa, xz, ya, yz = plan.x_off[i], plan.x_off[i + 1], plan.y_off[i], plan.y_off[i + 1]
+        assert np.linalg.norm(gxb[xa:xz].reshape(p["n_shape"]) - gxr) / np.linalg.norm(gxr) <= 1e-4, i
+        assert np.linalg.norm(grb[ya:yz].reshape(p["m_shape"]) - grr) / np.linalg.norm(grr) <= 1e-4, i
+        assert np.linalg.norm(gxb[xa:xz] - gxl[xa:xz]) / np.linalg.norm(gxl[xa:xz]) <= 1e-5, i
+    for gb, gl, t in ((g1b, g1l, t1), (g2b, g2l, t2)):
+        assert np.linalg.norm(gb - t) / np.linalg.norm(t) <= 1e-4
+        assert np.linalg.norm(gb - gl) / np.linalg.norm(gl) <= 1e-5
