@@ -58,6 +58,9 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
                           [f"-DSR_FFT_N={n}", f"-DSR_PASS_SET={pset}"]))
     for s in SOURCES:
         tasks.append((os.path.join(CSRC, s), os.path.join(BUILD, s.replace(".hip", ".o")), []))
+    for k in range(4):  # the level kernel, one pass set per translation unit
+        tasks.append((os.path.join(CSRC, "batched.hip"), os.path.join(BUILD, f"batched_set{k}.o"),
+                      [f"-DSR_LEVEL_SET={k}"]))
     jobs = jobs or min(16, os.cpu_count() or 4)
     failures = []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

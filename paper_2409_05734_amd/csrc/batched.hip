@@ -286,6 +286,26 @@ int batch_tile_width(int N) {
 
 }  // namespace
 
+// Each pass set's kernel is compiled in a translation unit of its own (this
+// file built with SR_LEVEL_SET = 0..3; they compile in parallel), behind a
+// plain host launcher (untyped pointers: the descriptor types are local to
+// each translation unit); the build without it holds the host side.
+hipError_t launch_level_set0(dim3 grid, hipStream_t s, const void* items, const void* descs);
+hipError_t launch_level_set1(dim3 grid, hipStream_t s, const void* items, const void* descs);
+hipError_t launch_level_set2(dim3 grid, hipStream_t s, const void* items, const void* descs);
+hipError_t launch_level_set3(dim3 grid, hipStream_t s, const void* items, const void* descs);
+
+#if defined(SR_LEVEL_SET)
+#define SR_LAUNCHER_NAME(k) launch_level_set##k
+#define SR_LAUNCHER(k) SR_LAUNCHER_NAME(k)
+hipError_t SR_LAUNCHER(SR_LEVEL_SET)(dim3 grid, hipStream_t s, const void* items, const void* descs) {
+  hipLaunchKernelGGL(batched_level_kernel<SR_LEVEL_SET>, grid, dim3(kBatchThreads), kBatchLds, s,
+                     (const BatchItem*)items, (const BatchDesc*)descs);
+  return hipGetLastError();
+}
+}  // namespace sr
+#else
+
 // Level lists of one recorded pass sequence (device descriptors and items).
 struct LevelSet {
   int set = LS_GD;  // pass set (which instantiation of the level kernel)
@@ -511,17 +531,13 @@ static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const fl
 static sr_status run_levels(sr_plan_s* p, const LevelSet& ls) {
   for (size_t q = 0; q < ls.level_cnt.size(); ++q) {
     if (ls.level_cnt[q] == 0) continue;
-    const dim3 grid(ls.level_cnt[q]), block(kBatchThreads);
+    const dim3 grid(ls.level_cnt[q]);
     const BatchItem* items = ls.d_items + ls.level_off[q];
-    if (ls.set == LS_SPEC)
-      hipLaunchKernelGGL(batched_level_kernel<LS_SPEC>, grid, block, kBatchLds, p->stream, items, ls.d_descs);
-    else if (ls.set == LS_OP)
-      hipLaunchKernelGGL(batched_level_kernel<LS_OP>, grid, block, kBatchLds, p->stream, items, ls.d_descs);
-    else if (ls.set == LS_VJP)
-      hipLaunchKernelGGL(batched_level_kernel<LS_VJP>, grid, block, kBatchLds, p->stream, items, ls.d_descs);
-    else
-      hipLaunchKernelGGL(batched_level_kernel<LS_GD>, grid, block, kBatchLds, p->stream, items, ls.d_descs);
-    hipError_t e = hipGetLastError();
+    hipError_t e;
+    if (ls.set == LS_SPEC) e = launch_level_set1(grid, p->stream, items, ls.d_descs);
+    else if (ls.set == LS_OP) e = launch_level_set2(grid, p->stream, items, ls.d_descs);
+    else if (ls.set == LS_VJP) e = launch_level_set3(grid, p->stream, items, ls.d_descs);
+    else e = launch_level_set0(grid, p->stream, items, ls.d_descs);
     if (e != hipSuccess) return hip_fail(e, "batched level launch");
   }
   return SR_OK;
@@ -834,3 +850,4 @@ sr_status batched_spectral(sr_plan_s* p, const std::vector<int>& which, const fl
 }
 
 }  // namespace sr
+#endif  // SR_LEVEL_SET
