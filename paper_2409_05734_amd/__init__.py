@@ -8,6 +8,14 @@ HIP stream into them; all computation happens in the library's HIP kernels.
     sr_forward(plan, x, y=y)          # y = |A x|^2          (Eq. (1), Eq. (5))
     sr_spectral_init(plan, y, v0, 100, -1.0, x0)              (Eq. (3)-(4))
     sr_gd_solve(plan, y, x0, 500, [eta])                       (Eq. (2))
+
+Several problems go into one plan (arrays concatenated, offsets from
+sr_plan_offsets).  Problems of one shape whose phase blocks are shared or
+evenly spaced run as a stack (one launch per pass for all of them, results
+bitwise equal to one-by-one runs); plans of many uneven problems run one
+launch per pass level (sr_plan_set_schedule picks explicitly).
+StructuredA / StructuredAH (autograd.py) make A and A^H differentiable with
+respect to the signal and the phases.
 """
 from __future__ import annotations
 
