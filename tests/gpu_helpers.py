@@ -1,7 +1,21 @@
-"""Helpers shared by the GPU tests: build plans, move arrays, compare."""
+"""Helpers shared by the GPU tests: build plans, move arrays, compare.
+
+Comparisons return one number that a test holds against its tolerance tol:
+the relative L2 error ||a - b|| / ||b|| together with an element bound,
+
+    err = max(||a - b|| / ||b||,  max_i |a_i - b_i| / (ELEM * rms(b))),
+
+so that `err <= tol` means both ||a - b|| <= tol ||b|| and every element
+within ELEM * tol of the reference's root-mean-square magnitude.  Rounding
+errors of the FFT-based kernels spread evenly over the elements (their
+maximum is a few times their RMS), while a few wrong elements in a large
+grid hardly move the L2 norm but break the element bound.
+"""
 import numpy as np
 
 import oracle
+
+ELEM = 10.0
 
 
 def to_dev(a, dev):
@@ -14,14 +28,34 @@ def to_host(t):
     return t.detach().cpu().numpy()
 
 
+def _err(a, b):
+    a = np.asarray(a, dtype=np.complex128).ravel()
+    b = np.asarray(b, dtype=np.complex128).ravel()
+    nb = np.linalg.norm(b)
+    e = a - b
+    rel = float(np.linalg.norm(e) / nb)
+    if e.size == 0:
+        return rel
+    rms = nb / np.sqrt(b.size)
+    return max(rel, float(np.max(np.abs(e)) / (ELEM * rms)))
+
+
 def rel_l2(a, b):
+    """Relative L2 error combined with the element bound (module docstring)."""
+    return _err(a, b)
+
+
+def rel_l2_only(a, b):
+    """Plain relative L2 error ||a - b|| / ||b||."""
     a = np.asarray(a, dtype=np.complex128)
     b = np.asarray(b, dtype=np.complex128)
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
 def aligned(a, ref):
-    return oracle.aligned_rel_error(a, ref)
+    """As rel_l2 after multiplying a by the global phase that best matches ref
+    (the measurements fix the signal only up to a global phase)."""
+    return _err(oracle.phase_align(np.asarray(a).reshape(np.shape(ref)), ref), ref)
 
 
 def make_plan(problems, thetas, dev):
