@@ -51,13 +51,13 @@ typedef enum {
   SR_E_SHAPE = -2,        /* inconsistent shapes (M < N, theta out of range, ...) */
   SR_E_UNSUPPORTED = -3,  /* valid but not implemented (e.g. an FFT length with a prime factor > 3) */
   SR_E_HIP = -4,          /* a HIP runtime call failed */
-  SR_E_NONFINITE = -5,    /* a non-finite value was met */
+  SR_E_NONFINITE = -5,    /* a solve produced NaN or Inf (reported by sr_plan_sync), or a step is not finite */
   SR_E_STATE = -6,        /* call not valid for this plan (e.g. structured call on a dense plan) */
   SR_E_NOMEM = -7         /* device allocation failed, or a caller workspace is too small */
 } sr_status;
 
 typedef enum {
-  SR_STRUCTURED = 0,  /* A = F D_L ... F D_1 U (section III, Eq. (5), alpha > 1) */
+  SR_STRUCTURED = 0,  /* A = S F D_L ... F D_1 U (section III, Eq. (5); any alpha: U pads, S trims) */
   SR_DENSE = 1        /* i.i.d. complex Gaussian A given as an explicit m x n matrix (section II-A) */
 } sr_kind;
 
@@ -168,7 +168,14 @@ sr_status sr_plan_set_schedule(sr_plan plan, int32_t schedule);
  * SR_LOSS_POISSON with eps not finite and positive.                          */
 sr_status sr_plan_set_loss(sr_plan plan, int32_t loss, float eps);
 
-/* Wait for all work of the plan's stream; reports device-side failures.      */
+/* Wait for all work of the plan's stream; reports device-side failures:
+ *  SR_E_HIP        a HIP call failed, or a grid-wide barrier wait of the
+ *                  persistent solver exceeded its bound;
+ *  SR_E_NONFINITE  a GD or spectral solve since the previous sync returned a
+ *                  NaN or Inf entry (final iterate, spectral estimate, or an
+ *                  entry of a loss trace): the solve diverged (step too large)
+ *                  or its inputs held NaN / Inf.  The results are still
+ *                  written; the flag is cleared once reported.                */
 sr_status sr_plan_sync(sr_plan plan);
 
 /* Free the plan and its workspace (after waiting for its stream).             */

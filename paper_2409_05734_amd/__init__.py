@@ -25,8 +25,8 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _lib
-from ._lib import (SR_DENSE, SR_LOSS_L2, SR_LOSS_POISSON, SR_SCHED_AUTO, SR_SCHED_BATCHED, SR_SCHED_LOOP,
-                   SR_STRUCTURED, SrError)
+from ._lib import (SR_DENSE, SR_E_NONFINITE, SR_LOSS_L2, SR_LOSS_POISSON, SR_SCHED_AUTO, SR_SCHED_BATCHED,
+                   SR_SCHED_LOOP, SR_STRUCTURED, SrError)
 
 __all__ = [
     "Problem", "Plan", "SrError",
@@ -34,6 +34,7 @@ __all__ = [
     "sr_plan_sync",
     "sr_forward", "sr_adjoint", "sr_spectral_init", "sr_gd_solve", "sr_forward_vjp", "sr_adjoint_vjp",
     "SR_STRUCTURED", "SR_DENSE", "SR_SCHED_AUTO", "SR_SCHED_LOOP", "SR_SCHED_BATCHED", "SR_LOSS_L2", "SR_LOSS_POISSON",
+    "SR_E_NONFINITE",
 ]
 
 

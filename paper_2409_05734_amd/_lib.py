@@ -20,6 +20,7 @@ SR_SCHED_LOOP = 1
 SR_SCHED_BATCHED = 2
 SR_LOSS_L2 = 0
 SR_LOSS_POISSON = 1
+SR_E_NONFINITE = -5
 
 STATUS_NAMES = {
     0: "SR_OK", -1: "SR_E_ARG", -2: "SR_E_SHAPE", -3: "SR_E_UNSUPPORTED", -4: "SR_E_HIP",

@@ -78,6 +78,7 @@ struct DenseArgs {
   int q_ld;                // 2 * (signals rounded up to 32): row length of the partials of A X
   int loss;                // E1_GD: LOSS_L2 or LOSS_POISSON
   float loss_eps;          // E1_GD: Poisson guard
+  unsigned* nf;            // E2_GD / E2_SPEC: set to 1 when an updated entry is NaN or Inf
 };
 
 __device__ __forceinline__ f4 ld4(const float* p) { return *reinterpret_cast<const f4*>(p); }
@@ -342,6 +343,7 @@ __global__ void __launch_bounds__(NT) dense_epi2_kernel(const DenseArgs a) {
   const int kb = blockIdx.x * 32 + (tid & 7) * 4;
   const int J = 2 * a.n;
   float part = 0.f;
+  bool bad = false;
   if (p < a.nb) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -366,7 +368,9 @@ __global__ void __launch_bounds__(NT) dense_epi2_kernel(const DenseArgs a) {
         a.x[o] = cscale(gv, a.step);
       } else if constexpr (EPI == E2_GD) {
         const float2 xo = a.x[o];
-        a.x[o] = make_float2(xo.x - a.step * gv.x, xo.y - a.step * gv.y);
+        const float2 nx = make_float2(xo.x - a.step * gv.x, xo.y - a.step * gv.y);
+        a.x[o] = nx;
+        bad |= !finite2(nx);
       } else {
         // u_new = step * M v - 2 lambda v, v = u / ||u|| (the 1/||u|| was applied to R's source in A X)
         const float2 uo = a.x[o];
@@ -374,9 +378,11 @@ __global__ void __launch_bounds__(NT) dense_epi2_kernel(const DenseArgs a) {
         const float2 nu = make_float2(a.step * gv.x - c * uo.x, a.step * gv.y - c * uo.y);
         a.x[o] = nu;
         part += cabs2(nu);
+        bad |= !finite2(nu);
       }
     }
   }
+  if constexpr (EPI == E2_GD || EPI == E2_SPEC) flag_nonfinite(a.nf, bad);
   if constexpr (EPI == E2_SPEC) {
     red[tid] = part;
     __syncthreads();
@@ -441,14 +447,19 @@ __global__ void __launch_bounds__(256) row_norm2_kernel(const float2* __restrict
 }
 
 // x_p *= sqrt(sum(y_p) * inv_mc) * inv[p]
+// (a NaN or Inf in the estimate raises the flag nf)
 __global__ void dense_final_scale_kernel(float2* x, int n, int nb, const double* ysum, const float* inv,
-                                         float inv_mc) {
+                                         float inv_mc, unsigned* nf) {
   const long long tot = (long long)n * nb;
+  bool bad = false;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
        e += (long long)gridDim.x * blockDim.x) {
     const int p = (int)(e / n);
-    x[e] = cscale(x[e], (float)sqrt(ysum[p] * (double)inv_mc) * inv[p]);
+    const float2 v = cscale(x[e], (float)sqrt(ysum[p] * (double)inv_mc) * inv[p]);
+    x[e] = v;
+    bad |= !finite2(v);
   }
+  flag_nonfinite(nf, bad);
 }
 
 // Reduction splits of one product: about kTargetGroups workgroups, every
@@ -488,6 +499,7 @@ DenseArgs base(const sr_plan_s* p) {
   a.m = (int)p->geo[0].m;
   a.n = (int)p->geo[0].n;
   a.nb = (int)p->geo.size();
+  a.nf = p->sync + 2;
   return a;
 }
 
@@ -607,7 +619,8 @@ sr_status dense_spectral(sr_plan_s* p, const float* y, const float2* v0, int ite
   DN_HIP(hipGetLastError());
   const long long tot = (long long)a.n * a.nb;
   const int groups = (int)std::min<long long>((tot + 255) / 256, 2048);
-  hipLaunchKernelGGL(dense_final_scale_kernel, dim3(groups), dim3(256), 0, p->stream, x0, a.n, a.nb, ysum, inv, inv_mc);
+  hipLaunchKernelGGL(dense_final_scale_kernel, dim3(groups), dim3(256), 0, p->stream, x0, a.n, a.nb, ysum, inv, inv_mc,
+                     a.nf);
   DN_HIP(hipGetLastError());
   return SR_OK;
 }

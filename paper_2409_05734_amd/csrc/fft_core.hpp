@@ -118,6 +118,19 @@ __device__ __forceinline__ void st1(Rsrc r, unsigned off, float x) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, off, 0, 0);
 }
 
+// ------------------------------------------------------- non-finite values
+// True unless v is NaN or +-Inf (the comparison fails for NaN).
+__device__ __forceinline__ bool finite2(float2 v) {
+  return fabsf(v.x) <= 3.402823466e38f && fabsf(v.y) <= 3.402823466e38f;
+}
+
+// Raise the non-finite flag from the lanes that met one: a vector store of
+// the same value from every such lane (no read-modify-write needed).
+__device__ __forceinline__ void flag_nonfinite(unsigned* nf, bool bad) {
+  if (nf != nullptr && bad)
+    __builtin_amdgcn_raw_buffer_store_b32(1u, __builtin_amdgcn_make_buffer_rsrc(nf, (short)0, 4, 0x00020000), 0u, 0, 0);
+}
+
 // --------------------------------------------------------------- butterflies
 // In-place R-point DFT, y_k = sum_j u_j w^(jk), w = exp(-2 pi i/R) (forward)
 // or exp(+2 pi i/R) (INV).  No scaling.

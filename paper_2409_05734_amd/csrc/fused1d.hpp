@@ -35,6 +35,7 @@ struct Fused1DArgs {
   int loss;                  // GD: LOSS_L2 or LOSS_POISSON
   float loss_eps;            // GD: Poisson guard
   float* gth;                // derivatives: phase-cotangent accumulator (L*m)
+  unsigned* nf;              // GD / spectral: set to 1 when the result holds NaN or Inf (nullable)
 };
 
 // The transform shape of the 1D kernels: the narrow shape (four elements per
@@ -160,11 +161,16 @@ __device__ __forceinline__ void fused1d_body(const Fused1DArgs& a) {
         if (in_window(k)) x[j] = make_float2(x[j].x - a.step * v[j].x, x[j].y - a.step * v[j].y);
       }
     }
+    bool bad = false;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int k = T::elem(t, j);
-      if (in_window(k)) a.x_out[k - a.off] = x[j];
+      if (in_window(k)) {
+        a.x_out[k - a.off] = x[j];
+        bad |= !finite2(x[j]);
+      }
     }
+    flag_nonfinite(a.nf, bad);
   } else if constexpr (OP == F1_FWD_VJP) {
     // x_in = x, r_in = cotangent of A x; x_out = A^H gz (nullable); gth += dtheta
     __shared__ float2 sv[kFused1DPhaseSlots];  // u_l = D_l w_{l-1}
@@ -292,11 +298,17 @@ __device__ __forceinline__ void fused1d_body(const Fused1DArgs& a) {
       inv = rsqrtf(block_sum<NT>(acc, red));
     }
     const float scale = sqrtf(ysum * a.step) * inv;  // sqrt(sum(y)/(m c)) / ||u||
+    bool bad = false;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int k = T::elem(t, j);
-      if (in_window(k)) a.x_out[k - a.off] = cscale(u[j], scale);
+      if (in_window(k)) {
+        const float2 o = cscale(u[j], scale);
+        a.x_out[k - a.off] = o;
+        bad |= !finite2(o);
+      }
     }
+    flag_nonfinite(a.nf, bad);
   }
 }
 

@@ -55,6 +55,7 @@ struct F2Desc {
   int op;
   int loss;          // GD: LOSS_L2 or LOSS_POISSON
   float loss_eps;    // GD: Poisson guard
+  unsigned* nf;      // set to 1 when the result holds NaN or Inf
 };
 
 template <int N>
@@ -366,11 +367,15 @@ __global__ void __launch_bounds__(kF2Threads) fused2d_kernel(const F2Desc* __res
     }
     __syncthreads();
   }
-  if (d.op == F2_SPEC) {
-    // x0 = sqrt(sum(y) / (m c)) u / ||u||
-    const float s = scale_out * pa.s_prev;
-    for (int e = threadIdx.x; e < d.N1 * d.N2; e += kF2Threads) d.x[e] = cscale(d.x[e], s);
+  // x0 = sqrt(sum(y) / (m c)) u / ||u|| (spectral); the result checked for NaN / Inf
+  const float s = d.op == F2_SPEC ? scale_out * pa.s_prev : 1.f;
+  bool bad = false;
+  for (int e = threadIdx.x; e < d.N1 * d.N2; e += kF2Threads) {
+    const float2 v = cscale(d.x[e], s);
+    if (d.op == F2_SPEC) d.x[e] = v;
+    bad |= !finite2(v);
   }
+  flag_nonfinite(d.nf, bad);
 }
 
 // Grid layout of the LDS-resident path: both lengths in {16, ..., 256} and
@@ -472,6 +477,7 @@ static F2Desc f2_desc(const sr_plan_s* p, size_t i, int op, const float* y, floa
   d.op = op;
   d.loss = p->loss;
   d.loss_eps = p->loss_eps;
+  d.nf = p->sync + 2;
   return d;
 }
 

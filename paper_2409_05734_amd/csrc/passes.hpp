@@ -109,6 +109,9 @@ struct PassArgs {
   int stack, ntr_p;
   int s_in, s_out, s_out2, s_win, s_th, s_save, s_gth, s_xin;
   const float* step_v;  // GD update of a stack: each problem's step (nullable: `step` for all)
+  // non-finite flag (nullable): the final update of a solve (POST_GD,
+  // POST_SPEC) stores 1 here when an updated iterate entry is NaN or Inf
+  unsigned* nf;
 };
 
 // 1/sqrt of the sum of the previous iterate's squared-norm partials: strided
@@ -344,6 +347,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   if constexpr (FFT2) T::template fft<INV2>(v, lds, ph, w, t, bl);
 
   if constexpr (MID != MID_STORE) {
+    constexpr bool CHECK = (POST == POST_GD || POST == POST_SPEC);  // the last update of a solve
+    bool bad = false;
     float step = a.step;
     if constexpr (POST_IS_GD) {
       if (a.step_v != nullptr && active) step = a.step_v[sp];
@@ -366,8 +371,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
         acc += ow ? cabs2(val) : 0.f;
       }
       st2(r_out, off8(ow, out_addr(k)), val);
+      if constexpr (CHECK) bad |= ow && !finite2(val);
       if constexpr (POST_FWD) v[j] = ow ? cmul(val, dq[j]) : make_float2(0.f, 0.f);  // zero outside the support
     }
+    if constexpr (CHECK) flag_nonfinite(a.nf, bad);
   }
 
   if constexpr (POST_FWD) {

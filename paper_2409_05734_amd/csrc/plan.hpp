@@ -107,7 +107,7 @@ struct sr_plan_s {
   double* ysum = nullptr;  // sum(y) scratch (per problem)
   float* fscratch = nullptr;  // float scratch (dense solver scalars)
   float* dsplit = nullptr;    // dense plans: split-reduction partial products
-  unsigned* sync = nullptr;   // [0] grid-barrier counter, [1] barrier error flag
+  unsigned* sync = nullptr;   // [0] grid-barrier counter, [1] barrier error flag, [2] non-finite flag
   double* red_ws = nullptr;   // per-workgroup partials of the two-stage reductions (kRedGroups)
   float2* vjp_buf = nullptr;  // per-layer intermediates for derivatives (allocated on first use)
   sr::StackState stk;         // the stack being run (P = 1 outside stacked calls)

@@ -38,6 +38,7 @@ inline PassArgs base_args(const sr_plan_s* p, const Geo& g, int k) {
   a.win_ld = g.W2;
   a.crop = g.cropped() ? 1 : 0;
   a.loss_eps = p->loss_eps;
+  a.nf = p->sync + 2;
   return a;
 }
 

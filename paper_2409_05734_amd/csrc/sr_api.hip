@@ -522,6 +522,7 @@ static Fused1DArgs args_1d(const sr_plan_s* p, const Geo& g, Fused1DArgs a) {
   a.tw = p->twiddles(g.M1, 1) ? p->twiddles(g.M1, 1) : p->twiddles(g.M1, 0);  // the 1D kernels' shape
   a.loss = p->loss;
   a.loss_eps = p->loss_eps;
+  a.nf = p->sync + 2;
   return a;
 }
 
@@ -754,13 +755,18 @@ sr_status sr_plan_set_loss(sr_plan p, int32_t loss, float eps) {
 sr_status sr_plan_sync(sr_plan p) {
   if (p == nullptr) return fail(SR_E_ARG, "NULL plan");
   SR_HIP(hipStreamSynchronize(p->stream));
-  int err = 0;
-  SR_HIP(hipMemcpy(&err, p->sync + 1, sizeof(int), hipMemcpyDeviceToHost));
-  if (err != 0) {
-    int zero = 0;
-    (void)hipMemcpy(p->sync + 1, &zero, sizeof(int), hipMemcpyHostToDevice);
-    return fail(SR_E_HIP, "a grid-wide barrier wait exceeded its bound; results of that solve are invalid");
+  // [1] barrier time-out, [2] non-finite result; both cleared once reported
+  unsigned flags[2] = {0, 0};
+  SR_HIP(hipMemcpy(flags, p->sync + 1, sizeof(flags), hipMemcpyDeviceToHost));
+  if (flags[0] != 0 || flags[1] != 0) {
+    const unsigned zero[2] = {0, 0};
+    SR_HIP(hipMemcpy(p->sync + 1, zero, sizeof(zero), hipMemcpyHostToDevice));
   }
+  if (flags[0] != 0)
+    return fail(SR_E_HIP, "a grid-wide barrier wait exceeded its bound; results of that solve are invalid");
+  if (flags[1] != 0)
+    return fail(SR_E_NONFINITE,
+                "a solve since the last sync produced a NaN or Inf (iterate, spectral estimate or loss-trace entry)");
   return SR_OK;
 }
 

@@ -29,13 +29,18 @@ __device__ double block_sum_d(double v, double* red) {
 
 // out = sum of part[0..n) in index order (one thread: order is fixed);
 // thread t does the t-th of `count` sets of n partials, into out[t * ostride]
-__global__ void reduce_partials_kernel(const float* __restrict__ part, int n, float* out, int count, int ostride) {
+// (used for loss traces: a non-finite loss raises the plan's flag nf)
+__global__ void reduce_partials_kernel(const float* __restrict__ part, int n, float* out, int count, int ostride,
+                                       unsigned* nf) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  bool bad = false;
   if (t < count) {
     double acc = 0.0;
     for (int i = 0; i < n; ++i) acc += (double)part[(long long)t * n + i];
     out[(long long)t * ostride] = (float)acc;
+    bad = !(fabs(acc) <= 3.402823466e38);
   }
+  flag_nonfinite(nf, bad);
 }
 
 // Two-stage deterministic reductions: stage 1 gives workgroup g the
@@ -94,16 +99,22 @@ void red_shape(long long n, int* groups, long long* chunk) {
 
 // x *= sqrt(sum(y) * inv_mc) / ||x||, ||x||^2 = sum of the partials
 // (blockIdx.y: one of several problems, each with its x, partials and sum)
+// (the spectral estimate's last step: a NaN or Inf in it raises the flag nf)
 __global__ void final_scale_kernel(float2* x, long long n, const float* __restrict__ part, int npart,
-                                   const double* __restrict__ ysum, float inv_mc) {
+                                   const double* __restrict__ ysum, float inv_mc, unsigned* nf) {
   x += blockIdx.y * n;
   part += blockIdx.y * npart;
   ysum += blockIdx.y;
   double acc = 0.0;
   for (int i = 0; i < npart; ++i) acc += (double)part[i];
   const float sc = (float)(sqrt(*ysum * (double)inv_mc) / sqrt(acc));
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    x[i] = cscale(x[i], sc);
+  bool bad = false;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const float2 v = cscale(x[i], sc);
+    x[i] = v;
+    bad |= !finite2(v);
+  }
+  flag_nonfinite(nf, bad);
 }
 
 // out[i] = exp(i theta[i])
@@ -147,7 +158,7 @@ sr_status fill_phase_table(sr_plan_s* p) {
 
 sr_status reduce_partials(sr_plan_s* p, const float* part, int n, float* out, int count, int ostride) {
   hipLaunchKernelGGL(reduce_partials_kernel, dim3((count + 63) / 64), dim3(64), 0, p->stream, part, n, out, count,
-                     ostride);
+                     ostride, p->sync + 2);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SR_OK : hip_fail(e, "reduce_partials");
 }
@@ -191,7 +202,7 @@ sr_status final_scale(sr_plan_s* p, float2* x, int64_t n, const float* part, int
                       float inv_mc, int count) {
   int groups = (int)std::min<int64_t>((n + 255) / 256, 1024);
   hipLaunchKernelGGL(final_scale_kernel, dim3(groups, count), dim3(256), 0, p->stream, x, (long long)n, part, npart,
-                     ysum, inv_mc);
+                     ysum, inv_mc, p->sync + 2);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SR_OK : hip_fail(e, "final_scale");
 }

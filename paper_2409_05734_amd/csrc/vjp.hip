@@ -338,8 +338,9 @@ sr_status vjp_batch_prepare(sr_plan_s* p, VjpBatchState** out) {
   VJ_CHECK(level_bufs_alloc(p));
   VjpBatchState* st = p->vjp_batch;
   if (st == nullptr) {
+    // built completely before the plan refers to it: a failed allocation
+    // leaves no half-made state behind for the next call to reuse
     st = new VjpBatchState();
-    p->vjp_batch = st;
     size_t elems = 0;
     st->save_off.assign(p->geo.size(), 0);
     for (size_t i = 0; i < p->geo.size(); ++i) {
@@ -349,9 +350,11 @@ sr_status vjp_batch_prepare(sr_plan_s* p, VjpBatchState** out) {
     }
     if (hipMalloc(&st->save, std::max<size_t>(elems, 1) * sizeof(float2)) != hipSuccess) {
       st->save = nullptr;
+      delete st;
       return fail(SR_E_NOMEM, "batched derivative workspace allocation failed");
     }
     for (LevelLists*& l : st->lists) l = level_lists_new();
+    p->vjp_batch = st;
   }
   *out = st;
   return SR_OK;
