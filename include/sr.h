@@ -215,6 +215,23 @@ sr_status sr_spectral_init(sr_plan plan, const float* y, const void* v0, int32_t
 sr_status sr_gd_solve(sr_plan plan, const float* y, void* x_inout, int32_t iters, const float* eta_host,
                       float* loss_trace);
 
+/* sr_gd_solve for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same GD iterations as sr_gd_solve (same kernels, same results), with the
+ * two ping-pong grids in a fixed device array of the library (16 MiB per GPU,
+ * reserved when the library loads and held until the process ends) instead
+ * of the plan's workspace.  The call itself allocates nothing: no hipMalloc,
+ * no graph instantiation (every pass is launched directly), nothing but
+ * kernel launches on the plan's stream.
+ *  Limits: structured plans of 2D problems only (1D problems need no scratch;
+ *  use sr_gd_solve), each grid of at most 2^20 points (M1 * M2 <= 1048576,
+ *  e.g. 1024 x 1024); larger grids return SR_E_ARG, 1D problems
+ *  SR_E_UNSUPPORTED, dense plans SR_E_STATE.  No loss trace.
+ *  The array is shared by every call on one GPU: calls that overlap on the
+ *  same GPU (other streams, other threads) race; serialise them.
+ *  Arguments as for sr_gd_solve.                                              */
+sr_status sr_gd_solve_noalloc(sr_plan plan, const float* y, void* x_inout, int32_t iters, const float* eta_host);
+
 /* Reverse-mode derivatives (gradients follow PyTorch's complex convention
  * dL/dRe + i dL/dIm), for differentiating through A and A^H.
  * sr_forward_vjp: given x and a cotangent gz of z = A x, writes

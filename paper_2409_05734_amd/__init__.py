@@ -32,7 +32,8 @@ __all__ = [
     "Problem", "Plan", "SrError",
     "sr_plan_set_theta", "sr_plan_workspace_size", "sr_plan_set_workspace", "sr_plan_offsets", "sr_plan_set_schedule", "sr_plan_set_loss",
     "sr_plan_sync",
-    "sr_forward", "sr_adjoint", "sr_spectral_init", "sr_gd_solve", "sr_forward_vjp", "sr_adjoint_vjp",
+    "sr_forward", "sr_adjoint", "sr_spectral_init", "sr_gd_solve", "sr_gd_solve_noalloc", "sr_forward_vjp",
+    "sr_adjoint_vjp",
     "SR_STRUCTURED", "SR_DENSE", "SR_SCHED_AUTO", "SR_SCHED_LOOP", "SR_SCHED_BATCHED", "SR_LOSS_L2", "SR_LOSS_POISSON",
     "SR_E_NONFINITE",
 ]
@@ -236,6 +237,15 @@ def sr_gd_solve(plan: Plan, y, x_inout, iters: int, eta, loss_trace=None) -> Non
               _ptr(x_inout, torch.complex64, plan.n_total, "x_inout"), int(iters),
               eta_h.ctypes.data_as(ctypes.c_void_p),
               _ptr(loss_trace, torch.float32, int(iters) * plan.nprob, "loss_trace", True))
+
+
+def sr_gd_solve_noalloc(plan: Plan, y, x_inout, iters: int, eta) -> None:
+    """sr_gd_solve that allocates no device memory (2D grids up to 2^20 points)."""
+    torch = _torch()
+    eta_h = np.ascontiguousarray(np.broadcast_to(np.asarray(eta, dtype=np.float32), (plan.nprob,)))
+    _lib.call("sr_gd_solve_noalloc", plan.handle, _ptr(y, torch.float32, plan.m_total, "y"),
+              _ptr(x_inout, torch.complex64, plan.n_total, "x_inout"), int(iters),
+              eta_h.ctypes.data_as(ctypes.c_void_p))
 
 
 def sr_forward_vjp(plan: Plan, x, gz, gx_out, gtheta_accum) -> None:

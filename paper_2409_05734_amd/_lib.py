@@ -59,6 +59,7 @@ SIGNATURES = {
     "sr_adjoint": (ctypes.c_int, [_vp, _vp, _vp]),
     "sr_spectral_init": (ctypes.c_int, [_vp, _vp, _vp, _i32, _f32, _vp]),
     "sr_gd_solve": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),
+    "sr_gd_solve_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp]),
     "sr_forward_vjp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "sr_adjoint_vjp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "sr_status_string": (ctypes.c_char_p, [ctypes.c_int]),

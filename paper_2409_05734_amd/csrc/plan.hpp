@@ -139,6 +139,7 @@ struct sr_plan_s {
   hipStream_t aux_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
+  int device = 0;  // the GPU the plan was created on (current device at sr_plan_create)
   int schedule = SR_SCHED_AUTO;
   int loss = SR_LOSS_L2;  // GD loss (sr_plan_set_loss) and its Poisson guard
   float loss_eps = 0.f;

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -570,6 +571,43 @@ static sr_status flush_1d(sr_plan_s* p, int op, Batch1D& items) {
 
 // ====================================================================== ABI
 
+// ------------------------------------------------ no-allocation GD scratch
+// sr_gd_solve_noalloc keeps its two ping-pong grids in this file-scope device
+// array instead of the plan's workspace, so that the call allocates nothing.
+// Each GPU the library runs on holds its own copy until the process ends; its
+// address on a device comes from hipGetSymbolAddress, taken once per device
+// at plan creation with that device current (in host code the array's name
+// is not a device address and is never used directly).  Every call on a GPU
+// shares that GPU's array: calls that overlap on one GPU (two streams, two
+// threads) race.  No part of it needs clearing: every pass reads only what an
+// earlier pass of the same call wrote.
+namespace {
+constexpr size_t kScratchBytes = size_t(16) << 20;  // two grids of up to 2^20 points
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Once per device, with that device current: the device address of `scratch`.
+sr_status scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(SR_E_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device] != nullptr) return SR_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+  if (ptr == nullptr) return fail(SR_E_HIP, "no device address for the scratch array");
+  g_scratch_ptr[device] = ptr;
+  return SR_OK;
+}
+
+void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+}  // namespace
+
 extern "C" {
 
 const char* sr_status_string(sr_status s) {
@@ -647,8 +685,12 @@ sr_status sr_plan_create(sr_plan* out, const sr_problem* probs, int32_t nprob, c
     if (theta_host != nullptr || theta_len != 0) return fail(SR_E_ARG, "theta must be NULL for dense plans");
   }
 
+  int device = 0;
+  SR_HIP(hipGetDevice(&device));
+  if (kind == SR_STRUCTURED) SR_CHECK(scratch_setup(device));
   sr_plan_s* p = new (std::nothrow) sr_plan_s();
   if (p == nullptr) return fail(SR_E_NOMEM, "host allocation failed");
+  p->device = device;
   p->geo = geo;
   p->kind = kind;
   p->stream = (hipStream_t)hip_stream;
@@ -1008,6 +1050,50 @@ sr_status sr_gd_solve(sr_plan p, const float* y, void* x_inout, int32_t iters, c
     }
   }
   return flush_1d(p, F1_GD, b1);
+}
+
+// GD with the ping-pong grids in the device's scratch array: the passes of
+// sr_gd_solve's per-problem schedule (first pass, then steady iterations with
+// the update fused into the next first pass), launched directly (no graphs,
+// whose instantiation allocates), problem after problem on the plan's stream.
+sr_status sr_gd_solve_noalloc(sr_plan p, const float* y, void* x_inout, int32_t iters, const float* eta_host) {
+  if (p == nullptr || y == nullptr || x_inout == nullptr || eta_host == nullptr)
+    return fail(SR_E_ARG, "NULL argument");
+  if (iters < 0) return fail(SR_E_ARG, "iters must be >= 0");
+  if (p->kind != SR_STRUCTURED) return fail(SR_E_STATE, "the no-allocation GD takes structured plans only");
+  for (size_t i = 0; i < p->geo.size(); ++i) {
+    const Geo& g = p->geo[i];
+    if (!std::isfinite(eta_host[i])) return fail(SR_E_NONFINITE, "step size is not finite");
+    if (g.ndim != 2)
+      return fail(SR_E_UNSUPPORTED, "the no-allocation GD takes 2D problems only (1D solves need no scratch: "
+                                    "sr_gd_solve runs them in LDS)");
+    const size_t need = 2 * (size_t)g.mg * sizeof(float2);
+    if (need > kScratchBytes)
+      return fail(SR_E_ARG, "problem " + std::to_string(i) + ": a " + std::to_string(g.M1) + "x" +
+                                std::to_string(g.M2) + " grid needs " + std::to_string(need) +
+                                " bytes of scratch; the no-allocation GD holds " + std::to_string(kScratchBytes) +
+                                " (grids up to 2^20 points)");
+  }
+  float2* const ptr = (float2*)scratch_ptr(p->device);
+  if (ptr == nullptr) return fail(SR_E_STATE, "no scratch address for the plan's device");
+  if (iters == 0) return SR_OK;
+  float2* xs = (float2*)x_inout;
+  float2* const a0 = p->bufA;
+  float2* const b0 = p->bufB;
+  sr_status st = SR_OK;
+  for (size_t i = 0; i < p->geo.size() && st == SR_OK; ++i) {
+    const Geo& g = p->geo[i];
+    const float* yi = y + p->yoff[i];
+    float2* xi = xs + p->xoff[i];
+    const float step = eta_host[i] / (float)g.m;
+    p->bufA = ptr;
+    p->bufB = ptr + g.mg;
+    st = first_pass(p, g, xi, 1.f, nullptr, 0);
+    for (int it = 0; it < iters && st == SR_OK; ++it) st = gd_steady(p, g, yi, xi, step, nullptr, it == iters - 1);
+  }
+  p->bufA = a0;
+  p->bufB = b0;
+  return st;
 }
 
 // Whether a stack's spectral passes keep each tile inside one problem (the
