@@ -568,14 +568,30 @@ def autograd(torch, srpr, sr_inputs, dev):
         tot.backward()
         return t.grad
 
+    def peak_bytes(steps):
+        # torch-allocated device memory of one objective and its gradient
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats(dev)
+        base = torch.cuda.memory_allocated(dev)
+        t = th.clone().requires_grad_(True)
+        unrolled_gd_loss(plan, t, xs, x0, steps, d["mu"]).backward()
+        torch.cuda.synchronize()
+        return torch.cuda.max_memory_allocated(dev) - base
+
     g1 = batch_step()
     g2 = loop_step()
     rel = float(((g1 - g2).norm() / g2.norm()).item())
     b_ms = _time_calls(torch, s, batch_step, 2, warm=1)
     l_ms = _time_calls(torch, s, loop_step, 1, warm=0)
+    p20, p10 = peak_bytes(d["steps"]), peak_bytes(d["steps"] // 2)
+    n_tot, m_tot = B * int(np.prod(n_shape)), B * int(np.prod(m_shape))
     return {"workload": "64 problems 128^2 -> 256^2, L=2, loss after 20 unrolled GD steps, d loss / d theta",
             "batched_plan_ms": b_ms, "per_problem_loop_ms": l_ms, "speedup_vs_loop": l_ms / b_ms,
-            "grad_rel_diff_vs_loop": rel}
+            "grad_rel_diff_vs_loop": rel,
+            "torch_peak_bytes_20_steps": int(p20), "torch_peak_bytes_10_steps": int(p10),
+            "torch_bytes_per_step": (p20 - p10) / (d["steps"] - d["steps"] // 2),
+            "signal_bytes_per_step": 8 * n_tot, "measurement_bytes": 8 * m_tot,
+            "library_temporaries_bytes": 8 * (3 * m_tot + 2 * n_tot)}
 
 
 def lds_resident(torch, srpr, sr_inputs, dev, count=512, iters=300):

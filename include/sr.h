@@ -243,6 +243,25 @@ sr_status sr_gd_solve_noalloc(sr_plan plan, const float* y, void* x_inout, int32
 sr_status sr_forward_vjp(sr_plan plan, const void* x, const void* gz, void* gx_out, float* gtheta_accum);
 sr_status sr_adjoint_vjp(sr_plan plan, const void* r, const void* gv, void* gr_out, float* gtheta_accum);
 
+/* Reverse mode through one GD step and through the intensities, for
+ * differentiating an unrolled solve with respect to the phase masks (e.g. mask
+ * design: a loss on the iterate after T steps, with y = |A(theta) x*|^2).
+ * sr_gd_step_vjp: the step x+ = x - (eta/m) A^H((|Ax|^2 - y) . Ax) of
+ *   sr_gd_solve (section II-B.1, Eq. (2); l2 loss only).  Given x (the step's
+ *   input), y, eta (HOST array, one raw step per problem) and the cotangent
+ *   gx_next of x+, writes gx_out = d<gx_next, x+>/dx (must not alias gx_next)
+ *   and ADDS d<gx_next, x+>/dy into gy_accum (measurement layout, nullable)
+ *   and d<gx_next, x+>/dtheta into gtheta_accum.  Nothing of the forward step
+ *   needs to be kept: A x and the residual are recomputed.
+ * sr_intensity_vjp: y = |A x|^2 (Eq. (1)).  Given x and the cotangent gy of
+ *   y, writes gx_out = d<gy, y>/dx (nullable) and ADDS d<gy, y>/dtheta into
+ *   gtheta_accum.
+ * Structured plans; the first call allocates 3 measurement-sized and 2
+ * signal-sized complex64 temporaries for the plan's lifetime.                 */
+sr_status sr_gd_step_vjp(sr_plan plan, const float* y, const void* x, const float* eta_host, const void* gx_next,
+                         void* gx_out, float* gy_accum, float* gtheta_accum);
+sr_status sr_intensity_vjp(sr_plan plan, const void* x, const float* gy, void* gx_out, float* gtheta_accum);
+
 /* Static description of a status code.                                        */
 const char* sr_status_string(sr_status s);
 

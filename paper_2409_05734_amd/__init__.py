@@ -33,7 +33,7 @@ __all__ = [
     "sr_plan_set_theta", "sr_plan_workspace_size", "sr_plan_set_workspace", "sr_plan_offsets", "sr_plan_set_schedule", "sr_plan_set_loss",
     "sr_plan_sync",
     "sr_forward", "sr_adjoint", "sr_spectral_init", "sr_gd_solve", "sr_gd_solve_noalloc", "sr_forward_vjp",
-    "sr_adjoint_vjp",
+    "sr_adjoint_vjp", "sr_gd_step_vjp", "sr_intensity_vjp",
     "SR_STRUCTURED", "SR_DENSE", "SR_SCHED_AUTO", "SR_SCHED_LOOP", "SR_SCHED_BATCHED", "SR_LOSS_L2", "SR_LOSS_POISSON",
     "SR_E_NONFINITE",
 ]
@@ -261,4 +261,23 @@ def sr_adjoint_vjp(plan: Plan, r, gv, gr_out, gtheta_accum) -> None:
     _lib.call("sr_adjoint_vjp", plan.handle, _ptr(r, torch.complex64, plan.m_total, "r"),
               _ptr(gv, torch.complex64, plan.n_total, "gv"),
               _ptr(gr_out, torch.complex64, plan.m_total, "gr_out", True),
+              _ptr(gtheta_accum, torch.float32, plan.theta_len, "gtheta_accum"))
+
+
+def sr_gd_step_vjp(plan: Plan, y, x, eta, gx_next, gx_out, gy_accum, gtheta_accum) -> None:
+    torch = _torch()
+    eta_h = np.ascontiguousarray(np.broadcast_to(np.asarray(eta, dtype=np.float32), (plan.nprob,)))
+    _lib.call("sr_gd_step_vjp", plan.handle, _ptr(y, torch.float32, plan.m_total, "y"),
+              _ptr(x, torch.complex64, plan.n_total, "x"), eta_h.ctypes.data_as(ctypes.c_void_p),
+              _ptr(gx_next, torch.complex64, plan.n_total, "gx_next"),
+              _ptr(gx_out, torch.complex64, plan.n_total, "gx_out"),
+              _ptr(gy_accum, torch.float32, plan.m_total, "gy_accum", True),
+              _ptr(gtheta_accum, torch.float32, plan.theta_len, "gtheta_accum"))
+
+
+def sr_intensity_vjp(plan: Plan, x, gy, gx_out, gtheta_accum) -> None:
+    torch = _torch()
+    _lib.call("sr_intensity_vjp", plan.handle, _ptr(x, torch.complex64, plan.n_total, "x"),
+              _ptr(gy, torch.float32, plan.m_total, "gy"),
+              _ptr(gx_out, torch.complex64, plan.n_total, "gx_out", True),
               _ptr(gtheta_accum, torch.float32, plan.theta_len, "gtheta_accum"))

@@ -62,6 +62,8 @@ SIGNATURES = {
     "sr_gd_solve_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp]),
     "sr_forward_vjp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "sr_adjoint_vjp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "sr_gd_step_vjp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "sr_intensity_vjp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "sr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sr_last_error": (ctypes.c_char_p, []),
 }

@@ -205,6 +205,9 @@ sr_plan_s::~sr_plan_s() {
   if (f1_args) (void)hipFree(f1_args);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   if (vjp_buf) (void)hipFree(vjp_buf);
+  if (gstep_buf) (void)hipFree(gstep_buf);
+  if (d_off) (void)hipFree(d_off);
+  if (d_scale) (void)hipFree(d_scale);
   if (stk_buf) (void)hipFree(stk_buf);
   if (stk_gth) (void)hipFree(stk_gth);
   if (stk_steps) (void)hipFree(stk_steps);

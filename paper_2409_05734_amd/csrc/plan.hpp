@@ -124,6 +124,12 @@ struct sr_plan_s {
   sr::OpBatchState* op_batch = nullptr;      // and for batched A / A^H
   sr::VjpBatchState* vjp_batch = nullptr;    // and for the batched derivatives
   float2* lvl_bufs = nullptr;                // their shared per-problem ping-pong buffers
+  // GD-step and intensity derivatives (vjp.hip): z, r, rbar (measurement
+  // layout) and two signal-layout temporaries, allocated on first use; a
+  // device copy of the concatenation offsets and the per-problem step scales
+  float2* gstep_buf = nullptr;
+  int64_t* d_off = nullptr;  // x offsets (nprob + 1), then y offsets (nprob + 1)
+  float* d_scale = nullptr;  // nprob per-problem factors
   std::vector<size_t> lvl_off;
   size_t vjp_elems = 0;
 
@@ -214,5 +220,9 @@ sr_status batched_spectral(sr_plan_s* p, const std::vector<int>& which, const fl
 // vjp.hip (reverse-mode derivatives of A and A^H)
 sr_status vjp_forward(sr_plan_s* p, const float2* x, const float2* gz, float2* gx, float* gtheta);
 sr_status vjp_adjoint(sr_plan_s* p, const float2* r, const float2* gv, float2* gr, float* gtheta);
+// one GD step's reverse (l2 loss) and the reverse of y = |A x|^2
+sr_status gd_step_vjp(sr_plan_s* p, const float* y, const float2* x, const float* eta_host, const float2* gxn,
+                      float2* gx, float* gy, float* gtheta);
+sr_status intensity_vjp(sr_plan_s* p, const float2* x, const float* gy, float2* gx, float* gtheta);
 
 }  // namespace sr

@@ -1293,4 +1293,24 @@ sr_status sr_adjoint_vjp(sr_plan p, const void* r, const void* gv, void* gr_out,
   return vjp_adjoint(p, (const float2*)r, (const float2*)gv, (float2*)gr_out, gtheta_accum);
 }
 
+sr_status sr_gd_step_vjp(sr_plan p, const float* y, const void* x, const float* eta_host, const void* gx_next,
+                         void* gx_out, float* gy_accum, float* gtheta_accum) {
+  if (p == nullptr || y == nullptr || x == nullptr || eta_host == nullptr || gx_next == nullptr || gx_out == nullptr ||
+      gtheta_accum == nullptr)
+    return fail(SR_E_ARG, "NULL argument");
+  if (p->kind != SR_STRUCTURED) return fail(SR_E_STATE, "VJPs need a structured plan");
+  if (p->loss != SR_LOSS_L2) return fail(SR_E_UNSUPPORTED, "the GD-step derivative covers the l2 intensity loss");
+  for (size_t i = 0; i < p->geo.size(); ++i)
+    if (!std::isfinite(eta_host[i])) return fail(SR_E_NONFINITE, "step size is not finite");
+  if (gx_out == gx_next) return fail(SR_E_ARG, "gx_out must not alias gx_next");
+  return gd_step_vjp(p, y, (const float2*)x, eta_host, (const float2*)gx_next, (float2*)gx_out, gy_accum,
+                     gtheta_accum);
+}
+
+sr_status sr_intensity_vjp(sr_plan p, const void* x, const float* gy, void* gx_out, float* gtheta_accum) {
+  if (p == nullptr || x == nullptr || gy == nullptr || gtheta_accum == nullptr) return fail(SR_E_ARG, "NULL argument");
+  if (p->kind != SR_STRUCTURED) return fail(SR_E_STATE, "VJPs need a structured plan");
+  return intensity_vjp(p, (const float2*)x, gy, (float2*)gx_out, gtheta_accum);
+}
+
 }  // extern "C"

@@ -551,3 +551,153 @@ sr_status vjp_adjoint(sr_plan_s* p, const float2* r, const float2* gv, float2* g
 }
 
 }  // namespace sr
+
+namespace sr {
+
+// ------------------------------------------- GD-step and intensity derivatives
+// One GD step (section II-B.1, Eq. (2)): z = A x, r = (|z|^2 - y) z,
+// x+ = x - (eta/m) A^H r.  Given the cotangent xbar+ of x+ (PyTorch's
+// convention), the reverse step is
+//   vbar = -(eta/m) xbar+,   (rbar, thetabar) from the derivative of A^H r,
+//   zbar = (2|z|^2 - y) rbar + z^2 conj(rbar),   ybar += -Re(conj(rbar) z),
+//   (xbar_A, thetabar) from the derivative of A x,   xbar = xbar+ + xbar_A,
+// with z recomputed from x (nothing of the forward step is kept but x).
+// The intensities y = |A x|^2 (Eq. (1)) have zbar = 2 ybar z.
+namespace {
+
+// problem b = blockIdx.y covers [off[b], off[b + 1]) of a concatenated array
+#define SR_PROBLEM_RANGE(off)                                                                     \
+  const long long lo_ = (off)[blockIdx.y], hi_ = (off)[blockIdx.y + 1];                          \
+  for (long long e = lo_ + blockIdx.x * (long long)blockDim.x + threadIdx.x; e < hi_;            \
+       e += (long long)gridDim.x * blockDim.x)
+
+// r = (|z|^2 - y) z   (the l2 residual of the GD step)
+__global__ void step_resid_kernel(const float2* __restrict__ z, const float* __restrict__ y, float2* __restrict__ r,
+                                  const int64_t* __restrict__ yoff) {
+  SR_PROBLEM_RANGE(yoff) {
+    const float2 zz = z[e];
+    r[e] = cscale(zz, cabs2(zz) - y[e]);
+  }
+}
+
+// out = s_b * in over problem b's signal (s_b = -eta_b / m_b)
+__global__ void step_scale_kernel(const float2* __restrict__ in, const float* __restrict__ s, float2* __restrict__ out,
+                                  const int64_t* __restrict__ xoff) {
+  const float sb = s[blockIdx.y];
+  SR_PROBLEM_RANGE(xoff) out[e] = cscale(in[e], sb);
+}
+
+// rbar -> zbar = (2|z|^2 - y) rbar + z^2 conj(rbar) in place; gy += -Re(conj(rbar) z)
+__global__ void step_zbar_kernel(const float2* __restrict__ z, const float* __restrict__ y, float2* __restrict__ rz,
+                                 float* __restrict__ gy, const int64_t* __restrict__ yoff) {
+  SR_PROBLEM_RANGE(yoff) {
+    const float2 zz = z[e], rb = rz[e];
+    const float a = 2.f * cabs2(zz) - y[e];
+    const float2 z2 = cmul(zz, zz);
+    rz[e] = make_float2(a * rb.x + z2.x * rb.x + z2.y * rb.y, a * rb.y + z2.y * rb.x - z2.x * rb.y);
+    if (gy != nullptr) gy[e] -= rb.x * zz.x + rb.y * zz.y;
+  }
+}
+
+// out = a + b
+__global__ void step_add_kernel(const float2* __restrict__ a, const float2* __restrict__ b, float2* __restrict__ out,
+                                long long n) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    out[e] = cadd(a[e], b[e]);
+}
+
+// z <- 2 gy z   (cotangent of z from that of y = |z|^2)
+__global__ void intensity_bar_kernel(float2* __restrict__ z, const float* __restrict__ gy, long long n) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    z[e] = cscale(z[e], 2.f * gy[e]);
+}
+
+#undef SR_PROBLEM_RANGE
+
+dim3 range_grid(const sr_plan_s* p, bool meas) {
+  int64_t longest = 0;
+  for (const Geo& g : p->geo) longest = std::max(longest, meas ? g.m : g.n);
+  return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((longest + 255) / 256, 512)), (unsigned)p->geo.size());
+}
+
+dim3 flat_grid(long long n) { return dim3((unsigned)std::max<long long>(1, std::min<long long>((n + 255) / 256, 4096))); }
+
+// The temporaries (3 measurement-layout arrays, 2 signal-layout ones) and the
+// device offset table, allocated once per plan.
+sr_status step_bufs(sr_plan_s* p) {
+  if (p->gstep_buf != nullptr) return SR_OK;
+  const size_t m = (size_t)p->yoff.back(), n = (size_t)p->xoff.back(), np = p->geo.size();
+  float2* buf = nullptr;
+  if (hipMalloc(&buf, (3 * m + 2 * n) * sizeof(float2)) != hipSuccess)
+    return fail(SR_E_NOMEM, "GD-step derivative workspace allocation failed");
+  int64_t* off = nullptr;
+  if (hipMalloc(&off, 2 * (np + 1) * sizeof(int64_t)) != hipSuccess) {
+    (void)hipFree(buf);
+    return fail(SR_E_NOMEM, "offset table allocation failed");
+  }
+  float* sc = nullptr;
+  if (hipMalloc(&sc, np * sizeof(float)) != hipSuccess) {
+    (void)hipFree(buf);
+    (void)hipFree(off);
+    return fail(SR_E_NOMEM, "step table allocation failed");
+  }
+  // the plan's offset vectors live as long as the plan: an ordered copy
+  hipError_t e = hipMemcpyAsync(off, p->xoff.data(), (np + 1) * sizeof(int64_t), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(off + np + 1, p->yoff.data(), (np + 1) * sizeof(int64_t), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(buf);
+    (void)hipFree(off);
+    (void)hipFree(sc);
+    return hip_fail(e, "offset table upload");
+  }
+  p->gstep_buf = buf;
+  p->d_off = off;
+  p->d_scale = sc;
+  return SR_OK;
+}
+
+}  // namespace
+
+sr_status gd_step_vjp(sr_plan_s* p, const float* y, const float2* x, const float* eta_host, const float2* gxn,
+                      float2* gx, float* gy, float* gtheta) {
+  VJ_CHECK(step_bufs(p));
+  const size_t m = (size_t)p->yoff.back(), n = (size_t)p->xoff.back(), np = p->geo.size();
+  float2* z = p->gstep_buf;
+  float2* r = z + m;
+  float2* rz = r + m;     // rbar, then zbar
+  float2* vbar = rz + m;  // -(eta/m) xbar+
+  float2* gxa = vbar + n; // A^H zbar
+  const int64_t* xoff = p->d_off;
+  const int64_t* yoff = p->d_off + np + 1;
+  std::vector<float> s(np);
+  for (size_t i = 0; i < np; ++i) s[i] = -eta_host[i] / (float)p->geo[i].m;
+  VJ_CHECK(put_floats(p, p->d_scale, s.data(), (int)np));
+  // recompute z = A x and r
+  VJ_CHECK(sr_forward(p, x, z, nullptr));
+  hipLaunchKernelGGL(step_resid_kernel, range_grid(p, true), dim3(256), 0, p->stream, z, y, r, yoff);
+  hipLaunchKernelGGL(step_scale_kernel, range_grid(p, false), dim3(256), 0, p->stream, gxn, p->d_scale, vbar, xoff);
+  if (hipError_t e = hipGetLastError(); e != hipSuccess) return hip_fail(e, "GD-step derivative kernels");
+  // through A^H r: rbar and the phase terms of the adjoint
+  VJ_CHECK(vjp_adjoint(p, r, vbar, rz, gtheta));
+  hipLaunchKernelGGL(step_zbar_kernel, range_grid(p, true), dim3(256), 0, p->stream, z, y, rz, gy, yoff);
+  if (hipError_t e = hipGetLastError(); e != hipSuccess) return hip_fail(e, "GD-step derivative kernels");
+  // through z = A x: the signal cotangent and the phase terms of the forward operator
+  VJ_CHECK(vjp_forward(p, x, rz, gxa, gtheta));
+  hipLaunchKernelGGL(step_add_kernel, flat_grid((long long)n), dim3(256), 0, p->stream, gxn, gxa, gx, (long long)n);
+  if (hipError_t e = hipGetLastError(); e != hipSuccess) return hip_fail(e, "GD-step derivative kernels");
+  return SR_OK;
+}
+
+sr_status intensity_vjp(sr_plan_s* p, const float2* x, const float* gy, float2* gx, float* gtheta) {
+  VJ_CHECK(step_bufs(p));
+  const size_t m = (size_t)p->yoff.back();
+  float2* z = p->gstep_buf;
+  VJ_CHECK(sr_forward(p, x, z, nullptr));
+  hipLaunchKernelGGL(intensity_bar_kernel, flat_grid((long long)m), dim3(256), 0, p->stream, z, gy, (long long)m);
+  if (hipError_t e = hipGetLastError(); e != hipSuccess) return hip_fail(e, "intensity derivative kernel");
+  return vjp_forward(p, x, z, gx, gtheta);
+}
+
+}  // namespace sr

@@ -111,3 +111,87 @@ def test_autograd_mask_gradient_against_central_differences(gpu):
     assert abs(loss - loss_fd) / abs(loss_fd) < 1e-4
     dd = (dirs * g.astype(np.float64)[None]).reshape(len(fd), -1).sum(axis=1)
     assert rel_l2(dd, fd) < 1e-3
+
+
+@pytest.mark.parametrize("n_shape,m_shape,L,B,shared", [((20, 12), (32, 64), 2, 1, False),
+                                                        ((24, 24), (64, 64), 3, 3, True),
+                                                        ((30, 20), (64, 32), 1, 2, False)])
+def test_gd_step_and_intensity_vjp_against_finite_differences(gpu, n_shape, m_shape, L, B, shared):
+    """sr_gd_step_vjp (reverse of one GD step of Eq. (2)) and sr_intensity_vjp
+    (reverse of y = |A x|^2, Eq. (1)) against FP64 central differences of the
+    oracle's step x - eta g(x) and of its intensities, in 6 seeded directions
+    for x, y and theta each (single problems and several problems, with
+    shared or separate masks)."""
+    import torch
+    import paper_2409_05734_amd as srpr
+    rng = np.random.default_rng(B * 10 + L)
+    n = int(np.prod(n_shape))
+    m = int(np.prod(m_shape))
+    ths = [sr_inputs.phase_masks(rng, L, m_shape) for _ in range(1 if shared else B)]
+    probs = [srpr.Problem(n_shape, m_shape, L, theta_offset=0 if shared else b * L * m) for b in range(B)]
+    plan = srpr.Plan(probs, np.concatenate([t.ravel() for t in ths]))
+    th_of = (lambda b: ths[0]) if shared else (lambda b: ths[b])
+    xs = [sr_inputs.complex_gaussian(rng, n_shape) for _ in range(B)]
+    x = [(xs[b] + 0.5 * sr_inputs.complex_gaussian(rng, n_shape)).astype(np.complex64) for b in range(B)]
+    y = [oracle.measurements(xs[b], th_of(b)).astype(np.float32) for b in range(B)]
+    eta = np.array([oracle.default_step(oracle.StructuredOperator(th_of(b), n_shape), y[b], 0.2) for b in range(B)],
+                   np.float32)
+    gxn = [sr_inputs.complex_gaussian(rng, n_shape) for _ in range(B)]
+    gyv = [rng.standard_normal(m_shape).astype(np.float32) for _ in range(B)]
+    cat = lambda a: np.concatenate([v.ravel() for v in a])
+    theta = to_dev(np.concatenate([t.ravel() for t in ths]), gpu)
+    gx = torch.empty(B * n, dtype=torch.complex64, device=gpu)
+    gy = torch.zeros(B * m, dtype=torch.float32, device=gpu)
+    gth = torch.zeros_like(theta)
+    srpr.sr_gd_step_vjp(plan, to_dev(cat(y), gpu), to_dev(cat(x), gpu), eta, to_dev(cat(gxn), gpu), gx, gy, gth)
+    gx2 = torch.empty(B * n, dtype=torch.complex64, device=gpu)
+    gth2 = torch.zeros_like(theta)
+    srpr.sr_intensity_vjp(plan, to_dev(cat(x), gpu), to_dev(cat(gyv), gpu), gx2, gth2)
+    torch.cuda.synchronize()
+    gx, gy, gth = to_host(gx).reshape(B, *n_shape), to_host(gy).reshape(B, *m_shape), to_host(gth)
+    gx2, gth2 = to_host(gx2).reshape(B, *n_shape), to_host(gth2)
+
+    def thetas(th_flat):
+        if shared:
+            return [th_flat.reshape(L, *m_shape)] * B
+        return [th_flat[b * L * m:(b + 1) * L * m].reshape(L, *m_shape) for b in range(B)]
+
+    def f_step(xx, yy, th_flat):
+        t = thetas(th_flat)
+        tot = 0.0
+        for b in range(B):
+            op = oracle.StructuredOperator(t[b], n_shape)
+            xp = xx[b] - float(eta[b]) * oracle.gd_gradient(op, yy[b], xx[b])
+            tot += np.vdot(gxn[b], xp).real
+        return tot
+
+    def f_int(xx, th_flat):
+        t = thetas(th_flat)
+        return sum(float(np.sum(gyv[b] * oracle.measurements(xx[b], t[b]))) for b in range(B))
+
+    x64 = [v.astype(np.complex128) for v in x]
+    y64 = [v.astype(np.float64) for v in y]
+    t64 = np.concatenate([t.ravel() for t in ths]).astype(np.float64)
+    eps = 1e-6
+    got, want = [], []
+    for k in range(6):
+        dx = [sr_inputs.complex_gaussian(rng, n_shape).astype(np.complex128) for _ in range(B)]
+        dy = [rng.standard_normal(m_shape) for _ in range(B)]
+        dt = rng.standard_normal(t64.shape)
+        xp = [a + eps * d for a, d in zip(x64, dx)]
+        xm = [a - eps * d for a, d in zip(x64, dx)]
+        want.append((f_step(xp, y64, t64) - f_step(xm, y64, t64)) / (2 * eps))
+        got.append(sum(np.vdot(gx[b].astype(np.complex128), dx[b]).real for b in range(B)))
+        yp = [a + eps * d for a, d in zip(y64, dy)]
+        ym = [a - eps * d for a, d in zip(y64, dy)]
+        want.append((f_step(x64, yp, t64) - f_step(x64, ym, t64)) / (2 * eps))
+        got.append(sum(float(np.sum(gy[b] * dy[b])) for b in range(B)))
+        want.append((f_step(x64, y64, t64 + eps * dt) - f_step(x64, y64, t64 - eps * dt)) / (2 * eps))
+        got.append(float(np.sum(gth * dt)))
+        want.append((f_int(xp, t64) - f_int(xm, t64)) / (2 * eps))
+        got.append(sum(np.vdot(gx2[b].astype(np.complex128), dx[b]).real for b in range(B)))
+        want.append((f_int(x64, t64 + eps * dt) - f_int(x64, t64 - eps * dt)) / (2 * eps))
+        got.append(float(np.sum(gth2 * dt)))
+    got, want = np.array(got).reshape(6, 5), np.array(want).reshape(6, 5)
+    for j in range(5):  # each derivative on its own scale
+        assert np.linalg.norm(got[:, j] - want[:, j]) <= 1e-4 * np.linalg.norm(want[:, j]), (j, got[:, j], want[:, j])
