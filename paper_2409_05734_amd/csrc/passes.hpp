@@ -244,9 +244,9 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   if constexpr (!TAB) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      if constexpr (PRE == PRE_PHASE) dp[j] = phase<false>(dp[j].x, 1.f);
-      if constexpr (MID_PH) dm[j] = phase<false>(dm[j].x, 1.f);
-      if constexpr (POST_PH) dq[j] = phase<false>(dq[j].x, 1.f);
+      if constexpr (PRE == PRE_PHASE) dp[j] = phase_turns(dp[j].x);
+      if constexpr (MID_PH) dm[j] = phase_turns(dm[j].x);
+      if constexpr (POST_PH) dq[j] = phase_turns(dq[j].x);
     }
   }
 
