@@ -6,8 +6,12 @@
 // lengths, layers and step size); level q of a batched iteration runs pass q
 // of every problem that has one.  A launch is a flat list of work items
 // (descriptor, tile); all tiles are 256-thread workgroups, the tile width of
-// each length chosen so that (N / E) * B = 256.  Each problem owns private
-// ping-pong buffers, so problems never share scratch.
+// each length chosen so that (N / E) * B = 256.  For the GD and power-
+// iteration passes, each (length, axis) runs the default thread shape (E = 8
+// or 12, radix-8 stages) or, where the length has one, the narrow shape (E =
+// 4, radix-4 stages, twice the threads per transform), as the level tuner
+// picks per plan.  Each problem owns private ping-pong buffers, so problems
+// never share scratch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,7 +34,7 @@ struct BatchDesc {
   int N;
   int col;
   int kind;
-  int pad;
+  int ev;  // thread shape: 0 default, 1 narrow (GD and power-iteration sets)
 };
 
 struct BatchItem {
@@ -38,25 +42,25 @@ struct BatchItem {
   int tile;
 };
 
-template <int N>
+template <int N, int EV = 0>
 constexpr int batch_b() {
-  return kBatchThreads * FftShape<N>::E / N;
+  return kBatchThreads * (EV ? 4 : FftShape<N>::E) / N;
 }
 
-template <int N, bool COL>
+template <int N, bool COL, int EV = 0>
 __device__ __forceinline__ void run_kind_gd(const PassArgs& a, int kind, int tile, float2* lds, float* red) {
-  constexpr int B = batch_b<N>();
+  constexpr int B = batch_b<N, EV>();
   if constexpr (COL) {
     switch (kind) {
       case PK_FIRST_FWD:
-        pass_tile_rt<N, B, COL, PRE_PHASE, MID_NONE, false, false, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
+        pass_tile_rt<N, B, COL, PRE_PHASE, MID_NONE, false, false, false, POST_STORE, EV>(a, tile, lds, red, nullptr, 0,
                                                                                    nullptr);
         return;
       case PK_LAST_GD:
-        pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_GD>(a, tile, lds, red, nullptr, 0, nullptr);
+        pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_GD, EV>(a, tile, lds, red, nullptr, 0, nullptr);
         return;
       case PK_LAST_GD_FWD:
-        pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_GD_FWD>(a, tile, lds, red, nullptr, 0,
+        pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_GD_FWD, EV>(a, tile, lds, red, nullptr, 0,
                                                                                   nullptr);
         return;
       default:
@@ -65,19 +69,19 @@ __device__ __forceinline__ void run_kind_gd(const PassArgs& a, int kind, int til
   }
   switch (kind) {
     case PK_MID_FWD:
-      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE, true, false, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE, true, false, false, POST_STORE, EV>(a, tile, lds, red, nullptr, 0,
                                                                                 nullptr);
       return;
     case PK_TURN_GD:  // (loss partials where the descriptor asks for a trace)
-      pass_tile_rt<N, B, COL, PRE_NONE, MID_GD, true, false, true, POST_STORE>(a, tile, lds, red, nullptr, 0,
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_GD, true, false, true, POST_STORE, EV>(a, tile, lds, red, nullptr, 0,
                                                                             a.part_out);
       return;
     case PK_TURN_GD_POIS:
-      pass_tile_rt<N, B, COL, PRE_NONE, MID_GD_POIS, true, false, true, POST_STORE>(a, tile, lds, red, nullptr, 0,
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_GD_POIS, true, false, true, POST_STORE, EV>(a, tile, lds, red, nullptr, 0,
                                                                                  a.part_out);
       return;
     case PK_MID_ADJ:
-      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE_CONJ, true, true, true, POST_STORE>(a, tile, lds, red, nullptr, 0,
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE_CONJ, true, true, true, POST_STORE, EV>(a, tile, lds, red, nullptr, 0,
                                                                                    nullptr);
       return;
     default:
@@ -89,21 +93,21 @@ __device__ __forceinline__ void run_kind_gd(const PassArgs& a, int kind, int til
 // The passes of a power iteration (deferred normalisation: the last pass
 // reads the previous iterate's squared-norm partials and writes the new
 // ones, each problem's own, through its descriptor).
-template <int N, bool COL>
+template <int N, bool COL, int EV = 0>
 __device__ __forceinline__ void run_kind_spec(const PassArgs& a, int kind, int tile, float2* lds, float* red) {
-  constexpr int B = batch_b<N>();
+  constexpr int B = batch_b<N, EV>();
   if constexpr (COL) {
     switch (kind) {
       case PK_FIRST_FWD:
-        pass_tile_rt<N, B, COL, PRE_PHASE, MID_NONE, false, false, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
+        pass_tile_rt<N, B, COL, PRE_PHASE, MID_NONE, false, false, false, POST_STORE, EV>(a, tile, lds, red, nullptr, 0,
                                                                                    nullptr);
         return;
       case PK_LAST_SPEC:
-        pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_SPEC>(a, tile, lds, red, a.part_in, a.npart,
+        pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_SPEC, EV>(a, tile, lds, red, a.part_in, a.npart,
                                                                                 a.part_out);
         return;
       case PK_LAST_SPEC_FWD:
-        pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_SPEC_FWD>(a, tile, lds, red, a.part_in,
+        pass_tile_rt<N, B, COL, PRE_NONE, MID_NONE, false, true, false, POST_SPEC_FWD, EV>(a, tile, lds, red, a.part_in,
                                                                                     a.npart, a.part_out);
         return;
       default:
@@ -112,14 +116,14 @@ __device__ __forceinline__ void run_kind_spec(const PassArgs& a, int kind, int t
   }
   switch (kind) {
     case PK_MID_FWD:
-      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE, true, false, false, POST_STORE>(a, tile, lds, red, nullptr, 0,
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE, true, false, false, POST_STORE, EV>(a, tile, lds, red, nullptr, 0,
                                                                                 nullptr);
       return;
     case PK_TURN_SPEC:
-      pass_tile_rt<N, B, COL, PRE_NONE, MID_SPEC, true, false, true, POST_STORE>(a, tile, lds, red, nullptr, 0, nullptr);
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_SPEC, true, false, true, POST_STORE, EV>(a, tile, lds, red, nullptr, 0, nullptr);
       return;
     case PK_MID_ADJ:
-      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE_CONJ, true, true, true, POST_STORE>(a, tile, lds, red, nullptr, 0,
+      pass_tile_rt<N, B, COL, PRE_NONE, MID_PHASE_CONJ, true, true, true, POST_STORE, EV>(a, tile, lds, red, nullptr, 0,
                                                                                    nullptr);
       return;
     default:
@@ -230,6 +234,21 @@ template <int N, int SET>
 __device__ __forceinline__ void run_len(const BatchDesc& d, int tile, float2* lds, float* red) {
   static_assert(Tile<N, batch_b<N>(), true>::THREADS == kBatchThreads, "batched tiles are 256 threads");
   static_assert(2 * sizeof(float2) * Tile<N, batch_b<N>(), true>::BUF <= kBatchLds, "batched LDS budget");
+  if constexpr (HasNarrow<N>::value && (SET == LS_GD || SET == LS_SPEC)) {
+    using TN = TileV<N, batch_b<N, 1>(), true, true, 1>;
+    static_assert(TN::THREADS == kBatchThreads, "batched narrow tiles are 256 threads");
+    static_assert(2 * sizeof(float2) * TN::BUF <= kBatchLds, "batched LDS budget");
+    if (d.ev) {
+      if constexpr (SET == LS_SPEC) {
+        if (d.col) run_kind_spec<N, true, 1>(d.a, d.kind, tile, lds, red);
+        else run_kind_spec<N, false, 1>(d.a, d.kind, tile, lds, red);
+      } else {
+        if (d.col) run_kind_gd<N, true, 1>(d.a, d.kind, tile, lds, red);
+        else run_kind_gd<N, false, 1>(d.a, d.kind, tile, lds, red);
+      }
+      return;
+    }
+  }
   if constexpr (SET == LS_SPEC) {
     if (d.col) run_kind_spec<N, true>(d.a, d.kind, tile, lds, red);
     else run_kind_spec<N, false>(d.a, d.kind, tile, lds, red);
@@ -269,7 +288,18 @@ __global__ void __launch_bounds__(kBatchThreads, 3) batched_level_kernel(const B
   }
 }
 
-int batch_tile_width(int N) {
+// Transforms per 256-thread tile: default shape, or the narrow one (ev = 1)
+// where the length has it (0: length not taken by the level kernel).
+int batch_tile_width(int N, int ev = 0) {
+  if (ev) {
+    switch (N) {
+      case 64: return batch_b<64, 1>();
+      case 128: return batch_b<128, 1>();
+      case 256: return batch_b<256, 1>();
+      case 512: return batch_b<512, 1>();
+      default: break;
+    }
+  }
   switch (N) {
     case 16: return batch_b<16>();
     case 32: return batch_b<32>();
@@ -416,7 +446,8 @@ static sr_status build_levels(sr_plan_s* p, const std::vector<std::vector<PassRe
       d.N = pass_len(g, r.k);
       d.col = pass_col(r.k);
       d.kind = r.kind;
-      const int B = batch_tile_width(d.N);
+      d.ev = (ls.set == LS_GD || ls.set == LS_SPEC) ? p->bev(d.N, d.col != 0) : 0;
+      const int B = batch_tile_width(d.N, d.ev);
       const int di = (int)descs.size();
       descs.push_back(d);
       for (int t = 0; t * B < r.a.ntr; ++t) items.push_back({di, t});
@@ -473,7 +504,7 @@ static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const fl
       const Geo& g = p->geo[i];
       const int k = g.L + 1;
       const int ntr = (k == 2) ? g.M1 : (pass_col(k) ? g.M2 : g.M1);
-      const int bt = batch_tile_width(pass_len(g, k));
+      const int bt = batch_tile_width(pass_len(g, k), p->bev(pass_len(g, k), pass_col(k)));
       pd[i] = make_int2(tot, bt > 0 ? (ntr + bt - 1) / bt : 0);
       tot += pd[i].y;
     }
@@ -490,7 +521,7 @@ static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const fl
       const Geo& g = p->geo[i];
       const int k = g.L + 1;
       const int ntr = (k == 2) ? g.M1 : (pass_col(k) ? g.M2 : g.M1);
-      const int bt = batch_tile_width(pass_len(g, k));
+      const int bt = batch_tile_width(pass_len(g, k), p->bev(pass_len(g, k), pass_col(k)));
       poff[i] = tot;
       tot += bt > 0 ? (ntr + bt - 1) / bt : 0;
     }
@@ -548,8 +579,95 @@ static sr_status batched_levels_gd(sr_plan_s* p, const float* y, float2* x, int 
 static sr_status batched_levels_gd_trace(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta,
                                         float* loss_trace);
 
+// Level tuner: for each (length, axis) of the plan's level passes that has a
+// narrow thread shape, in decreasing order of the grid points it transforms,
+// try the narrow shape against the current choice by timing batched GD
+// iterations on zeroed stand-ins (best of three runs of six iterations after
+// a warm-up), and keep the faster.  Runs once per plan, on its first batched
+// solve.  SR_BATCH_EV=0 / 1 pins every length to the default / narrow shape;
+// SR_TUNE=0 keeps the defaults.
+#define SR_CHECK_B(x)          \
+  do {                         \
+    sr_status s_ = (x);        \
+    if (s_ != SR_OK) return s_; \
+  } while (0)
+
+static sr_status batch_tune(sr_plan_s* p) {
+  if (p->batch_tuned) return SR_OK;
+  p->batch_tuned = true;
+  std::map<std::pair<int, int>, double> weight;
+  bool any = false;
+  for (const Geo& g : p->geo) {
+    if (!batch_level_capable(g) || lds_resident(g)) continue;
+    any = true;
+    if (batch_tile_width(g.M1, 1) != 0) weight[{g.M1, 1}] += (double)g.mg * (g.L + 1);
+    if (batch_tile_width(g.M2, 1) != 0) weight[{g.M2, 0}] += (double)g.mg * g.L;
+  }
+  if (!any || weight.empty()) return SR_OK;
+  if (const char* force = std::getenv("SR_BATCH_EV"); force != nullptr) {
+    const int v = std::atoi(force) != 0 ? 1 : 0;
+    for (const auto& w : weight) p->batch_ev[w.first] = v;
+    return SR_OK;
+  }
+  if (const char* env = std::getenv("SR_TUNE"); env != nullptr && std::atoi(env) == 0) return SR_OK;
+  const size_t n_tot = (size_t)p->xoff.back(), m_tot = (size_t)p->yoff.back();
+  float2* sx = nullptr;
+  float* sy = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto release = [&]() {
+    (void)hipStreamSynchronize(p->stream);  // nothing queued may still read the stand-ins
+    if (sx) (void)hipFree(sx);
+    if (sy) (void)hipFree(sy);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (p->batch) p->batch->key.clear();  // the caller's solve rebuilds its lists
+  };
+  if (hipMalloc(&sx, std::max<size_t>(n_tot, 1) * sizeof(float2)) != hipSuccess ||
+      hipMalloc(&sy, std::max<size_t>(m_tot, 1) * sizeof(float)) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    release();
+    return SR_OK;  // no room to tune: keep the defaults
+  }
+  (void)hipMemsetAsync(sx, 0, n_tot * sizeof(float2), p->stream);
+  (void)hipMemsetAsync(sy, 0, m_tot * sizeof(float), p->stream);
+  const std::vector<float> eta(p->geo.size(), 0.f);
+  sr_status st = SR_OK;
+  auto time_levels = [&](float* ms) -> sr_status {
+    if (p->batch) p->batch->key.clear();  // rebuild the lists under the current shapes
+    SR_CHECK_B(batched_levels_gd(p, sy, sx, 2, eta.data()));
+    float best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      if (hipEventRecord(e0, p->stream) != hipSuccess) return fail(SR_E_HIP, "tuner event");
+      SR_CHECK_B(batched_levels_gd(p, sy, sx, 6, eta.data()));
+      if (hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+        return fail(SR_E_HIP, "tuner event");
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      best = std::min(best, t);
+    }
+    *ms = best;
+    return SR_OK;
+  };
+  std::vector<std::pair<double, std::pair<int, int>>> order;
+  for (const auto& w : weight) order.push_back({-w.second, w.first});
+  std::sort(order.begin(), order.end());
+  float base = 0.f;
+  st = time_levels(&base);
+  for (size_t c = 0; c < order.size() && st == SR_OK; ++c) {
+    const auto key = order[c].second;
+    p->batch_ev[key] = 1;
+    float t = 0.f;
+    st = time_levels(&t);
+    if (st == SR_OK && t < base) base = t;
+    else p->batch_ev[key] = 0;
+  }
+  release();
+  return st;
+}
+
 sr_status batched_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta, float* loss_trace) {
   if (iters <= 0) return SR_OK;
+  if (sr_status t = batch_tune(p); t != SR_OK) return t;
   if (loss_trace != nullptr) return batched_levels_gd_trace(p, y, x, iters, eta, loss_trace);
   std::vector<int> small, rest;
   for (size_t i = 0; i < p->geo.size(); ++i) (lds_resident(p->geo[i]) ? small : rest).push_back((int)i);
@@ -743,7 +861,8 @@ static sr_status spec_prepare(sr_plan_s* p, const std::vector<int>& which, const
       const Geo& g = p->geo[i];
       st->part_off[i] = pelems;
       if (!batch_level_capable(g)) continue;
-      st->nq[i] = (g.N2 + batch_tile_width(g.M1) - 1) / batch_tile_width(g.M1);
+      const int bq = batch_tile_width(g.M1, p->bev(g.M1, true));  // the last (column) pass's tiles
+      st->nq[i] = (g.N2 + bq - 1) / bq;
       pelems += 2 * (size_t)std::max(st->nq[i], 1);
     }
     if (hipMalloc(&st->parts, std::max<size_t>(pelems, 1) * sizeof(float)) != hipSuccess) {
@@ -802,6 +921,7 @@ static sr_status spec_prepare(sr_plan_s* p, const std::vector<int>& which, const
 
 sr_status batched_spectral(sr_plan_s* p, const std::vector<int>& which, const float* y, const float2* v0, int iters,
                            float lam, float2* x) {
+  if (sr_status t = batch_tune(p); t != SR_OK) return t;  // shapes fixed before any list is built
   SpecBatchState* st = nullptr;
   sr_status s = spec_prepare(p, which, y, x, lam, &st);
   if (s != SR_OK) return s;

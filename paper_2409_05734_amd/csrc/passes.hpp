@@ -406,18 +406,18 @@ constexpr bool pass_has_phase() {
 // pass_tile with the phase source picked at run time (the tables are set
 // for every diagonal of a pass or for none), window-aware so that it serves
 // every geometry.
-template <int N, int B, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST>
+template <int N, int B, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST, int EV = 0>
 __device__ __forceinline__ void pass_tile_rt(const PassArgs& a, int tile, float2* lds, float* red, const float* part_in,
                                              int npart, float* part_out) {
   if constexpr (pass_has_phase<PRE, MID, POST>()) {
     if (a.ep_pre != nullptr || a.ep_mid != nullptr || a.ep_post != nullptr) {
-      pass_tile<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, true, 0, true, true>(a, tile, lds, red, part_in, npart,
-                                                                                 part_out);
+      pass_tile<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, true, EV, true, true>(a, tile, lds, red, part_in, npart,
+                                                                                  part_out);
       return;
     }
   }
-  pass_tile<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, true, 0, false, true>(a, tile, lds, red, part_in, npart,
-                                                                              part_out);
+  pass_tile<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, true, EV, false, true>(a, tile, lds, red, part_in, npart,
+                                                                               part_out);
 }
 
 template <int N, int B, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST, bool DB = true,

@@ -152,6 +152,15 @@ struct sr_plan_s {
   hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
   std::vector<std::pair<std::string, hipGraphExec_t>> graphs;  // captured solver chunks (most recent last)
   std::map<std::pair<int, int>, int> tiles;  // (FFT length, column mode) -> tuned tile width
+  // level kernel (batched schedule): (FFT length, column mode) -> thread shape
+  // of the GD and power-iteration passes (0 default, 1 narrow), tuned on the
+  // first batched solve
+  std::map<std::pair<int, int>, int> batch_ev;
+  bool batch_tuned = false;
+  int bev(int N, bool col) const {
+    auto it = batch_ev.find({N, col ? 1 : 0});
+    return it == batch_ev.end() ? 0 : it->second;
+  }
 
   int tile(int N, bool col) const {
     auto it = tiles.find({N, col ? 1 : 0});
