@@ -76,7 +76,10 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         raise RuntimeError("libsrpr build failed:\n" + msg)
     objs = [t[1] for t in tasks]
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    # hipBLASLt: the dense baseline's products where the library GEMM is faster
+    rocm_lib = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(hipcc()))), "lib")
+    cmd = ([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs +
+           ["-L" + rocm_lib, "-lhipblaslt", "-Wl,-rpath," + rocm_lib])
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("libsrpr link failed:\n" + r.stderr)

@@ -18,9 +18,13 @@
 // (|z|^2 - y) z with loss partials, the spectral weight T(y) z, and the GD or
 // spectral update of the iterate with norm partials.
 #include <hip/hip_runtime.h>
+#include <hipblaslt/hipblaslt.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
 
 #include "fft_core.hpp"
 #include "loss.hpp"
@@ -462,6 +466,77 @@ __global__ void dense_final_scale_kernel(float2* x, int n, int nb, const double*
   flag_nonfinite(nf, bad);
 }
 
+// ---- the library GEMM (hipBLASLt) for the two real products
+// The same products as dense_mm_kernel with S = 1, in column-major terms
+// (A's floats are the column-major 2n x m matrix At_cm, leading dimension 2n):
+//   A X  : D1 (q x m)  = Bxt (q x 2n) . At_cm,   Bxt = Bx^T, q = 64 per signal tile;
+//   A^H R: D2 (2n x q) = At_cm . Br (m x q),     Br[i][2p] = Re r_pi, [2p+1] = Im r_pi.
+// D1 and D2 land in the split buffer in exactly the layouts the epilogue
+// kernels read for one partial, so the epilogues are shared.
+
+// Bxt (q x 2n, column-major, leading dimension q) from the signals x (nb x n)
+__global__ void pack_bx_kernel(const float2* __restrict__ x, const float* __restrict__ scale, int n, int nb, int q,
+                               float* __restrict__ bxt) {
+  const long long tot = (long long)n * q / 2;  // (signal slot, k) pairs
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const int ps = (int)(e % (q / 2));
+    const int k = (int)(e / (q / 2));
+    float2 v = make_float2(0.f, 0.f);
+    if (ps < nb) v = cscale(x[(long long)ps * n + k], scale != nullptr ? scale[ps] : 1.f);
+    float* c0 = bxt + (long long)(2 * k) * q + 2 * ps;      // column 2k
+    float* c1 = bxt + (long long)(2 * k + 1) * q + 2 * ps;  // column 2k+1
+    c0[0] = v.x;
+    c0[1] = v.y;
+    c1[0] = -v.y;
+    c1[1] = v.x;
+  }
+}
+
+// Br (m x q, column-major, leading dimension m) from the residuals r (nb x m)
+__global__ void pack_br_kernel(const float2* __restrict__ r, const float* __restrict__ scale, int m, int nb, int q,
+                               float* __restrict__ br) {
+  const long long tot = (long long)m * (q / 2);
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % m);
+    const int ps = (int)(e / m);
+    float2 v = make_float2(0.f, 0.f);
+    if (ps < nb) v = cscale(r[(long long)ps * m + i], scale != nullptr ? scale[ps] : 1.f);
+    br[(long long)(2 * ps) * m + i] = v.x;
+    br[(long long)(2 * ps + 1) * m + i] = v.y;
+  }
+}
+
+}  // namespace
+
+struct DenseLib {
+  hipblasLtHandle_t h = nullptr;
+  hipblasLtMatmulDesc_t desc = nullptr;
+  hipblasLtMatrixLayout_t l1[3] = {nullptr, nullptr, nullptr};  // Bxt, At_cm, D1
+  hipblasLtMatrixLayout_t l2[3] = {nullptr, nullptr, nullptr};  // At_cm, Br, D2
+  hipblasLtMatmulAlgo_t algo[2];
+  bool ok[2] = {false, false};   // the product has a library algorithm
+  bool use[2] = {false, false};  // the product runs on it (else dense_mm_kernel)
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  float* pack = nullptr;  // Bxt or Br
+  ~DenseLib() {
+    for (auto l : l1)
+      if (l) (void)hipblasLtMatrixLayoutDestroy(l);
+    for (auto l : l2)
+      if (l) (void)hipblasLtMatrixLayoutDestroy(l);
+    if (desc) (void)hipblasLtMatmulDescDestroy(desc);
+    if (h) (void)hipblasLtDestroy(h);
+    if (ws) (void)hipFree(ws);
+    if (pack) (void)hipFree(pack);
+  }
+};
+
+void destroy_dense_lib(DenseLib* d) { delete d; }
+
+namespace {
+
+constexpr size_t kLibWorkspace = size_t(64) << 20;
+
 // Reduction splits of one product: about kTargetGroups workgroups, every
 // split a whole number of BK chunks.
 void plan_split(int tiles, int K, int* S, int* kchunk) {
@@ -474,17 +549,39 @@ void plan_split(int tiles, int K, int* S, int* kchunk) {
 
 int signal_tiles(const DenseArgs& a) { return (a.nb + 31) / 32; }
 
+// The product of kind G: on the library (lib != nullptr and chosen for G)
+// or on dense_mm_kernel; then the epilogue EPI.
 template <int G, int EPI>
-hipError_t gemm(DenseArgs a, float* split, hipStream_t st) {
+hipError_t gemm(DenseArgs a, float* split, hipStream_t st, const DenseLib* lib = nullptr) {
   const int M = G == 1 ? a.m : 2 * a.n;
   const int K = G == 1 ? 2 * a.n : a.m;
   const int tiles = (M + BT - 1) / BT;
-  plan_split(tiles * signal_tiles(a), K, &a.S, &a.kchunk);
   a.split = split;
   a.q_ld = 64 * signal_tiles(a);
-  hipLaunchKernelGGL((dense_mm_kernel<G>), dim3(tiles * a.S, signal_tiles(a)), dim3(NT), 0, st, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  if (lib != nullptr && lib->use[G - 1]) {
+    a.S = 1;
+    const long long pairs = G == 1 ? (long long)a.n * a.q_ld / 2 : (long long)a.m * (a.q_ld / 2);
+    const int groups = (int)std::min<long long>((pairs + 255) / 256, 8192);
+    if constexpr (G == 1)
+      hipLaunchKernelGGL(pack_bx_kernel, dim3(groups), dim3(256), 0, st, a.src, a.src_scale, a.n, a.nb, a.q_ld,
+                         lib->pack);
+    else
+      hipLaunchKernelGGL(pack_br_kernel, dim3(groups), dim3(256), 0, st, a.src, a.src_scale, a.m, a.nb, a.q_ld,
+                         lib->pack);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const float one = 1.f, zero = 0.f;
+    const hipblasLtMatrixLayout_t* l = G == 1 ? lib->l1 : lib->l2;
+    const void* opA = G == 1 ? (const void*)lib->pack : (const void*)a.A;
+    const void* opB = G == 1 ? (const void*)a.A : (const void*)lib->pack;
+    const hipblasStatus_t bs = hipblasLtMatmul(lib->h, lib->desc, &one, opA, l[0], opB, l[1], &zero, split, l[2],
+                                               split, l[2], &lib->algo[G - 1], lib->ws, lib->ws_bytes, st);
+    if (bs != HIPBLAS_STATUS_SUCCESS) return hipErrorLaunchFailure;
+  } else {
+    plan_split(tiles * signal_tiles(a), K, &a.S, &a.kchunk);
+    hipLaunchKernelGGL((dense_mm_kernel<G>), dim3(tiles * a.S, signal_tiles(a)), dim3(NT), 0, st, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if constexpr (G == 1) {
     hipLaunchKernelGGL((dense_epi1_kernel<EPI>), dim3(tiles, signal_tiles(a)), dim3(NT), 0, st, a);
   } else {
@@ -532,12 +629,98 @@ size_t dense_split_floats(int m, int n, int nb) {
 
 // Scratch layout for dense plans: bufA holds R (nb x m complex); fscratch
 // holds per-signal scalars; part holds per-signal partials.
+sr_status dense_lib_setup(sr_plan_s* p) {
+  const char* force = std::getenv("SR_DENSE_GEMM");
+  if (force != nullptr && std::strcmp(force, "own") == 0) return SR_OK;
+  DenseArgs a = base(p);
+  const uint64_t q = 64 * (uint64_t)signal_tiles(a), m = (uint64_t)a.m, n2 = 2 * (uint64_t)a.n;
+  DenseLib* d = new (std::nothrow) DenseLib();
+  if (d == nullptr) return SR_OK;
+  auto give_up = [&]() {
+    delete d;
+    return SR_OK;  // the hand-written products serve every plan
+  };
+  if (hipblasLtCreate(&d->h) != HIPBLAS_STATUS_SUCCESS) return give_up();
+  if (hipblasLtMatmulDescCreate(&d->desc, HIPBLAS_COMPUTE_32F, HIP_R_32F) != HIPBLAS_STATUS_SUCCESS) return give_up();
+  if (hipblasLtMatrixLayoutCreate(&d->l1[0], HIP_R_32F, q, n2, (int64_t)q) != HIPBLAS_STATUS_SUCCESS ||
+      hipblasLtMatrixLayoutCreate(&d->l1[1], HIP_R_32F, n2, m, (int64_t)n2) != HIPBLAS_STATUS_SUCCESS ||
+      hipblasLtMatrixLayoutCreate(&d->l1[2], HIP_R_32F, q, m, (int64_t)q) != HIPBLAS_STATUS_SUCCESS ||
+      hipblasLtMatrixLayoutCreate(&d->l2[0], HIP_R_32F, n2, m, (int64_t)n2) != HIPBLAS_STATUS_SUCCESS ||
+      hipblasLtMatrixLayoutCreate(&d->l2[1], HIP_R_32F, m, q, (int64_t)m) != HIPBLAS_STATUS_SUCCESS ||
+      hipblasLtMatrixLayoutCreate(&d->l2[2], HIP_R_32F, n2, q, (int64_t)n2) != HIPBLAS_STATUS_SUCCESS)
+    return give_up();
+  hipblasLtMatmulPreference_t pref = nullptr;
+  if (hipblasLtMatmulPreferenceCreate(&pref) != HIPBLAS_STATUS_SUCCESS) return give_up();
+  const uint64_t wmax = kLibWorkspace;
+  (void)hipblasLtMatmulPreferenceSetAttribute(pref, HIPBLASLT_MATMUL_PREF_MAX_WORKSPACE_BYTES, &wmax, sizeof(wmax));
+  size_t need = 0;
+  for (int g = 0; g < 2; ++g) {
+    const hipblasLtMatrixLayout_t* l = g == 0 ? d->l1 : d->l2;
+    hipblasLtMatmulHeuristicResult_t res[1];
+    int cnt = 0;
+    if (hipblasLtMatmulAlgoGetHeuristic(d->h, d->desc, l[0], l[1], l[2], l[2], pref, 1, res, &cnt) ==
+            HIPBLAS_STATUS_SUCCESS &&
+        cnt > 0 && res[0].state == HIPBLAS_STATUS_SUCCESS) {
+      d->algo[g] = res[0].algo;
+      d->ok[g] = true;
+      need = std::max(need, res[0].workspaceSize);
+    }
+  }
+  (void)hipblasLtMatmulPreferenceDestroy(pref);
+  if (!d->ok[0] && !d->ok[1]) return give_up();
+  if (need > 0 && hipMalloc(&d->ws, need) != hipSuccess) return give_up();
+  d->ws_bytes = need;
+  if (hipMalloc(&d->pack, sizeof(float) * std::max(q * n2, m * q)) != hipSuccess) return give_up();
+  // per product: the faster of the library and dense_mm_kernel (best of three
+  // applications each, on the plan's own matrix; the source is scratch of the
+  // right size, the epilogue writes nothing but scratch)
+  const bool all_lib = force != nullptr && std::strcmp(force, "lib") == 0;
+  const bool can_time = (size_t)a.n <= (size_t)a.m;  // bufB (m x nb) holds the A^H R output
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!all_lib && (!can_time || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
+    if (e0) (void)hipEventDestroy(e0);
+    return give_up();
+  }
+  for (int g = 0; g < 2; ++g) {
+    if (!d->ok[g]) continue;
+    if (all_lib) {
+      d->use[g] = true;
+      continue;
+    }
+    float best[2] = {1e30f, 1e30f};
+    for (int v = 0; v < 2; ++v) {
+      d->use[g] = v == 1;
+      DenseArgs t = a;
+      t.src = p->bufA;
+      t.x = p->bufB;
+      t.step = 1.f;
+      for (int rep = 0; rep < 4; ++rep) {
+        (void)hipEventRecord(e0, p->stream);
+        const hipError_t e = g == 0 ? gemm<1, E1_STORE>(t, p->dsplit, p->stream, d)
+                                    : gemm<2, E2_STORE>(t, p->dsplit, p->stream, d);
+        (void)hipEventRecord(e1, p->stream);
+        if (e != hipSuccess || hipEventSynchronize(e1) != hipSuccess) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) best[v] = std::min(best[v], ms);  // the first is a warm-up
+      }
+    }
+    d->use[g] = best[1] < best[0];
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return give_up();
+  if (!d->use[0] && !d->use[1]) return give_up();
+  p->dense_lib = d;
+  return SR_OK;
+}
+
 sr_status dense_forward(sr_plan_s* p, const float2* x, float2* z, float* y) {
   DenseArgs a = base(p);
   a.src = x;
   a.z_out = z;
   a.y_out = y;
-  DN_HIP((gemm<1, E1_STORE>(a, p->dsplit, p->stream)));
+  DN_HIP((gemm<1, E1_STORE>(a, p->dsplit, p->stream, p->dense_lib)));
   return SR_OK;
 }
 
@@ -546,7 +729,7 @@ sr_status dense_adjoint(sr_plan_s* p, const float2* r, float2* x) {
   a.src = r;
   a.x = x;
   a.step = 1.f;
-  DN_HIP((gemm<2, E2_STORE>(a, p->dsplit, p->stream)));
+  DN_HIP((gemm<2, E2_STORE>(a, p->dsplit, p->stream, p->dense_lib)));
   return SR_OK;
 }
 
@@ -565,7 +748,7 @@ sr_status dense_gd(sr_plan_s* p, const float* y, float2* x, int iters, const flo
     g1.part_ld = t1;
     g1.loss = p->loss;
     g1.loss_eps = p->loss_eps;
-    DN_HIP((gemm<1, E1_GD>(g1, p->dsplit, p->stream)));
+    DN_HIP((gemm<1, E1_GD>(g1, p->dsplit, p->stream, p->dense_lib)));
     if (loss_trace) {
       hipLaunchKernelGGL(sum_rows_kernel, dim3((a.nb + 63) / 64), dim3(64), 0, p->stream, p->part, t1, t1, a.nb,
                          loss_trace + it, iters);
@@ -575,7 +758,7 @@ sr_status dense_gd(sr_plan_s* p, const float* y, float2* x, int iters, const flo
     g2.src = p->bufA;
     g2.x = x;
     g2.step = eta[0] / (float)a.m;
-    DN_HIP((gemm<2, E2_GD>(g2, p->dsplit, p->stream)));
+    DN_HIP((gemm<2, E2_GD>(g2, p->dsplit, p->stream, p->dense_lib)));
   }
   return SR_OK;
 }
@@ -603,7 +786,7 @@ sr_status dense_spectral(sr_plan_s* p, const float* y, const float2* v0, int ite
     g1.ysum = ysum;
     g1.lam = lam;
     g1.z_out = p->bufA;
-    DN_HIP((gemm<1, E1_SPEC>(g1, p->dsplit, p->stream)));
+    DN_HIP((gemm<1, E1_SPEC>(g1, p->dsplit, p->stream, p->dense_lib)));
     DenseArgs g2 = a;  // u <- A^H r / (m c) - 2 lambda u / ||u||
     g2.src = p->bufA;
     g2.x = x0;
@@ -612,7 +795,7 @@ sr_status dense_spectral(sr_plan_s* p, const float* y, const float2* v0, int ite
     g2.prev_scale = inv;
     g2.part = p->part;
     g2.part_ld = t2;
-    DN_HIP((gemm<2, E2_SPEC>(g2, p->dsplit, p->stream)));
+    DN_HIP((gemm<2, E2_SPEC>(g2, p->dsplit, p->stream, p->dense_lib)));
     cnt = t2;
   }
   hipLaunchKernelGGL(inv_norms_kernel, dim3((a.nb + 63) / 64), dim3(64), 0, p->stream, p->part, t2, cnt, a.nb, inv);

@@ -216,6 +216,7 @@ sr_plan_s::~sr_plan_s() {
   if (spec_batch) sr::destroy_spec_batch_state(spec_batch);
   if (op_batch) sr::destroy_op_batch_state(op_batch);
   if (vjp_batch) sr::destroy_vjp_batch_state(vjp_batch);
+  if (dense_lib) sr::destroy_dense_lib(dense_lib);
   if (lvl_bufs) (void)hipFree(lvl_bufs);
   if (ws && ws_owned) (void)hipFree(ws);
 }

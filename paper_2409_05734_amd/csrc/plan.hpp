@@ -44,6 +44,8 @@ struct OpBatchState;
 void destroy_op_batch_state(OpBatchState* s);
 struct VjpBatchState;
 void destroy_vjp_batch_state(VjpBatchState* s);
+struct DenseLib;
+void destroy_dense_lib(DenseLib* d);
 
 // A stack of problems of one geometry run as one: every fused pass of the
 // first problem's schedule is launched once for all P problems, each buffer
@@ -90,6 +92,7 @@ struct sr_plan_s {
   bool use_table = false;  // passes read eph instead of evaluating sincos(theta)
   int64_t theta_len = 0;
   const float2* dense_A = nullptr;  // caller-owned dense matrix (SR_DENSE)
+  sr::DenseLib* dense_lib = nullptr;  // library GEMM state of a dense plan (null: hand-written products only)
 
   std::map<std::pair<int, int>, float2*> tw;  // (FFT length, thread shape) -> device twiddle table
   float2* twbuf = nullptr;
@@ -195,6 +198,9 @@ sr_status dense_forward(sr_plan_s* p, const float2* x, float2* z, float* y);
 sr_status dense_adjoint(sr_plan_s* p, const float2* r, float2* x);
 sr_status dense_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta, float* loss_trace);
 sr_status dense_spectral(sr_plan_s* p, const float* y, const float2* v0, int iters, float lam, float2* x0);
+// hipBLASLt for the dense products where it is faster (timed per product at
+// plan creation; SR_DENSE_GEMM=own / lib pins the choice)
+sr_status dense_lib_setup(sr_plan_s* p);
 
 // fused2d.hip (LDS-resident solves of small 2D problems, one workgroup each)
 // SR_LDS_RESIDENT=1 / 0 turns the LDS-resident solver on / off for batched

@@ -698,6 +698,7 @@ sr_status sr_plan_create(sr_plan* out, const sr_problem* probs, int32_t nprob, c
   p->dense_A = (const float2*)dense_A;
   sr_status st = p->init(theta_host);
   if (st == SR_OK && kind == SR_STRUCTURED) st = tune_plan(p);
+  if (st == SR_OK && kind == SR_DENSE) st = dense_lib_setup(p);
   if (st != SR_OK) {
     delete p;
     return st;

@@ -2,7 +2,7 @@
 FP32 MFMA against the FP64 oracle: A x and A^H r per application (relative
 L2 <= 2e-5), GD iterates (<= 1e-4 after phase alignment), spectral
 initialisation, loss traces, ragged shapes and the full 16384 x 4096 x 32
-baseline size."""
+baseline size, each on the hand-written products and on the library GEMM."""
 import numpy as np
 import pytest
 
@@ -14,6 +14,15 @@ pytestmark = pytest.mark.gpu
 
 TOL_OP = 2e-5
 TOL_IT = 1e-4
+
+
+@pytest.fixture(autouse=True, params=["own", "lib"])
+def dense_products(request, monkeypatch):
+    """Every test on both implementations of the two real products: the
+    hand-written MFMA kernel and the library GEMM (the plan's timed choice
+    is one of the two)."""
+    monkeypatch.setenv("SR_DENSE_GEMM", request.param)
+    return request.param
 
 
 def _plan(A, nb, dev):
