@@ -19,7 +19,9 @@ respect to the signal and the phases.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -144,6 +146,7 @@ class Plan:
         _lib.call("sr_plan_offsets", self.handle, xo, yo)
         self.x_off = list(xo)
         self.y_off = list(yo)
+        _track(self)
 
     @property
     def nprob(self) -> int:
@@ -167,6 +170,32 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# Plans still alive at interpreter exit are destroyed from an exit handler.
+# It is registered when the first plan is made, after torch (imported by
+# Plan.__init__) has registered its own, so it runs before them (exit
+# handlers run last-registered first): every plan's graphs, streams and
+# device memory go back while the HIP runtime and any profiler attached to it
+# are fully up, rather than from finalizers that may run during their teardown.
+_live_plans: "weakref.WeakSet[Plan]" = weakref.WeakSet()
+_exit_hook = False
+
+
+def _destroy_live_plans() -> None:
+    for plan in list(_live_plans):
+        try:
+            plan.close()
+        except Exception:
+            pass
+
+
+def _track(plan: Plan) -> None:
+    global _exit_hook
+    if not _exit_hook:
+        atexit.register(_destroy_live_plans)
+        _exit_hook = True
+    _live_plans.add(plan)
 
 
 def sr_plan_set_theta(plan: Plan, theta_dev) -> None:

@@ -87,5 +87,46 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     return LIB
 
 
+# Host sanitizers (AddressSanitizer, UndefinedBehaviorSanitizer) on the host
+# code only: each -fsanitize= applies to the host compilation (-Xarch_host);
+# device code is built as usual.  The host-side translation units are rebuilt
+# instrumented and linked, with the ordinary pass-kernel objects, into a
+# check program that drives the C ABI (csrc/host_check.cpp).
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+CHECK = os.path.join(PKG, "sr_host_check")
+
+
+def build_host_check(jobs: int | None = None) -> str:
+    """Build csrc/host_check.cpp against host-sanitized objects (needs build() first)."""
+    san = os.path.join(BUILD, "san")
+    os.makedirs(san, exist_ok=True)
+    tasks = [(os.path.join(CSRC, s), os.path.join(san, s.replace(".hip", ".o")), SAN_FLAGS) for s in SOURCES]
+    tasks.append((os.path.join(CSRC, "host_check.cpp"), os.path.join(san, "host_check.o"),
+                  SAN_FLAGS + ["-x", "hip"]))
+    plain = [os.path.join(BUILD, f"passes_{n}_{pset}.o") for n in FFT_LENGTHS for pset in (0, 1)]
+    plain += [os.path.join(BUILD, f"batched_set{k}.o") for k in range(4)]
+    missing = [o for o in plain if not os.path.exists(o)]
+    if missing:
+        raise RuntimeError("run build() first: missing " + ", ".join(missing[:3]))
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    failures = []
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        for rc, cmd, err in ex.map(lambda t: _compile(*t), tasks):
+            if rc != 0:
+                failures.append((cmd, err))
+    if failures:
+        raise RuntimeError("host check build failed:\n" + "\n\n".join(f"$ {c}\n{e}" for c, e in failures))
+    rocm_lib = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(hipcc()))), "lib")
+    cmd = ([hipcc(), f"--offload-arch={ARCH}"] + SAN_FLAGS + ["-o", CHECK] + [t[1] for t in tasks] + plain +
+           ["-L" + rocm_lib, "-lhipblaslt", "-Wl,-rpath," + rocm_lib])
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("host check link failed:\n" + r.stderr)
+    return CHECK
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
+    if "--host-check" in sys.argv:
+        print(build_host_check())

@@ -1,0 +1,203 @@
+// Host-side exercise of the C ABI for the sanitizer build (AddressSanitizer
+// and UndefinedBehaviorSanitizer on the host code only; the GPU kernels are
+// the ordinary ones).  Phase 1 needs no GPU: every argument and shape check
+// of plan creation and of the entry points, with the documented statuses.
+// Phase 2 (when a GPU is visible): plans through the tuner, the stacked,
+// batched and dense schedules, the solvers, derivatives, workspace move and
+// teardown, checking statuses only (numerics are the test-suite's job).
+// Exit status 0 when every check holds; the sanitizers abort on the first
+// host memory or undefined-behaviour error they find.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "../../include/sr.h"
+
+namespace {
+
+int g_failures = 0;
+
+void expect(bool ok, const char* what) {
+  if (!ok) {
+    std::fprintf(stderr, "FAIL: %s (last error: %s)\n", what, sr_last_error());
+    ++g_failures;
+  }
+}
+
+sr_problem prob(int ndim, int n0, int n1, int m0, int m1, int L, int kind = SR_STRUCTURED, int64_t off = 0) {
+  sr_problem q;
+  std::memset(&q, 0, sizeof(q));
+  q.ndim = ndim;
+  q.n[0] = n0;
+  q.n[1] = n1;
+  q.m[0] = m0;
+  q.m[1] = m1;
+  q.layers = L;
+  q.kind = kind;
+  q.theta_offset = off;
+  return q;
+}
+
+sr_status create(sr_plan* out, const std::vector<sr_problem>& ps, const std::vector<float>& th,
+                 const void* dense = nullptr) {
+  return sr_plan_create(out, ps.data(), (int32_t)ps.size(), th.empty() ? nullptr : th.data(), (int64_t)th.size(),
+                        dense, nullptr);
+}
+
+void argument_checks() {
+  sr_plan p = nullptr;
+  std::vector<float> th(8192, 0.5f);
+  expect(sr_plan_create(nullptr, nullptr, 0, nullptr, 0, nullptr, nullptr) == SR_E_ARG, "NULL out");
+  expect(create(&p, {}, th) == SR_E_ARG, "no problems");
+  expect(create(&p, {prob(3, 4, 4, 8, 8, 1)}, th) == SR_E_ARG, "ndim 3");
+  expect(create(&p, {prob(2, 16, 16, 32, 30, 2)}, std::vector<float>(1920, 0.f)) == SR_E_UNSUPPORTED, "length 30");
+  expect(create(&p, {prob(2, 16, 16, 32, 32, 0)}, th) == SR_E_ARG, "L = 0");
+  expect(create(&p, {prob(2, 16, 16, 32, 32, 2)}, std::vector<float>(1000, 0.f)) == SR_E_SHAPE, "theta range");
+  expect(create(&p, {prob(2, 0, 16, 32, 32, 2)}, th) == SR_E_SHAPE, "empty signal");
+  expect(create(&p, {prob(1, 40, 1, 100, 1, 1)}, th) == SR_E_UNSUPPORTED, "1D length 100");
+  expect(create(&p, {prob(1, 256, 1, 2048, 1, 4)}, th) == SR_E_UNSUPPORTED, "1D L*m");
+  {
+    const sr_problem q = prob(1, 8, 1, 32, 1, 1);
+    expect(sr_plan_create(&p, &q, 1, nullptr, 32, nullptr, nullptr) == SR_E_ARG, "structured without phases");
+  }
+  expect(create(&p, {prob(1, 8, 1, 32, 1, 1, SR_DENSE)}, {}) == SR_E_ARG, "dense without matrix");
+  expect(create(&p, {prob(1, 8, 1, 32, 1, 1), prob(1, 8, 1, 32, 1, 1, SR_DENSE)}, th) == SR_E_ARG, "mixed kinds");
+  expect(create(&p, {prob(1, 7, 1, 32, 1, 1, SR_DENSE)}, {}, (const void*)&th[0]) == SR_E_UNSUPPORTED,
+         "dense odd length");
+  expect(p == nullptr, "failed creation leaves no plan");
+  expect(sr_forward(nullptr, nullptr, nullptr, nullptr) == SR_E_ARG, "forward NULL");
+  expect(sr_adjoint(nullptr, nullptr, nullptr) == SR_E_ARG, "adjoint NULL");
+  expect(sr_gd_solve(nullptr, nullptr, nullptr, 1, nullptr, nullptr) == SR_E_ARG, "gd NULL");
+  expect(sr_gd_solve_noalloc(nullptr, nullptr, nullptr, 1, nullptr) == SR_E_ARG, "noalloc NULL");
+  expect(sr_spectral_init(nullptr, nullptr, nullptr, 1, -1.f, nullptr) == SR_E_ARG, "spectral NULL");
+  expect(sr_gd_step_vjp(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr) == SR_E_ARG,
+         "step vjp NULL");
+  expect(sr_plan_set_loss(nullptr, 0, 0.f) == SR_E_ARG, "set_loss NULL");
+  expect(sr_plan_set_workspace(nullptr, nullptr, 0) == SR_E_ARG, "set_workspace NULL");
+  expect(sr_plan_destroy(nullptr) == SR_OK, "destroy NULL");
+  for (int s = 1; s >= -7; --s) expect(sr_status_string((sr_status)s) != nullptr, "status string");
+}
+
+template <class T>
+T* dev_alloc(size_t n, float fill = 0.f) {
+  T* p = nullptr;
+  if (hipMalloc(&p, sizeof(T) * std::max<size_t>(n, 1)) != hipSuccess) return nullptr;
+  std::vector<float> h(sizeof(T) / sizeof(float) * n, fill);
+  if (hipMemcpy(p, h.data(), sizeof(T) * n, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+  return p;
+}
+
+void run_plan(const std::vector<sr_problem>& ps, const std::vector<float>& th, const char* name, int schedule) {
+  sr_plan p = nullptr;
+  if (create(&p, ps, th) != SR_OK) {
+    expect(false, name);
+    return;
+  }
+  std::vector<int64_t> xo(ps.size() + 1), yo(ps.size() + 1);
+  expect(sr_plan_offsets(p, xo.data(), yo.data()) == SR_OK, "offsets");
+  expect(sr_plan_set_schedule(p, schedule) == SR_OK, "schedule");
+  const size_t n = (size_t)xo.back(), m = (size_t)yo.back();
+  float2* x = dev_alloc<float2>(n, 0.25f);
+  float2* z = dev_alloc<float2>(m);
+  float2* v = dev_alloc<float2>(n);
+  float* y = dev_alloc<float>(m, 1.f);
+  float* gth = dev_alloc<float>(th.size());
+  float* lt = dev_alloc<float>(4 * ps.size());
+  float2* gx = dev_alloc<float2>(n);
+  float2* gr = dev_alloc<float2>(m);
+  float* gy = dev_alloc<float>(m);
+  std::vector<float> eta(ps.size(), 1e-3f);
+  expect(x && z && v && y && gth && lt && gx && gr && gy, "device buffers");
+  expect(sr_forward(p, x, z, y) == SR_OK, "forward");
+  expect(sr_adjoint(p, z, v) == SR_OK, "adjoint");
+  expect(sr_spectral_init(p, y, x, 3, -1.f, v) == SR_OK, "spectral");
+  expect(sr_gd_solve(p, y, v, 4, eta.data(), lt) == SR_OK, "gd with trace");
+  expect(sr_gd_solve(p, y, v, 60, eta.data(), nullptr) == SR_OK, "gd through a graph chunk");
+  expect(sr_forward_vjp(p, x, z, gx, gth) == SR_OK, "forward vjp");
+  expect(sr_adjoint_vjp(p, z, x, gr, gth) == SR_OK, "adjoint vjp");
+  expect(sr_gd_step_vjp(p, y, x, eta.data(), v, gx, gy, gth) == SR_OK, "gd step vjp");
+  expect(sr_intensity_vjp(p, x, y, gx, gth) == SR_OK, "intensity vjp");
+  const bool all2d = ps[0].ndim == 2;
+  if (all2d) expect(sr_gd_solve_noalloc(p, y, v, 3, eta.data()) == SR_OK, "noalloc gd");
+  expect(sr_gd_solve(p, y, v, -1, eta.data(), nullptr) == SR_E_ARG, "negative iterations");
+  std::vector<float> bad(eta);
+  bad[0] = NAN;
+  expect(sr_gd_solve(p, y, v, 2, bad.data(), nullptr) == SR_E_NONFINITE, "non-finite step");
+  size_t wsb = 0;
+  expect(sr_plan_workspace_size(p, &wsb) == SR_OK && wsb > 0, "workspace size");
+  void* ws = nullptr;
+  if (hipMalloc(&ws, wsb) == hipSuccess) {
+    expect(sr_plan_set_workspace(p, ws, wsb - 1) == SR_E_ARG, "short workspace");
+    expect(sr_plan_set_workspace(p, ws, wsb) == SR_OK, "move workspace");
+    expect(sr_gd_solve(p, y, v, 2, eta.data(), nullptr) == SR_OK, "gd after move");
+  }
+  expect(sr_plan_sync(p) == SR_OK, "sync");
+  expect(sr_plan_destroy(p) == SR_OK, "destroy");
+  if (ws) (void)hipFree(ws);
+  for (void* q : {(void*)x, (void*)z, (void*)v, (void*)y, (void*)gth, (void*)lt, (void*)gx, (void*)gr, (void*)gy})
+    if (q) (void)hipFree(q);
+  std::printf("  %s: ok\n", name);
+}
+
+void gpu_checks() {
+  // one 2D problem (tuner), a stack of three, uneven problems on the levels, 1D
+  run_plan({prob(2, 100, 90, 256, 256, 2)}, std::vector<float>(2 * 65536, 1.f), "single 2D", SR_SCHED_AUTO);
+  run_plan({prob(2, 24, 20, 64, 64, 2, SR_STRUCTURED, 0), prob(2, 24, 20, 64, 64, 2, SR_STRUCTURED, 8192),
+            prob(2, 24, 20, 64, 64, 2, SR_STRUCTURED, 16384)},
+           std::vector<float>(3 * 8192, 1.f), "stack of three", SR_SCHED_AUTO);
+  std::vector<sr_problem> uneven;
+  int64_t off = 0;
+  const int sides[] = {32, 64, 96, 128, 32, 64, 96, 128, 48};
+  for (int s : sides) {
+    uneven.push_back(prob(2, s, s, 2 * s, s == 48 ? 96 : 2 * s, 2, SR_STRUCTURED, off));
+    off += 2 * (int64_t)(2 * s) * (s == 48 ? 96 : 2 * s);
+  }
+  run_plan(uneven, std::vector<float>((size_t)off, 1.f), "uneven, batched levels", SR_SCHED_BATCHED);
+  run_plan({prob(1, 64, 1, 256, 1, 2)}, std::vector<float>(512, 1.f), "1D", SR_SCHED_AUTO);
+  // dense
+  const int m = 256, n = 64;
+  float2* A = dev_alloc<float2>((size_t)m * n, 0.5f);
+  sr_plan p = nullptr;
+  std::vector<sr_problem> dp = {prob(1, n, 1, m, 1, 1, SR_DENSE), prob(1, n, 1, m, 1, 1, SR_DENSE)};
+  if (A && sr_plan_create(&p, dp.data(), 2, nullptr, 0, A, nullptr) == SR_OK) {
+    float2* x = dev_alloc<float2>(2 * n, 0.25f);
+    float2* z = dev_alloc<float2>(2 * m);
+    float* y = dev_alloc<float>(2 * m, 1.f);
+    std::vector<float> eta(2, 0.f);  // x now holds A^H A x of a constant matrix: any step overflows it
+    expect(sr_forward(p, x, z, y) == SR_OK, "dense forward");
+    expect(sr_adjoint(p, z, x) == SR_OK, "dense adjoint");
+    expect(sr_gd_solve(p, y, x, 3, eta.data(), nullptr) == SR_OK, "dense gd");
+    expect(sr_plan_sync(p) == SR_OK, "dense sync");
+    expect(sr_plan_destroy(p) == SR_OK, "dense destroy");
+    (void)hipFree(x);
+    (void)hipFree(z);
+    (void)hipFree(y);
+    std::printf("  dense: ok\n");
+  } else {
+    expect(false, "dense plan");
+  }
+  if (A) (void)hipFree(A);
+}
+
+}  // namespace
+
+int main(int argc, char** argv) {
+  const bool no_gpu = argc > 1 && std::strcmp(argv[1], "--no-gpu") == 0;
+  std::printf("argument checks\n");
+  argument_checks();
+  if (!no_gpu) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
+      std::fprintf(stderr, "no GPU visible (run with --no-gpu for the argument checks alone)\n");
+      return 2;
+    }
+    std::printf("plans on the GPU\n");
+    gpu_checks();
+  }
+  std::printf(g_failures == 0 ? "host checks passed\n" : "host checks FAILED (%d)\n", g_failures);
+  return g_failures == 0 ? 0 : 1;
+}
