@@ -226,18 +226,31 @@ __device__ __forceinline__ void run_kind_vjp(const PassArgs& a, int kind, int ti
 
 constexpr size_t kBatchLds = 2 * sizeof(float2) * kBatchThreads * 12;  // covers 2 * B * NP elements for E <= 12
 
+// Length classes of the GD level kernel.  The twelve-element lengths (96,
+// 192, 384) hold the kernel's register count up (about 200 VGPRs, with 27
+// twiddles per thread); without them it needs 124 and no spill, and its
+// tiles fit a 36 KB LDS budget, so four workgroups share a CU.  A GD solve
+// runs the problems with no twelve-element axis on that instantiation and
+// the others on one with every length, on two streams.
+enum LevelCls : int { LEN_ALL = 0, LEN_POW2 = 1, LEN_TWELVE = 2 };
+constexpr int level_groups(int cls) { return cls == LEN_POW2 ? 4 : cls == LEN_TWELVE ? 2 : 3; }
+constexpr size_t level_lds(int cls) {
+  return cls == LEN_POW2 ? 2 * sizeof(float2) * kBatchThreads * 9 : kBatchLds;  // E = 8 tiles pad 1 in 8
+}
+constexpr bool twelve_len(int N) { return N == 96 || N == 192 || N == 384; }
+
 // Pass sets of the level kernel, one instantiation each (so that no set
 // carries the registers of the others).
 enum LevelSetKind : int { LS_GD = 0, LS_SPEC = 1, LS_OP = 2, LS_VJP = 3 };
 
-template <int N, int SET>
+template <int N, int SET, int CLS>
 __device__ __forceinline__ void run_len(const BatchDesc& d, int tile, float2* lds, float* red) {
   static_assert(Tile<N, batch_b<N>(), true>::THREADS == kBatchThreads, "batched tiles are 256 threads");
-  static_assert(2 * sizeof(float2) * Tile<N, batch_b<N>(), true>::BUF <= kBatchLds, "batched LDS budget");
+  static_assert(2 * sizeof(float2) * Tile<N, batch_b<N>(), true>::BUF <= level_lds(CLS), "batched LDS budget");
   if constexpr (HasNarrow<N>::value && (SET == LS_GD || SET == LS_SPEC)) {
     using TN = TileV<N, batch_b<N, 1>(), true, true, 1>;
     static_assert(TN::THREADS == kBatchThreads, "batched narrow tiles are 256 threads");
-    static_assert(2 * sizeof(float2) * TN::BUF <= kBatchLds, "batched LDS budget");
+    static_assert(2 * sizeof(float2) * TN::BUF <= level_lds(CLS), "batched LDS budget");
     if (d.ev) {
       if constexpr (SET == LS_SPEC) {
         if (d.col) run_kind_spec<N, true, 1>(d.a, d.kind, tile, lds, red);
@@ -264,26 +277,36 @@ __device__ __forceinline__ void run_len(const BatchDesc& d, int tile, float2* ld
   }
 }
 
-// Three workgroups per CU (the LDS budget's limit): the compiler fits the
-// kernel in 168 VGPRs (a small spill on the twelve-element lengths) instead of
-// 197, which held it to two; measured 71 -> 62.5 ms on 256 uneven problems.
-template <int SET>
-__global__ void __launch_bounds__(kBatchThreads, 3) batched_level_kernel(const BatchItem* __restrict__ items,
-                                                                      const BatchDesc* __restrict__ descs) {
+// The power-of-two class compiles only those lengths; the twelve-element
+// class compiles every length, since its problems may have a power-of-two
+// length on their other axis.
+template <int N, int SET, int CLS>
+__device__ __forceinline__ void run_len_if(const BatchDesc& d, int tile, float2* lds, float* red) {
+  if constexpr (CLS != LEN_POW2 || !twelve_len(N)) run_len<N, SET, CLS>(d, tile, lds, red);
+}
+
+// All lengths: three workgroups per CU (the LDS budget's limit); the compiler
+// fits the kernel in 168 VGPRs (a small spill on the twelve-element lengths)
+// instead of 197, which held it to two (71 -> 62.5 ms on 256 uneven
+// problems).  The power-of-two class: four workgroups per CU, 124 VGPRs, no
+// spill; the twelve-element class: two, no spill.
+template <int SET, int CLS>
+__global__ void __launch_bounds__(kBatchThreads, level_groups(CLS))
+    batched_level_kernel(const BatchItem* __restrict__ items, const BatchDesc* __restrict__ descs) {
   extern __shared__ float2 lds[];
   __shared__ float red[kBatchThreads];
   const BatchItem it = items[xcd_tile(blockIdx.x, gridDim.x)];
   const BatchDesc& d = descs[it.desc];
   switch (d.N) {
-    case 16: run_len<16, SET>(d, it.tile, lds, red); break;
-    case 32: run_len<32, SET>(d, it.tile, lds, red); break;
-    case 64: run_len<64, SET>(d, it.tile, lds, red); break;
-    case 96: run_len<96, SET>(d, it.tile, lds, red); break;
-    case 128: run_len<128, SET>(d, it.tile, lds, red); break;
-    case 192: run_len<192, SET>(d, it.tile, lds, red); break;
-    case 256: run_len<256, SET>(d, it.tile, lds, red); break;
-    case 384: run_len<384, SET>(d, it.tile, lds, red); break;
-    case 512: run_len<512, SET>(d, it.tile, lds, red); break;
+    case 16: run_len_if<16, SET, CLS>(d, it.tile, lds, red); break;
+    case 32: run_len_if<32, SET, CLS>(d, it.tile, lds, red); break;
+    case 64: run_len_if<64, SET, CLS>(d, it.tile, lds, red); break;
+    case 96: run_len_if<96, SET, CLS>(d, it.tile, lds, red); break;
+    case 128: run_len_if<128, SET, CLS>(d, it.tile, lds, red); break;
+    case 192: run_len_if<192, SET, CLS>(d, it.tile, lds, red); break;
+    case 256: run_len_if<256, SET, CLS>(d, it.tile, lds, red); break;
+    case 384: run_len_if<384, SET, CLS>(d, it.tile, lds, red); break;
+    case 512: run_len_if<512, SET, CLS>(d, it.tile, lds, red); break;
     default: break;
   }
 }
@@ -324,21 +347,39 @@ hipError_t launch_level_set0(dim3 grid, hipStream_t s, const void* items, const 
 hipError_t launch_level_set1(dim3 grid, hipStream_t s, const void* items, const void* descs);
 hipError_t launch_level_set2(dim3 grid, hipStream_t s, const void* items, const void* descs);
 hipError_t launch_level_set3(dim3 grid, hipStream_t s, const void* items, const void* descs);
+// the GD set by length class (SR_LEVEL_SET = 0 built with SR_LEVEL_CLS = 1 / 2)
+hipError_t launch_level_gd_pow2(dim3 grid, hipStream_t s, const void* items, const void* descs);
+hipError_t launch_level_gd_twelve(dim3 grid, hipStream_t s, const void* items, const void* descs);
 
 #if defined(SR_LEVEL_SET)
+#if !defined(SR_LEVEL_CLS) || SR_LEVEL_CLS == 0
 #define SR_LAUNCHER_NAME(k) launch_level_set##k
 #define SR_LAUNCHER(k) SR_LAUNCHER_NAME(k)
 hipError_t SR_LAUNCHER(SR_LEVEL_SET)(dim3 grid, hipStream_t s, const void* items, const void* descs) {
-  hipLaunchKernelGGL(batched_level_kernel<SR_LEVEL_SET>, grid, dim3(kBatchThreads), kBatchLds, s,
+  hipLaunchKernelGGL((batched_level_kernel<SR_LEVEL_SET, LEN_ALL>), grid, dim3(kBatchThreads), level_lds(LEN_ALL), s,
                      (const BatchItem*)items, (const BatchDesc*)descs);
   return hipGetLastError();
 }
+#elif SR_LEVEL_CLS == 1
+hipError_t launch_level_gd_pow2(dim3 grid, hipStream_t s, const void* items, const void* descs) {
+  hipLaunchKernelGGL((batched_level_kernel<LS_GD, LEN_POW2>), grid, dim3(kBatchThreads), level_lds(LEN_POW2), s,
+                     (const BatchItem*)items, (const BatchDesc*)descs);
+  return hipGetLastError();
+}
+#else
+hipError_t launch_level_gd_twelve(dim3 grid, hipStream_t s, const void* items, const void* descs) {
+  hipLaunchKernelGGL((batched_level_kernel<LS_GD, LEN_TWELVE>), grid, dim3(kBatchThreads), level_lds(LEN_TWELVE), s,
+                     (const BatchItem*)items, (const BatchDesc*)descs);
+  return hipGetLastError();
+}
+#endif
 }  // namespace sr
 #else
 
 // Level lists of one recorded pass sequence (device descriptors and items).
 struct LevelSet {
   int set = LS_GD;  // pass set (which instantiation of the level kernel)
+  int cls = LEN_ALL;  // length class (GD set only)
   BatchDesc* d_descs = nullptr;
   BatchItem* d_items = nullptr;
   std::vector<int> level_off, level_cnt;  // item ranges per level
@@ -354,7 +395,13 @@ struct LevelSet {
 // next first pass), and the final iteration (plain update).
 struct BatchState {
   std::string key;
-  LevelSet first, steady, last;
+  LevelSet first, steady, last;  // every problem (loss traces)
+  // without a trace: the same per length class of the problem (0: both
+  // axes a power of two, 1: an axis of twelve-element length), each on its
+  // own instantiation and stream
+  LevelSet cfirst[2], csteady[2], clast[2];
+  bool has[2] = {false, false};
+  bool split = false;
   // with a loss trace: the turnaround of each problem writes its loss
   // partials (nparts of them, at its own offset), summed per problem
   bool trace = false;
@@ -477,7 +524,8 @@ static sr_status build_levels(sr_plan_s* p, const std::vector<std::vector<PassRe
 // loss partials of a trace.
 static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const float* eta, bool trace,
                                BatchState** out) {
-  std::string key = std::to_string((uintptr_t)y) + ":" + std::to_string((uintptr_t)x) + (trace ? ":tr" : "");
+  std::string key = std::to_string((uintptr_t)y) + ":" + std::to_string((uintptr_t)x) + (trace ? ":tr" : "") +
+                    (fused2d_enabled(false) ? ":r" : "");
   for (size_t i = 0; i < p->geo.size(); ++i) {
     uint32_t u;
     std::memcpy(&u, &eta[i], 4);
@@ -488,6 +536,8 @@ static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const fl
     *out = st;
     return SR_OK;
   }
+  // graphs captured over the old lists (keys "batch:...", "batch0:...", "batch1:...")
+  if (sr_status dg = drop_graphs(p, "batch"); dg != SR_OK) return dg;
   if (sr_status lb = level_bufs(p); lb != SR_OK) return lb;
   if (st == nullptr) {
     st = new BatchState();
@@ -551,9 +601,37 @@ static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const fl
   p->bufA = saveA;
   p->bufB = saveB;
   if (status != SR_OK) return status;
-  if ((status = build_levels(p, rec_first, st->first)) != SR_OK) return status;
-  if ((status = build_levels(p, rec_steady, st->steady)) != SR_OK) return status;
-  if ((status = build_levels(p, rec_last, st->last)) != SR_OK) return status;
+  st->split = !trace && !batched_any_resident(p);  // (the aux stream serves the LDS-resident solver otherwise)
+  if (st->split) {
+    std::vector<std::vector<PassRecord>> cf[2], cs[2], cl[2];
+    for (int c = 0; c < 2; ++c) {
+      cf[c].assign(np, {});
+      cs[c].assign(np, {});
+      cl[c].assign(np, {});
+      st->has[c] = false;
+    }
+    for (size_t i = 0; i < np; ++i) {
+      if (rec_first[i].empty()) continue;
+      const Geo& g = p->geo[i];
+      const int c = (twelve_len(g.M1) || twelve_len(g.M2)) ? 1 : 0;
+      cf[c][i] = std::move(rec_first[i]);
+      cs[c][i] = std::move(rec_steady[i]);
+      cl[c][i] = std::move(rec_last[i]);
+      st->has[c] = true;
+    }
+    for (int c = 0; c < 2; ++c) {
+      if (!st->has[c]) continue;
+      const int cls = c == 0 ? LEN_POW2 : LEN_TWELVE;
+      st->cfirst[c].cls = st->csteady[c].cls = st->clast[c].cls = cls;
+      if ((status = build_levels(p, cf[c], st->cfirst[c])) != SR_OK) return status;
+      if ((status = build_levels(p, cs[c], st->csteady[c])) != SR_OK) return status;
+      if ((status = build_levels(p, cl[c], st->clast[c])) != SR_OK) return status;
+    }
+  } else {
+    if ((status = build_levels(p, rec_first, st->first)) != SR_OK) return status;
+    if ((status = build_levels(p, rec_steady, st->steady)) != SR_OK) return status;
+    if ((status = build_levels(p, rec_last, st->last)) != SR_OK) return status;
+  }
   st->key = key;
   *out = st;
   return SR_OK;
@@ -565,7 +643,9 @@ static sr_status run_levels(sr_plan_s* p, const LevelSet& ls) {
     const dim3 grid(ls.level_cnt[q]);
     const BatchItem* items = ls.d_items + ls.level_off[q];
     hipError_t e;
-    if (ls.set == LS_SPEC) e = launch_level_set1(grid, p->stream, items, ls.d_descs);
+    if (ls.set == LS_GD && ls.cls == LEN_POW2) e = launch_level_gd_pow2(grid, p->stream, items, ls.d_descs);
+    else if (ls.set == LS_GD && ls.cls == LEN_TWELVE) e = launch_level_gd_twelve(grid, p->stream, items, ls.d_descs);
+    else if (ls.set == LS_SPEC) e = launch_level_set1(grid, p->stream, items, ls.d_descs);
     else if (ls.set == LS_OP) e = launch_level_set2(grid, p->stream, items, ls.d_descs);
     else if (ls.set == LS_VJP) e = launch_level_set3(grid, p->stream, items, ls.d_descs);
     else e = launch_level_set0(grid, p->stream, items, ls.d_descs);
@@ -687,20 +767,18 @@ sr_status batched_gd(sr_plan_s* p, const float* y, float2* x, int iters, const f
 }
 
 // GD of the problems that are not LDS-resident, one launch per pass level.
-static sr_status batched_levels_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta) {
-  BatchState* st = nullptr;
-  sr_status s = batch_prepare(p, y, x, eta, false, &st);
-  if (s != SR_OK) return s;
+// One solve on one group of level sets, on the plan's current stream.
+static sr_status levels_gd_run(sr_plan_s* p, const LevelSet& first, const LevelSet& steady, const LevelSet& last,
+                               int iters, const std::string& gkey) {
   constexpr int kChunk = 50;
-  s = run_levels(p, st->first);
+  sr_status s = run_levels(p, first);
   if (s != SR_OK) return s;
   int it = 0;
   if (iters - 1 >= kChunk && graphs_enabled(p)) {
-    const std::string gkey = "batch:" + st->key;
     for (; it + kChunk <= iters - 1; it += kChunk) {
       s = launch_captured(p, gkey, [&]() -> sr_status {
         for (int c = 0; c < kChunk; ++c) {
-          sr_status q = run_levels(p, st->steady);
+          sr_status q = run_levels(p, steady);
           if (q != SR_OK) return q;
         }
         return SR_OK;
@@ -709,10 +787,34 @@ static sr_status batched_levels_gd(sr_plan_s* p, const float* y, float2* x, int 
     }
   }
   for (; it < iters - 1; ++it) {
-    s = run_levels(p, st->steady);
+    s = run_levels(p, steady);
     if (s != SR_OK) return s;
   }
-  return run_levels(p, st->last);
+  return run_levels(p, last);
+}
+
+static sr_status batched_levels_gd(sr_plan_s* p, const float* y, float2* x, int iters, const float* eta) {
+  BatchState* st = nullptr;
+  sr_status s = batch_prepare(p, y, x, eta, false, &st);
+  if (s != SR_OK) return s;
+  if (!st->split) return levels_gd_run(p, st->first, st->steady, st->last, iters, "batch:" + st->key);
+  // the two length classes are independent problems: the twelve-element one
+  // on the auxiliary stream beside the other
+  const bool two = st->has[0] && st->has[1];
+  if (two && (s = aux_fork(p)) != SR_OK) return s;
+  for (int c = 0; c < 2 && s == SR_OK; ++c) {
+    if (!st->has[c]) continue;
+    hipStream_t own = p->stream;
+    if (two && c == 1) p->stream = p->aux_stream;
+    s = levels_gd_run(p, st->cfirst[c], st->csteady[c], st->clast[c], iters,
+                      "batch" + std::to_string(c) + ":" + st->key);
+    p->stream = own;
+  }
+  if (two) {
+    const sr_status j = aux_join(p);
+    if (s == SR_OK) s = j;
+  }
+  return s;
 }
 
 // GD with a loss trace (no LDS-resident problems: the caller checks): the
@@ -844,11 +946,13 @@ static sr_status spec_prepare(sr_plan_s* p, const std::vector<int>& which, const
     key += ":" + std::to_string(u);
   }
   for (int i : which) key += "," + std::to_string(i);
+  if (fused2d_enabled(false)) key += ":r";
   SpecBatchState* st = p->spec_batch;
   if (st != nullptr && st->key == key) {
     *out = st;
     return SR_OK;
   }
+  if (sr_status dg = drop_graphs(p, "bspec:"); dg != SR_OK) return dg;  // captured over the old lists
   const size_t np = p->geo.size();
   if (sr_status lb = level_bufs(p); lb != SR_OK) return lb;
   if (st == nullptr) {

@@ -244,6 +244,22 @@ inline bool graphs_enabled(const sr_plan_s* p) {
   return e == nullptr || std::atoi(e) != 0;
 }
 
+// Destroy the captured graphs whose key starts with `prefix`, once the stream
+// has drained: their kernels take device lists that the caller is about to
+// free and rebuild, and a later call under the same key must capture anew.
+inline sr_status drop_graphs(sr_plan_s* p, const std::string& prefix) {
+  auto hit = [&](const std::pair<std::string, hipGraphExec_t>& g) { return g.first.compare(0, prefix.size(), prefix) == 0; };
+  if (std::none_of(p->graphs.begin(), p->graphs.end(), hit)) return SR_OK;
+  if (hipError_t e = hipStreamSynchronize(p->stream); e != hipSuccess) return hip_fail(e, "stream wait");
+  auto keep = std::remove_if(p->graphs.begin(), p->graphs.end(), [&](const auto& g) {
+    if (!hit(g)) return false;
+    (void)hipGraphExecDestroy(g.second);
+    return true;
+  });
+  p->graphs.erase(keep, p->graphs.end());
+  return SR_OK;
+}
+
 template <class F>
 sr_status launch_captured(sr_plan_s* p, const std::string& key, F&& enqueue) {
   for (auto it = p->graphs.begin(); it != p->graphs.end(); ++it) {

@@ -77,6 +77,66 @@ def test_batched_matches_loop_and_oracle(gpu, monkeypatch):
         assert aligned(xh[plan.x_off[i]:plan.x_off[i + 1]].reshape(p["n_shape"]), xr) <= 1e-4
 
 
+def test_batched_graphs_follow_rebuilt_lists(gpu):
+    """The level lists are rebuilt whenever a call's (y, x, eta) differ from
+    the previous call's, and the graphs captured over the old lists go with
+    them: returning to an earlier (y, x) captures afresh and reproduces the
+    first call bit for bit, for GD (Eq. (2)) and for the power iteration
+    (Eq. (3)), each past one captured chunk."""
+    import torch
+    import paper_2409_05734_amd as srpr
+    plan, probs, y, x0, eta = _setup(12, 13, gpu)
+    srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_BATCHED)
+    x0d = to_dev(x0, gpu)
+    y_b = y.clone()  # same values, another address
+    x_a, x_b = x0d.clone(), x0d.clone()
+    srpr.sr_gd_solve(plan, y, x_a, 60, eta)
+    first = x_a.clone()
+    srpr.sr_gd_solve(plan, y_b, x_b, 60, eta)
+    srpr.sr_gd_solve(plan, y, x_b, 60, 0.5 * eta)
+    x_a.copy_(x0d)
+    srpr.sr_gd_solve(plan, y, x_a, 60, eta)
+    srpr.sr_plan_sync(plan)
+    assert torch.equal(x_a, first)
+    out_a, out_b = torch.empty_like(x0d), torch.empty_like(x0d)
+    srpr.sr_spectral_init(plan, y, x0d, 60, -1.0, out_a)
+    first = out_a.clone()
+    srpr.sr_spectral_init(plan, y_b, x0d, 60, -1.0, out_b)
+    srpr.sr_spectral_init(plan, y, x0d, 60, -1.0, out_a)
+    srpr.sr_plan_sync(plan)
+    assert torch.equal(out_a, first)
+
+
+def test_batched_rectangular_mixed_lengths(gpu):
+    """Rectangular grids whose two axes fall in different length families
+    (twelve-element 96 / 192 beside powers of two), with square ones of each
+    family, in one batched plan: GD past one captured chunk (Eq. (2)) against
+    the oracle, every problem."""
+    import paper_2409_05734_amd as srpr
+    rng = np.random.default_rng(17)
+    specs = [((40, 30), (96, 64), 3), ((9, 80), (16, 96), 2), ((50, 90), (64, 192), 1), ((60, 40), (192, 128), 2),
+             ((48, 48), (96, 96), 2), ((30, 30), (64, 64), 2), ((100, 60), (128, 128), 3), ((20, 20), (32, 32), 1)]
+    cases = []
+    for n_shape, m_shape, L in specs:
+        th = sr_inputs.phase_masks(rng, L, m_shape)
+        xs = sr_inputs.complex_gaussian(rng, n_shape)
+        op = oracle.StructuredOperator(th, n_shape)
+        y = oracle.measurements(xs, th)
+        x0 = (xs + 0.5 * sr_inputs.complex_gaussian(rng, n_shape)).astype(np.complex64)
+        cases.append((th, op, y, x0, np.float32(oracle.default_step(op, y, 0.2))))
+    plan = srpr.Plan([srpr.Problem(*s) for s in specs], np.concatenate([c[0].ravel() for c in cases]))
+    srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_BATCHED)
+    x = to_dev(np.concatenate([c[3].ravel() for c in cases]), gpu)
+    yd = to_dev(np.concatenate([c[2].ravel() for c in cases]).astype(np.float32), gpu)
+    srpr.sr_gd_solve(plan, yd, x, 60, np.array([c[4] for c in cases], np.float32))
+    srpr.sr_plan_sync(plan)
+    xh = to_host(x)
+    for i, ((n_shape, m_shape, L), (th, op, y, x0, eta)) in enumerate(zip(specs, cases)):
+        xr = oracle.gd_solve(op, y.astype(np.float32).astype(np.float64), x0, 60, float(eta))
+        xi = xh[plan.x_off[i]:plan.x_off[i + 1]].reshape(n_shape)
+        assert aligned(xi, xr) <= 1e-4, (n_shape, m_shape, L)
+
+
 def test_batched_matches_tuned_loop(gpu):
     """Against the loop on the tuner's tile shapes (which may use the narrow
     thread shape, a different FFT factorisation): agreement to rounding over
