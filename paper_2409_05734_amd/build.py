@@ -61,9 +61,9 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     for k in range(4):  # the level kernel, one pass set per translation unit
         tasks.append((os.path.join(CSRC, "batched.hip"), os.path.join(BUILD, f"batched_set{k}.o"),
                       [f"-DSR_LEVEL_SET={k}"]))
-    for c in (1, 2):  # the GD set's two length classes
-        tasks.append((os.path.join(CSRC, "batched.hip"), os.path.join(BUILD, f"batched_gd_cls{c}.o"),
-                      ["-DSR_LEVEL_SET=0", f"-DSR_LEVEL_CLS={c}"]))
+    for k, c in ((0, 1), (0, 2), (1, 1), (1, 2)):  # the GD and spectral sets' two length classes
+        tasks.append((os.path.join(CSRC, "batched.hip"), os.path.join(BUILD, f"batched_set{k}_cls{c}.o"),
+                      [f"-DSR_LEVEL_SET={k}", f"-DSR_LEVEL_CLS={c}"]))
     jobs = jobs or min(16, os.cpu_count() or 4)
     failures = []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
@@ -109,7 +109,7 @@ def build_host_check(jobs: int | None = None) -> str:
                   SAN_FLAGS + ["-x", "hip"]))
     plain = [os.path.join(BUILD, f"passes_{n}_{pset}.o") for n in FFT_LENGTHS for pset in (0, 1)]
     plain += [os.path.join(BUILD, f"batched_set{k}.o") for k in range(4)]
-    plain += [os.path.join(BUILD, f"batched_gd_cls{c}.o") for c in (1, 2)]
+    plain += [os.path.join(BUILD, f"batched_set{k}_cls{c}.o") for k, c in ((0, 1), (0, 2), (1, 1), (1, 2))]
     missing = [o for o in plain if not os.path.exists(o)]
     if missing:
         raise RuntimeError("run build() first: missing " + ", ".join(missing[:3]))

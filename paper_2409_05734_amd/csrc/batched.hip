@@ -347,9 +347,12 @@ hipError_t launch_level_set0(dim3 grid, hipStream_t s, const void* items, const 
 hipError_t launch_level_set1(dim3 grid, hipStream_t s, const void* items, const void* descs);
 hipError_t launch_level_set2(dim3 grid, hipStream_t s, const void* items, const void* descs);
 hipError_t launch_level_set3(dim3 grid, hipStream_t s, const void* items, const void* descs);
-// the GD set by length class (SR_LEVEL_SET = 0 built with SR_LEVEL_CLS = 1 / 2)
-hipError_t launch_level_gd_pow2(dim3 grid, hipStream_t s, const void* items, const void* descs);
-hipError_t launch_level_gd_twelve(dim3 grid, hipStream_t s, const void* items, const void* descs);
+// the GD and spectral sets by length class (SR_LEVEL_SET = 0 / 1 built with
+// SR_LEVEL_CLS = 1 / 2): launch_level_s<set>_c<class>
+hipError_t launch_level_s0_c1(dim3 grid, hipStream_t s, const void* items, const void* descs);
+hipError_t launch_level_s0_c2(dim3 grid, hipStream_t s, const void* items, const void* descs);
+hipError_t launch_level_s1_c1(dim3 grid, hipStream_t s, const void* items, const void* descs);
+hipError_t launch_level_s1_c2(dim3 grid, hipStream_t s, const void* items, const void* descs);
 
 #if defined(SR_LEVEL_SET)
 #if !defined(SR_LEVEL_CLS) || SR_LEVEL_CLS == 0
@@ -360,16 +363,12 @@ hipError_t SR_LAUNCHER(SR_LEVEL_SET)(dim3 grid, hipStream_t s, const void* items
                      (const BatchItem*)items, (const BatchDesc*)descs);
   return hipGetLastError();
 }
-#elif SR_LEVEL_CLS == 1
-hipError_t launch_level_gd_pow2(dim3 grid, hipStream_t s, const void* items, const void* descs) {
-  hipLaunchKernelGGL((batched_level_kernel<LS_GD, LEN_POW2>), grid, dim3(kBatchThreads), level_lds(LEN_POW2), s,
-                     (const BatchItem*)items, (const BatchDesc*)descs);
-  return hipGetLastError();
-}
 #else
-hipError_t launch_level_gd_twelve(dim3 grid, hipStream_t s, const void* items, const void* descs) {
-  hipLaunchKernelGGL((batched_level_kernel<LS_GD, LEN_TWELVE>), grid, dim3(kBatchThreads), level_lds(LEN_TWELVE), s,
-                     (const BatchItem*)items, (const BatchDesc*)descs);
+#define SR_CLS_LAUNCHER_NAME(k, c) launch_level_s##k##_c##c
+#define SR_CLS_LAUNCHER(k, c) SR_CLS_LAUNCHER_NAME(k, c)
+hipError_t SR_CLS_LAUNCHER(SR_LEVEL_SET, SR_LEVEL_CLS)(dim3 grid, hipStream_t s, const void* items, const void* descs) {
+  hipLaunchKernelGGL((batched_level_kernel<SR_LEVEL_SET, SR_LEVEL_CLS>), grid, dim3(kBatchThreads),
+                     level_lds(SR_LEVEL_CLS), s, (const BatchItem*)items, (const BatchDesc*)descs);
   return hipGetLastError();
 }
 #endif
@@ -583,7 +582,10 @@ static sr_status batch_prepare(sr_plan_s* p, const float* y, float2* x, const fl
   sr_status status = SR_OK;
   for (size_t i = 0; i < np && status == SR_OK; ++i) {
     const Geo& g = p->geo[i];
-    if (lds_resident(g)) continue;  // solved by the LDS-resident kernel
+    // solved by the LDS-resident kernel, or not by the level kernel at all
+    // (the level tuner comes here for any plan with level problems; only
+    // those have private buffers)
+    if (lds_resident(g) || !batch_level_capable(g)) continue;
     p->bufA = p->lvl_bufs + p->lvl_off[i];  // each problem's private ping-pong buffers
     p->bufB = p->lvl_bufs + p->lvl_off[i] + g.mg;
     const float* yi = y + p->yoff[i];
@@ -643,8 +645,10 @@ static sr_status run_levels(sr_plan_s* p, const LevelSet& ls) {
     const dim3 grid(ls.level_cnt[q]);
     const BatchItem* items = ls.d_items + ls.level_off[q];
     hipError_t e;
-    if (ls.set == LS_GD && ls.cls == LEN_POW2) e = launch_level_gd_pow2(grid, p->stream, items, ls.d_descs);
-    else if (ls.set == LS_GD && ls.cls == LEN_TWELVE) e = launch_level_gd_twelve(grid, p->stream, items, ls.d_descs);
+    if (ls.set == LS_GD && ls.cls == LEN_POW2) e = launch_level_s0_c1(grid, p->stream, items, ls.d_descs);
+    else if (ls.set == LS_GD && ls.cls == LEN_TWELVE) e = launch_level_s0_c2(grid, p->stream, items, ls.d_descs);
+    else if (ls.set == LS_SPEC && ls.cls == LEN_POW2) e = launch_level_s1_c1(grid, p->stream, items, ls.d_descs);
+    else if (ls.set == LS_SPEC && ls.cls == LEN_TWELVE) e = launch_level_s1_c2(grid, p->stream, items, ls.d_descs);
     else if (ls.set == LS_SPEC) e = launch_level_set1(grid, p->stream, items, ls.d_descs);
     else if (ls.set == LS_OP) e = launch_level_set2(grid, p->stream, items, ls.d_descs);
     else if (ls.set == LS_VJP) e = launch_level_set3(grid, p->stream, items, ls.d_descs);
@@ -799,8 +803,10 @@ static sr_status batched_levels_gd(sr_plan_s* p, const float* y, float2* x, int 
   if (s != SR_OK) return s;
   if (!st->split) return levels_gd_run(p, st->first, st->steady, st->last, iters, "batch:" + st->key);
   // the two length classes are independent problems: the twelve-element one
-  // on the auxiliary stream beside the other
-  const bool two = st->has[0] && st->has[1];
+  // on the auxiliary stream beside the other (SR_BATCH_STREAMS=1: both on
+  // the plan's stream, one after the other)
+  const char* ns = std::getenv("SR_BATCH_STREAMS");
+  const bool two = st->has[0] && st->has[1] && (ns == nullptr || std::atoi(ns) != 1);
   if (two && (s = aux_fork(p)) != SR_OK) return s;
   for (int c = 0; c < 2 && s == SR_OK; ++c) {
     if (!st->has[c]) continue;
@@ -922,14 +928,118 @@ sr_status batched_operator(sr_plan_s* p, const std::vector<int>& which, bool adj
 sr_status spec_steady_public(sr_plan_s* p, const Geo& g, const float* y, float2* u, float lam, float inv_mc,
                              const double* ysum, const float* part_in, int npart_in, float* part_out, bool last);
 
+// Set-up and finish of a batched power iteration, one launch each for all
+// problems (instead of a few small launches per problem).  Stage 1 reduces
+// sum(y_i) and ||v0_i||^2 in the chunks, order and tree of the
+// single-problem reductions (so the sums come out the same), copying v0_i to
+// x_i on the way; stage 2 sums each problem's stage-1 partials in index
+// order.  The finish scales each x_i to sqrt(sum(y_i) / (m c)) u / ||u||
+// (Eq. (4)).
+struct SpecProb {
+  long long yoff, xoff, m, n;  // element offsets and lengths of y_i and x_i
+  long long cy, cx;            // stage-1 chunk lengths
+  int gy, gx;                  // stage-1 workgroups
+  int wy, wx;                  // offsets of the stage-1 partials in the workspace
+  int part_off, nq;            // the problem's two partial sets: offset, partials per set
+  int idx;                     // problem index in the plan
+  float inv_mc;
+};
+
+namespace {
+constexpr int kSpecRed = 256;
+
+__device__ double spec_block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = kSpecRed / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// grid (max workgroups, problems, 2): z = 0 reduces y_i, z = 1 copies v0_i
+// to x_i and reduces its squared magnitudes
+__global__ void __launch_bounds__(kSpecRed) spec_setup_stage1(const SpecProb* __restrict__ d, const float* __restrict__ y,
+                                                              const float2* __restrict__ v0, float2* __restrict__ x,
+                                                              double* __restrict__ ws) {
+  __shared__ double red[kSpecRed];
+  const SpecProb q = d[blockIdx.y];
+  const bool isx = blockIdx.z == 1;
+  if ((int)blockIdx.x >= (isx ? q.gx : q.gy)) return;  // (the whole workgroup)
+  double acc = 0.0;
+  if (!isx) {
+    const long long lo = blockIdx.x * q.cy, hi = min(q.m, lo + q.cy);
+    for (long long i = lo + threadIdx.x; i < hi; i += kSpecRed) acc += (double)y[q.yoff + i];
+  } else {
+    const long long lo = blockIdx.x * q.cx, hi = min(q.n, lo + q.cx);
+    for (long long i = lo + threadIdx.x; i < hi; i += kSpecRed) {
+      const float2 v = v0[q.xoff + i];
+      x[q.xoff + i] = v;
+      acc += (double)v.x * v.x + (double)v.y * v.y;
+    }
+  }
+  const double s = spec_block_sum(acc, red);
+  if (threadIdx.x == 0) ws[(isx ? q.wx : q.wy) + blockIdx.x] = s;
+}
+
+// one thread per problem: sum(y_i) into ysum, ||u_0||^2 as the first
+// partial set's single partial
+__global__ void spec_setup_stage2(const SpecProb* __restrict__ d, int count, const double* __restrict__ ws,
+                                  double* ysum, float* parts) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= count) return;
+  const SpecProb q = d[j];
+  double a = 0.0, b = 0.0;
+  for (int k = 0; k < q.gy; ++k) a += ws[q.wy + k];
+  for (int k = 0; k < q.gx; ++k) b += ws[q.wx + k];
+  ysum[q.idx] = a;
+  parts[q.part_off] = (float)b;
+}
+
+// grid (workgroups, problems): after `iters` iterations the estimate's
+// squared norm is in partial set iters & 1 (a single partial after none)
+__global__ void spec_finish(const SpecProb* __restrict__ d, float2* x, const float* __restrict__ parts,
+                            const double* __restrict__ ysum, int iters, unsigned* nf) {
+  const SpecProb q = d[blockIdx.y];
+  const float* P = parts + q.part_off + ((iters & 1) ? max(q.nq, 1) : 0);
+  const int np = iters == 0 ? 1 : q.nq;
+  double acc = 0.0;
+  for (int i = 0; i < np; ++i) acc += (double)P[i];
+  const float sc = (float)(sqrt(ysum[q.idx] * (double)q.inv_mc) / sqrt(acc));
+  bool bad = false;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < q.n; i += (long long)gridDim.x * blockDim.x) {
+    const float2 v = cscale(x[q.xoff + i], sc);
+    x[q.xoff + i] = v;
+    bad |= !finite2(v);
+  }
+  flag_nonfinite(nf, bad);
+}
+}  // namespace
+
+struct SpecSets {
+  LevelSet first, it0, it0_last, odd, odd_last, even, even_last;
+};
+
 struct SpecBatchState {
   std::string key;
   float* parts = nullptr;              // per problem of the plan: two partial sets
   std::vector<size_t> part_off;
   std::vector<int> nq;                 // partials per set (tiles of the last pass)
-  LevelSet first, it0, it0_last, odd, odd_last, even, even_last;
+  // the level sets: of every problem in cls[0] (split == false), or per
+  // length class of the problem (0: both axes a power of two, 1: an axis
+  // of twelve-element length), each on its own instantiation and stream
+  SpecSets cls[2];
+  bool has[2] = {false, false};
+  bool split = false;
+  SpecProb* d_prob = nullptr;          // the call's problems (set-up and finish)
+  double* ws = nullptr;                // their stage-1 partials
+  int nprob = 0, gmax = 1, fgroups = 1;
   ~SpecBatchState() {
     if (parts) (void)hipFree(parts);
+    if (d_prob) (void)hipFree(d_prob);
+    if (ws) (void)hipFree(ws);
   }
 };
 
@@ -952,7 +1062,7 @@ static sr_status spec_prepare(sr_plan_s* p, const std::vector<int>& which, const
     *out = st;
     return SR_OK;
   }
-  if (sr_status dg = drop_graphs(p, "bspec:"); dg != SR_OK) return dg;  // captured over the old lists
+  if (sr_status dg = drop_graphs(p, "bspec"); dg != SR_OK) return dg;  // captured over the old lists
   const size_t np = p->geo.size();
   if (sr_status lb = level_bufs(p); lb != SR_OK) return lb;
   if (st == nullptr) {
@@ -1012,44 +1122,89 @@ static sr_status spec_prepare(sr_plan_s* p, const std::vector<int>& which, const
   p->bufA = saveA;
   p->bufB = saveB;
   if (status != SR_OK) return status;
-  LevelSet* sets[7] = {&st->first, &st->it0, &st->it0_last, &st->odd, &st->odd_last, &st->even, &st->even_last};
+  // the call's problems for the set-up and finish launches
+  {
+    std::vector<SpecProb> dp;
+    int woff = 0;
+    st->gmax = 1;
+    st->fgroups = 1;
+    for (int i : which) {
+      const Geo& g = p->geo[i];
+      SpecProb q{};
+      q.yoff = p->yoff[i];
+      q.xoff = p->xoff[i];
+      q.m = g.m;
+      q.n = g.n;
+      red_shape(g.m, &q.gy, &q.cy);
+      red_shape(g.n, &q.gx, &q.cx);
+      q.wy = woff;
+      woff += q.gy;
+      q.wx = woff;
+      woff += q.gx;
+      q.part_off = (int)st->part_off[i];
+      q.nq = st->nq[i];
+      q.idx = i;
+      q.inv_mc = spec_inv_mc(g);
+      st->gmax = std::max({st->gmax, q.gy, q.gx});
+      st->fgroups = std::max(st->fgroups, (int)std::min<int64_t>((g.n + 255) / 256, 1024));
+      dp.push_back(q);
+    }
+    if (st->d_prob) (void)hipFree(st->d_prob);  // (build_levels above waited for the stream)
+    if (st->ws) (void)hipFree(st->ws);
+    st->d_prob = nullptr;
+    st->ws = nullptr;
+    st->nprob = (int)dp.size();
+    hipError_t e = hipMalloc(&st->d_prob, sizeof(SpecProb) * std::max<size_t>(dp.size(), 1));
+    if (e == hipSuccess) e = hipMalloc(&st->ws, sizeof(double) * std::max(woff, 1));
+    if (e != hipSuccess) return fail(SR_E_NOMEM, "batched power-iteration workspace allocation failed");
+    e = hipMemcpyAsync(st->d_prob, dp.data(), sizeof(SpecProb) * dp.size(), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);  // dp goes out of scope
+    if (e != hipSuccess) return hip_fail(e, "batched power-iteration descriptors");
+  }
+  // level sets, per length class where the auxiliary stream is free (the
+  // LDS-resident problems' solves use it otherwise)
   std::vector<std::vector<PassRecord>>* recsets[7] = {&r_first, &r_it0, &r_it0l, &r_odd, &r_oddl, &r_even, &r_evenl};
-  for (int k = 0; k < 7; ++k) {
-    sets[k]->set = LS_SPEC;
-    if ((status = build_levels(p, *recsets[k], *sets[k])) != SR_OK) return status;
+  st->split = !batched_any_resident(p);
+  st->has[0] = st->has[1] = false;
+  for (int c = 0; c < 2; ++c) {
+    std::vector<std::vector<PassRecord>> part[7];
+    for (int k = 0; k < 7; ++k) part[k].assign(np, {});
+    for (int i : which) {
+      const Geo& g = p->geo[i];
+      const int ci = st->split && (twelve_len(g.M1) || twelve_len(g.M2)) ? 1 : 0;
+      if (ci != c) continue;
+      for (int k = 0; k < 7; ++k) part[k][i] = (*recsets[k])[i];
+      st->has[c] = true;
+    }
+    if (!st->has[c]) continue;
+    SpecSets& S = st->cls[c];
+    LevelSet* sets[7] = {&S.first, &S.it0, &S.it0_last, &S.odd, &S.odd_last, &S.even, &S.even_last};
+    const int cls = !st->split ? LEN_ALL : c == 0 ? LEN_POW2 : LEN_TWELVE;
+    for (int k = 0; k < 7; ++k) {
+      sets[k]->set = LS_SPEC;
+      sets[k]->cls = cls;
+      if ((status = build_levels(p, part[k], *sets[k])) != SR_OK) return status;
+    }
   }
   st->key = key;
   *out = st;
   return SR_OK;
 }
 
-sr_status batched_spectral(sr_plan_s* p, const std::vector<int>& which, const float* y, const float2* v0, int iters,
-                           float lam, float2* x) {
-  if (sr_status t = batch_tune(p); t != SR_OK) return t;  // shapes fixed before any list is built
-  SpecBatchState* st = nullptr;
-  sr_status s = spec_prepare(p, which, y, x, lam, &st);
-  if (s != SR_OK) return s;
-  // sum(y), u_0 = v0 and its squared norm (one partial), per problem
-  for (int i : which) {
-    const Geo& g = p->geo[i];
-    if ((s = sum_floats(p, y + p->yoff[i], g.m, p->ysum + i)) != SR_OK) return s;
-    hipError_t e = hipMemcpyAsync(x + p->xoff[i], v0 + p->xoff[i], sizeof(float2) * g.n, hipMemcpyDeviceToDevice,
-                                  p->stream);
-    if (e != hipSuccess) return hip_fail(e, "start vector copy");
-    if ((s = norm2_partial(p, x + p->xoff[i], g.n, st->parts + st->part_off[i])) != SR_OK) return s;
-  }
+// The iterations of one group of level sets, on the plan's current stream.
+static sr_status spec_run_sets(sr_plan_s* p, const SpecSets& S, int iters, const std::string& gkey) {
+  sr_status s = SR_OK;
   if (iters > 0) {
-    if ((s = run_levels(p, st->first)) != SR_OK) return s;
-    if ((s = run_levels(p, iters == 1 ? st->it0_last : st->it0)) != SR_OK) return s;
+    if ((s = run_levels(p, S.first)) != SR_OK) return s;
+    if ((s = run_levels(p, iters == 1 ? S.it0_last : S.it0)) != SR_OK) return s;
   }
   int it = 1;
   constexpr int kChunk = 50;  // even: every chunk starts on an odd iteration
   if (iters - 1 - it >= kChunk && graphs_enabled(p)) {
-    const std::string gkey = "bspec:" + st->key;
     for (; it + kChunk <= iters - 1; it += kChunk) {
       s = launch_captured(p, gkey, [&]() -> sr_status {
         for (int c = 0; c < kChunk; ++c) {
-          sr_status q = run_levels(p, ((it + c) & 1) ? st->odd : st->even);
+          sr_status q = run_levels(p, ((it + c) & 1) ? S.odd : S.even);
           if (q != SR_OK) return q;
         }
         return SR_OK;
@@ -1059,17 +1214,42 @@ sr_status batched_spectral(sr_plan_s* p, const std::vector<int>& which, const fl
   }
   for (; it < iters; ++it) {
     const bool last = it == iters - 1;
-    const LevelSet& ls = (it & 1) ? (last ? st->odd_last : st->odd) : (last ? st->even_last : st->even);
+    const LevelSet& ls = (it & 1) ? (last ? S.odd_last : S.odd) : (last ? S.even_last : S.even);
     if ((s = run_levels(p, ls)) != SR_OK) return s;
   }
-  // x0 = sqrt(sum(y)/(m c)) u / ||u||
-  for (int i : which) {
-    const Geo& g = p->geo[i];
-    const float* P = st->parts + st->part_off[i] + ((iters & 1) ? std::max(st->nq[i], 1) : 0);
-    if ((s = final_scale(p, x + p->xoff[i], g.n, P, iters == 0 ? 1 : st->nq[i], p->ysum + i, spec_inv_mc(g))) !=
-        SR_OK)
-      return s;
+  return SR_OK;
+}
+
+sr_status batched_spectral(sr_plan_s* p, const std::vector<int>& which, const float* y, const float2* v0, int iters,
+                           float lam, float2* x) {
+  if (sr_status t = batch_tune(p); t != SR_OK) return t;  // shapes fixed before any list is built
+  SpecBatchState* st = nullptr;
+  sr_status s = spec_prepare(p, which, y, x, lam, &st);
+  if (s != SR_OK) return s;
+  // sum(y), u_0 = v0 and its squared norm (one partial), every problem
+  hipLaunchKernelGGL(spec_setup_stage1, dim3(st->gmax, st->nprob, 2), dim3(kSpecRed), 0, p->stream, st->d_prob, y, v0,
+                     x, st->ws);
+  hipLaunchKernelGGL(spec_setup_stage2, dim3((st->nprob + 63) / 64), dim3(64), 0, p->stream, st->d_prob, st->nprob,
+                     st->ws, p->ysum, st->parts);
+  if (hipError_t e = hipGetLastError(); e != hipSuccess) return hip_fail(e, "power-iteration set-up");
+  const bool two = st->split && st->has[0] && st->has[1];
+  if (two && (s = aux_fork(p)) != SR_OK) return s;
+  for (int c = 0; c < 2 && s == SR_OK; ++c) {
+    if (!st->has[c]) continue;
+    hipStream_t own = p->stream;
+    if (two && c == 1) p->stream = p->aux_stream;
+    s = spec_run_sets(p, st->cls[c], iters, "bspec" + std::to_string(c) + ":" + st->key);
+    p->stream = own;
   }
+  if (two) {
+    const sr_status j = aux_join(p);
+    if (s == SR_OK) s = j;
+  }
+  if (s != SR_OK) return s;
+  // x0 = sqrt(sum(y)/(m c)) u / ||u||
+  hipLaunchKernelGGL(spec_finish, dim3(st->fgroups, st->nprob), dim3(256), 0, p->stream, st->d_prob, x, st->parts,
+                     p->ysum, iters, p->sync + 2);
+  if (hipError_t e = hipGetLastError(); e != hipSuccess) return hip_fail(e, "power-iteration finish");
   return SR_OK;
 }
 

@@ -183,6 +183,9 @@ namespace sr {
 // set t into out[t * ostride])
 sr_status reduce_partials(sr_plan_s* p, const float* part, int n, float* out, int count = 1, int ostride = 0);
 // (count > 1: that many arrays of n elements end to end, each on its own)
+// stage-1 shape of the deterministic reductions of n elements: workgroups
+// and the contiguous chunk each one sums
+void red_shape(long long n, int* groups, long long* chunk);
 sr_status sum_floats(sr_plan_s* p, const float* y, int64_t n, double* out, int count = 1);
 sr_status norm2_partial(sr_plan_s* p, const float2* x, int64_t n, float* out, int count = 1);
 sr_status final_scale(sr_plan_s* p, float2* x, int64_t n, const float* part, int npart, const double* ysum,

@@ -1170,15 +1170,15 @@ sr_status sr_spectral_init(sr_plan p, const float* y, const void* v0, int32_t it
     const int P = stack_size(p, &ths);
     if (P > 1 && stack_spectral_ok(p, p->geo[0])) return spectral_stacked(p, P, ths, y, vs, iters, lambda, xs);
   }
-  // batched plans: problems whose grid fits one workgroup's LDS run their
-  // whole solve in the LDS-resident solver (by default), beside the level
-  // launches of the others
+  // batched plans: with SR_LDS_RESIDENT=1, problems whose grid fits one
+  // workgroup's LDS run their whole solve in the LDS-resident solver, beside
+  // the level launches of the others
   const bool want_batched = p->schedule == SR_SCHED_BATCHED || (p->schedule == SR_SCHED_AUTO && p->geo.size() >= 8);
   std::vector<char> resident(p->geo.size(), 0);
   std::vector<int> small;
   if (want_batched && p->geo.size() >= 2)
     for (size_t i = 0; i < p->geo.size(); ++i)
-      if (fused2d_enabled(true) && fused2d_supported(p->geo[i])) {
+      if (fused2d_enabled(false) && fused2d_supported(p->geo[i])) {
         resident[i] = 1;
         small.push_back((int)i);
       }

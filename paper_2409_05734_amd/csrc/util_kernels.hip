@@ -89,14 +89,6 @@ __global__ void reduce_stage2(const double* __restrict__ part, int g, double* ou
   }
 }
 
-void red_shape(long long n, int* groups, long long* chunk) {
-  long long g = (n + 4095) / 4096;
-  if (g > kRedGroups) g = kRedGroups;
-  if (g < 1) g = 1;
-  *groups = (int)g;
-  *chunk = (n + g - 1) / g;
-}
-
 // x *= sqrt(sum(y) * inv_mc) / ||x||, ||x||^2 = sum of the partials
 // (blockIdx.y: one of several problems, each with its x, partials and sum)
 // (the spectral estimate's last step: a NaN or Inf in it raises the flag nf)
@@ -135,6 +127,14 @@ __global__ void __launch_bounds__(kArgFloats) put_floats_kernel(float* dst, ArgF
 }
 
 }  // namespace
+
+void red_shape(long long n, int* groups, long long* chunk) {
+  long long g = (n + 4095) / 4096;
+  if (g > kRedGroups) g = kRedGroups;
+  if (g < 1) g = 1;
+  *groups = (int)g;
+  *chunk = (n + g - 1) / g;
+}
 
 sr_status put_floats(sr_plan_s* p, float* dst, const float* host, int count) {
   for (int lo = 0; lo < count; lo += kArgFloats) {

@@ -17,8 +17,8 @@ TOL_IT = 1e-4
 
 @pytest.fixture(autouse=True)
 def lds_resident_on(monkeypatch):
-    """The solver is opt-in for GD; every test here runs with it switched on
-    unless it says otherwise."""
+    """The solver is opt-in; every test here runs with it switched on unless
+    it says otherwise."""
     monkeypatch.setenv("SR_LDS_RESIDENT", "1")
 
 # every supported axis length, radix-8-first (padded rows) and 3-factor rows,
@@ -110,11 +110,11 @@ def test_lds_resident_is_deterministic(gpu):
     assert torch.equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("setting", [None, "0"])
-def test_spectral_default_and_off(gpu, monkeypatch, setting):
-    """Batched spectral solves take the LDS-resident solver by default (unset
-    switch) and run problem by problem with SR_LDS_RESIDENT=0; both against
-    the oracle."""
+@pytest.mark.parametrize("setting", [None, "1"])
+def test_spectral_default_and_on(gpu, monkeypatch, setting):
+    """Batched spectral solves run every problem on the level launches by
+    default (unset switch) and the small ones in the LDS-resident solver with
+    SR_LDS_RESIDENT=1; both against the oracle."""
     import torch
     import paper_2409_05734_amd as srpr
     if setting is None:
