@@ -8,8 +8,11 @@ namespace sr {
 
 hipError_t launch_pass(int N, int kind, bool col, int B, const PassArgs& a, hipStream_t s) {
   const bool rev = kind >= PK_MID_FWD_SAVE && kind <= PK_LAST_ADJ_GT;
-  // the reverse-mode passes are built for the default thread shape only
+  // the reverse-mode passes are built for the default thread shape only, and
+  // the wide shape for the column passes [F D F] and [F^H D^* F^H] only: the
+  // others run the length's default tile
   if (B <= 0 || (rev && (B & kNarrow))) B = default_tile(N, col);
+  if ((B & kWide) && (rev || !col || (kind != PK_MID_FWD && kind != PK_MID_ADJ))) B = default_tile(N, col);
   switch (N) {
 #define SR_CASE(n) \
   case n:          \
@@ -40,7 +43,7 @@ int default_tile(int N, bool col) {
   const int n = tile_options(N, col, opts, 16);
   int best = 1;
   for (int i = 0; i < n; ++i)
-    if (opts[i] < 256 && opts[i] > best) best = opts[i];  // widest double-buffered tile
+    if (opts[i] < kSingleBuffer && opts[i] > best) best = opts[i];  // widest double-buffered tile
   return n > 0 ? best : 1;
 }
 

@@ -17,6 +17,8 @@
 // stage's outputs land back in canonical order.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 namespace sr {
@@ -209,6 +211,43 @@ struct Dft<8, INV> {
   }
 };
 
+// 16 = 4 x 4: index n = 4 n1 + n2 in, k = k1 + 4 k2 out; four 4-point DFTs
+// over n1, the twiddles w16^(n2 k1), four 4-point DFTs over n2.
+template <bool INV>
+struct Dft<16, INV> {
+  __device__ __forceinline__ static void run(float2* u) {
+    const float c1 = 0.923879532511286756128183189396788933f;  // cos(pi/8)
+    const float s1 = 0.382683432365089771728459984030398866f;  // sin(pi/8)
+    const float h = 0.707106781186547524400844362104849039f;   // cos(pi/4)
+    float2 a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      float2 t[4] = {u[n2], u[4 + n2], u[8 + n2], u[12 + n2]};
+      Dft<4, INV>::run(t);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = t[k1];
+    }
+    // forward w16^j = (cos(2 pi j/16), -sin(2 pi j/16)); the inverse conjugates
+    auto tw = [](float2 v, float re, float im) { return INV ? cmulc(v, make_float2(re, im)) : cmul(v, make_float2(re, im)); };
+    a[1][1] = tw(a[1][1], c1, -s1);  // j = 1
+    a[1][2] = tw(a[1][2], h, -h);    // j = 2
+    a[1][3] = tw(a[1][3], s1, -c1);  // j = 3
+    a[2][1] = tw(a[2][1], h, -h);    // j = 2
+    a[2][2] = quarter<INV>(a[2][2]); // j = 4
+    a[2][3] = tw(a[2][3], -h, -h);   // j = 6
+    a[3][1] = tw(a[3][1], s1, -c1);  // j = 3
+    a[3][2] = tw(a[3][2], -h, -h);   // j = 6
+    a[3][3] = tw(a[3][3], -c1, s1);  // j = 9
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      float2 t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      Dft<4, INV>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) u[k1 + 4 * k2] = t[k2];
+    }
+  }
+};
+
 // ------------------------------------------------------------- radix lists
 template <int... Rs>
 struct RadixList {
@@ -257,6 +296,12 @@ template <> struct FftNarrow<128>  { using R = RadixList<4, 4, 4, 2>; };
 template <> struct FftNarrow<256>  { using R = RadixList<4, 4, 4, 4>; };
 template <> struct FftNarrow<512>  { using R = RadixList<4, 4, 4, 4, 2>; };
 template <> struct FftNarrow<1024> { using R = RadixList<4, 4, 4, 4, 4>; };
+// Wide thread shape: sixteen elements per thread with radix-16 stages, for
+// column tiles of eight 2048-point transforms in 1024 threads.
+template <int N> struct FftWide;
+template <> struct FftWide<2048> { using R = RadixList<16, 16, 8>; };
+template <int N> struct HasWide { static constexpr bool value = false; };
+template <> struct HasWide<2048> { static constexpr bool value = true; };
 template <int N> struct HasNarrow { static constexpr bool value = false; };
 template <> struct HasNarrow<64> { static constexpr bool value = true; };
 template <> struct HasNarrow<128> { static constexpr bool value = true; };
@@ -279,7 +324,8 @@ struct Tile {
   // One pad slot every R0 elements for radix-8- or radix-4-first lengths:
   // the stage-0 scatter (stride R0) would otherwise put lanes on one LDS
   // bank pair.
-  static constexpr int PADSHIFT = RL::values[0] == 8 ? 3 : (RL::values[0] == 4 && E_ == 4) ? 2 : 0;
+  static constexpr int PADSHIFT =
+      RL::values[0] == 16 ? 4 : RL::values[0] == 8 ? 3 : (RL::values[0] == 4 && E_ == 4) ? 2 : 0;
   static constexpr int NP = PADSHIFT ? N + (N >> PADSHIFT) : N;  // padded transform length
   static constexpr int LD = NP;               // row-mode LDS stride
   static constexpr int BUF = B * NP;          // complex elements per LDS buffer
@@ -302,14 +348,24 @@ struct Tile {
     return c;
   }
   static constexpr int NTW = tw_offset(RL::count) > 0 ? tw_offset(RL::count) : 1;
-  using Twiddles = float2[NTW];
+  // The sixteen-element shape reads each stage's twiddles from the table at
+  // that stage instead (its 29 would not fit in registers beside the data).
+  static constexpr bool LAZY_TW = E_ >= 16;
+  struct TableTw {
+    const float2* p;  // the table, offset to this thread
+  };
+  using Twiddles = typename std::conditional<LAZY_TW, TableTw, float2[NTW]>::type;
 
   // tw: this shape's thread-order twiddle table, entry i * TPT + t = twiddle
   // slot i of thread t (so each load instruction reads consecutive entries),
   // values exp(-2 pi i e/N) rounded from float64 (see for_each_twiddle).
   __device__ __forceinline__ static void load_twiddles(Twiddles& w, const float2* __restrict__ tw, int t) {
+    if constexpr (LAZY_TW) {
+      w.p = tw + t;
+    } else {
 #pragma unroll
-    for (int i = 0; i < NTW; ++i) w[i] = tw[i * TPT + t];
+      for (int i = 0; i < NTW; ++i) w[i] = tw[i * TPT + t];
+    }
   }
 
   // Host: calls f(slot, t, e) for every twiddle slot of every thread, where
@@ -370,6 +426,17 @@ struct Tile {
       constexpr int P = RL::span(S);
       constexpr int Q = E / R;  // butterflies per thread in this stage
       static_assert(E % R == 0, "radix must divide elements per thread");
+      // this stage's twiddles (from registers, or loaded from the table now,
+      // in flight across the exchange below)
+      constexpr int NS = S > 0 ? Q * (R - 1) : 1;
+      float2 ws[NS];
+      if constexpr (S > 0) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          if constexpr (LAZY_TW) ws[i] = w.p[(tw_offset(S) + i) * TPT];
+          else ws[i] = w[tw_offset(S) + i];
+        }
+      }
       if constexpr (S > 0) {
         // inputs of this stage: canonical positions in the buffer written last
         xsync();
@@ -387,7 +454,7 @@ struct Tile {
         if constexpr (S > 0) {
 #pragma unroll
           for (int r = 1; r < R; ++r) {
-            const float2 tf = w[tw_offset(S) + q * (R - 1) + (r - 1)];
+            const float2 tf = ws[q * (R - 1) + (r - 1)];
             u[r] = INV ? cmulc(u[r], tf) : cmul(u[r], tf);
           }
         }
@@ -413,7 +480,8 @@ struct Tile {
   }
 };
 
-// Tile of shape variant EV: 0 = the length's default shape, 1 = narrow.
+// Tile of shape variant EV: 0 = the length's default shape, 1 = narrow,
+// 2 = wide.
 template <int N, int B, bool COL, bool DB, int EV>
 struct TileSel {
   using type = Tile<N, B, COL, DB>;
@@ -421,6 +489,10 @@ struct TileSel {
 template <int N, int B, bool COL, bool DB>
 struct TileSel<N, B, COL, DB, 1> {
   using type = Tile<N, B, COL, DB, 4, typename FftNarrow<N>::R>;
+};
+template <int N, int B, bool COL, bool DB>
+struct TileSel<N, B, COL, DB, 2> {
+  using type = Tile<N, B, COL, DB, 16, typename FftWide<N>::R>;
 };
 template <int N, int B, bool COL, bool DB = true, int EV = 0>
 using TileV = typename TileSel<N, B, COL, DB, EV>::type;

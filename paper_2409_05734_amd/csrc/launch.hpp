@@ -59,12 +59,14 @@ struct TileCfg {
 
 // Tile widths available for a length and mode, and the default.  Column
 // widths with bit 256 set are single-buffered variants; widths with bit 512
-// set use the narrow shape (four elements per thread).
+// set use the narrow shape (four elements per thread), bit 1024 the wide
+// one (sixteen).
 int tile_options(int N, bool col, int* out, int max_out);
 int default_tile(int N, bool col);
 
 constexpr int kSingleBuffer = 256;
 constexpr int kNarrow = 512;
+constexpr int kWide = 1024;  // sixteen elements per thread, radix-16 stages (single-buffered columns)
 
 // Number of workgroups a pass of this length/mode/tile launches.
 int pass_groups(int N, bool col, int B, int ntr);

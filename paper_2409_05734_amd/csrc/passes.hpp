@@ -66,7 +66,7 @@ struct PassArgs {
   int tr_lo;          // grid coordinate of transform 0 on the other axis
   long long grid_ld;  // M2, row stride of the full measurement grid
   const float2* tw;   // thread-order twiddle table of the default thread shape
-  const float2* tw_n; // ... of the narrow thread shape (lengths that have one)
+  const float2* tw_n; // ... of the length's narrow or wide thread shape (where it has one)
   const float* th_pre;
   const float* th_mid;
   const float* th_post;
@@ -151,7 +151,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   constexpr bool POST_FWD = (POST == POST_GD_FWD || POST == POST_SPEC_FWD);
   constexpr bool POST_IS_GD = (POST == POST_GD || POST == POST_GD_FWD);
   constexpr bool POST_IS_SPEC = (POST == POST_SPEC || POST == POST_SPEC_FWD);
-  const int t = T::thread_t();
+  int t = T::thread_t();
   const int bl = T::thread_b();
   const int tb = tile * B + bl;  // transform index (over every problem of a stack)
   const bool active = tb < a.ntr;
@@ -160,7 +160,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
     sp = tb / a.ntr_p;
     b = tb - sp * a.ntr_p;
   }
-  const int gb = a.tr_lo + b;  // grid coordinate of this transform
+  int gb = a.tr_lo + b;  // grid coordinate of this transform
   const int gld = (int)a.grid_ld, ild = (int)a.in_ld, old = (int)a.out_ld;
   // the lane's problem's offset in each buffer (zero without a stack)
   const int o_in = sp * a.s_in, o_out = sp * a.s_out, o_out2 = sp * a.s_out2, o_win = sp * a.s_win;
@@ -240,15 +240,26 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
       }
     }
   }
-  // phases -> diagonal entries where no table was given
+  // phases -> diagonal entries where no table was given (the sixteen-
+  // element shape forms the mid and post entries where they are used, so
+  // that only the phases stay live across the first transform)
+  constexpr bool LATE_PH = !TAB && E >= 16;
   if constexpr (!TAB) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       if constexpr (PRE == PRE_PHASE) dp[j] = phase_turns(dp[j].x);
-      if constexpr (MID_PH) dm[j] = phase_turns(dm[j].x);
-      if constexpr (POST_PH) dq[j] = phase_turns(dq[j].x);
+      if constexpr (MID_PH && !LATE_PH) dm[j] = phase_turns(dm[j].x);
+      if constexpr (POST_PH && !LATE_PH) dq[j] = phase_turns(dq[j].x);
     }
   }
+  auto Dm = [&](int j) -> float2 {
+    if constexpr (LATE_PH) return phase_turns(dm[j].x);
+    else return dm[j];
+  };
+  auto Dq = [&](int j) -> float2 {
+    if constexpr (LATE_PH) return phase_turns(dq[j].x);
+    else return dq[j];
+  };
 
   float s_pre = a.scale_pre;
   float s_prev = 1.f;  // 1/||u_prev|| for the spectral update
@@ -276,7 +287,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
   if constexpr (MID == MID_PHASE || MID == MID_PHASE_CONJ) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const float2 d = cscale(dm[j], a.scale_mid);
+      const float2 d = cscale(Dm(j), a.scale_mid);
       v[j] = (MID == MID_PHASE_CONJ) ? cmulc(v[j], d) : cmul(v[j], d);
     }
   } else if constexpr (mid_rev_phase(MID)) {
@@ -286,18 +297,18 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
       const unsigned go8 = off8(active, gidx(k) + o_sv), go4 = off4(active, gidx(k) + o_gt);
       const float2 u = cscale(v[j], a.scale_mid);
       if constexpr (MID == MID_PHASE_SAVE) {
-        v[j] = cmul(u, dm[j]);
+        v[j] = cmul(u, Dm(j));
         st2(r_save, go8, v[j]);
       } else if constexpr (MID == MID_PHASE_CONJ_SAVE) {
-        v[j] = cmulc(u, dm[j]);
+        v[j] = cmulc(u, Dm(j));
         st2(r_save, go8, v[j]);
       } else if constexpr (MID == MID_PHASE_CONJ_GT) {
         // Im(u conj(s)) = u.y s.x - u.x s.y
         st1(r_gth, go4, gt[j] + (u.y * sv[j].x - u.x * sv[j].y));
-        v[j] = cmulc(u, dm[j]);
+        v[j] = cmulc(u, Dm(j));
       } else {  // MID_PHASE_GT: Im(conj(u) s) = u.x s.y - u.y s.x
         st1(r_gth, go4, gt[j] + (u.x * sv[j].y - u.y * sv[j].x));
-        v[j] = cmul(u, dm[j]);
+        v[j] = cmul(u, Dm(j));
       }
     }
   } else if constexpr (MID == MID_GD) {
@@ -345,6 +356,12 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
 
   // ---- second transform, post-diagonal, update, store
   if constexpr (FFT2) T::template fft<INV2>(v, lds, ph, w, t, bl);
+  if constexpr (E >= 16) {
+    // the sixteen-element shape recomputes its store addresses here rather
+    // than keeping the load phase's ones live (in scratch) across the
+    // transforms: the lane coordinates are marked as changed (no code)
+    asm volatile("" : "+v"(t), "+v"(b), "+v"(gb));
+  }
 
   if constexpr (MID != MID_STORE) {
     constexpr bool CHECK = (POST == POST_GD || POST == POST_SPEC);  // the last update of a solve
@@ -358,11 +375,13 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
       const int k = T::elem(t, j);
       const bool ow = out_win(k);
       float2 val = cscale(v[j], a.scale_out);
+      float2 qj = make_float2(1.f, 0.f);
+      if constexpr (POST_PH) qj = Dq(j);
       if constexpr (POST == POST_PHASE_CONJ_GT) {
-        const float2 u1 = cmul(xo[j], dq[j]);  // u_1 = D_1 U x at this position
+        const float2 u1 = cmul(xo[j], qj);  // u_1 = D_1 U x at this position
         st1(r_gth, off4(ow, gidx(k) + o_gt), gt[j] + (val.y * u1.x - val.x * u1.y));
       }
-      if constexpr (POST_PH) val = cmulc(val, dq[j]);
+      if constexpr (POST_PH) val = cmulc(val, qj);
       if constexpr (POST_IS_GD) {
         val = make_float2(xo[j].x - step * val.x, xo[j].y - step * val.y);
       } else if constexpr (POST_IS_SPEC) {
@@ -372,7 +391,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, int tile, float2* l
       }
       st2(r_out, off8(ow, out_addr(k)), val);
       if constexpr (CHECK) bad |= ow && !finite2(val);
-      if constexpr (POST_FWD) v[j] = ow ? cmul(val, dq[j]) : make_float2(0.f, 0.f);  // zero outside the support
+      if constexpr (POST_FWD) v[j] = ow ? cmul(val, qj) : make_float2(0.f, 0.f);  // zero outside the support
     }
     if constexpr (CHECK) flag_nonfinite(a.nf, bad);
   }

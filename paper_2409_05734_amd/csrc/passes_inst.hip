@@ -15,13 +15,14 @@ namespace sr {
 
 namespace {
 
-// Tile widths are encoded as B | kSingleBuffer for single-buffered tiles and
-// B | kNarrow for the narrow thread shape.
+// Tile widths are encoded as B | kSingleBuffer for single-buffered tiles,
+// B | kNarrow for the narrow thread shape and B | kWide | kSingleBuffer for
+// the wide one.
 template <int N, int BE, bool COL, int PRE, int MID, bool FFT2, bool INV1, bool INV2, int POST, bool TAB, bool WIN>
 hipError_t go_src(const PassArgs& a, hipStream_t s) {
   constexpr int B = BE & (kSingleBuffer - 1);
   constexpr bool DB = (BE & kSingleBuffer) == 0;
-  constexpr int EV = (BE & kNarrow) ? 1 : 0;
+  constexpr int EV = (BE & kNarrow) ? 1 : (BE & kWide) ? 2 : 0;
   using T = TileV<N, B, COL, DB, EV>;
   auto kern = pass_kernel<N, B, COL, PRE, MID, FFT2, INV1, INV2, POST, DB, EV, TAB, WIN>;
   const size_t lds = T::NBUF * sizeof(float2) * (size_t)T::BUF;
@@ -124,6 +125,19 @@ using Cfg = TileCfg<SR_FFT_N>;
 constexpr bool kHasNarrow = HasNarrow<SR_FFT_N>::value && SR_PASS_SET == 0;
 using CfgN = TileCfg<SR_FFT_N, kHasNarrow ? 1 : 0>;
 constexpr int kColOpts[4] = {2, 4, 8, 16};
+// the wide shape: the column passes with two transforms and a phase between
+// them ([F D F] and [F^H D^* F^H]), eight-column single-buffered tiles
+constexpr bool kHasWide = HasWide<SR_FFT_N>::value && SR_PASS_SET == 0;
+constexpr int kWideCols = 8;
+template <int N, int EV>
+constexpr bool wide_fits() {
+  if constexpr (EV == 2 && HasWide<N>::value) {
+    using T = TileV<N, kWideCols, true, false, 2>;
+    return T::THREADS <= 1024 && sizeof(float2) * T::BUF <= (size_t)TileCfg<N>::kMaxLds;
+  } else {
+    return false;
+  }
+}
 
 template <int N, int B>
 hipError_t col_tile(int kind, bool single, bool narrow, const PassArgs& a, hipStream_t s) {
@@ -139,6 +153,18 @@ hipError_t col_tile(int kind, bool single, bool narrow, const PassArgs& a, hipSt
 
 template <int N>
 hipError_t by_tile(int kind, bool col, int Benc, const PassArgs& a, hipStream_t s) {
+  if (Benc & kWide) {
+    // (only the two shapes below are built wide; the same template arguments
+    // as dispatch() gives these kinds)
+    if constexpr (kHasWide && wide_fits<N, 2>()) {
+      constexpr int W = kWideCols | kWide | kSingleBuffer;
+      if (col && Benc == W && kind == PK_MID_FWD)
+        return go<N, W, true, PRE_NONE, MID_PHASE, true, false, false, POST_STORE>(a, s);
+      if (col && Benc == W && kind == PK_MID_ADJ)
+        return go<N, W, true, PRE_NONE, MID_PHASE_CONJ, true, true, true, POST_STORE>(a, s);
+    }
+    return hipErrorInvalidValue;
+  }
   const bool narrow = (Benc & kNarrow) != 0;
   if (col) {
     const bool single = (Benc & kSingleBuffer) != 0;
@@ -193,6 +219,8 @@ int tile_options_n<SR_FFT_N>(bool col, int* out, int max_out) {
     if (kHasNarrow)
       for (int b : kColOpts)
         if (CfgN::col_ok(b) && n < max_out) out[n++] = b | kNarrow;
+    if constexpr (kHasWide && wide_fits<SR_FFT_N, 2>())
+      if (n < max_out) out[n++] = kWideCols | kWide | kSingleBuffer;
   } else {
     if (n < max_out) out[n++] = Cfg::ROW_SMALL;
     if (Cfg::ROW_BIG != Cfg::ROW_SMALL && n < max_out) out[n++] = Cfg::ROW_BIG;

@@ -34,8 +34,16 @@ bool twiddles_for(int shape, std::vector<float2>& out) {
     return true;
   }
   if constexpr (sr::HasNarrow<N>::value) {
-    fill_twiddles<N, 1>(out);
-    return true;
+    if (shape == 1) {
+      fill_twiddles<N, 1>(out);
+      return true;
+    }
+  }
+  if constexpr (sr::HasWide<N>::value) {
+    if (shape == 2) {
+      fill_twiddles<N, 2>(out);
+      return true;
+    }
   }
   return false;
 }
@@ -79,7 +87,7 @@ sr_status sr_plan_s::init(const float* theta_host) {
   std::vector<float2> host_tw;
   std::vector<std::pair<std::pair<int, int>, size_t>> tw_at;  // ((length, shape), offset)
   for (int N : lens)
-    for (int shape = 0; shape < 2; ++shape) {
+    for (int shape = 0; shape < 3; ++shape) {
       std::vector<float2> t;
       if (!thread_twiddles(N, shape, t)) continue;
       tw_at.push_back({{N, shape}, host_tw.size()});

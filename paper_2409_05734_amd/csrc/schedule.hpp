@@ -21,12 +21,23 @@ namespace sr {
 inline int pass_col(int k) { return (k % 2) == 1; }  // forward pass k (1-based): odd -> axis 0
 inline int pass_len(const Geo& g, int k) { return pass_col(k) ? g.M1 : g.M2; }
 
+// The tile a pass other than [F D F] / [F^H D^* F^H] runs (the passes that
+// write or read per-tile partial sums are among them): the tuner's choice,
+// or the length's default where that choice is the wide shape, which only
+// those two column passes have (launch_pass falls back the same way).
+inline int tile_other(const sr_plan_s* p, int N, bool col) {
+  int b = p->tile(N, col);
+  if (b <= 0 || (b & kWide)) b = default_tile(N, col);
+  return b;
+}
+
 inline PassArgs base_args(const sr_plan_s* p, const Geo& g, int k) {
   PassArgs a;
   std::memset(&a, 0, sizeof(a));
   a.grid_ld = g.M2;
   a.tw = p->twiddles(pass_len(g, k), 0);
-  a.tw_n = p->twiddles(pass_len(g, k), 1);
+  // the length's other thread shape: narrow, or wide (no length has both)
+  a.tw_n = p->twiddles(pass_len(g, k), 1) ? p->twiddles(pass_len(g, k), 1) : p->twiddles(pass_len(g, k), 2);
   a.scale_pre = 1.f;
   a.scale_mid = 1.f;
   a.scale_out = 1.f;
@@ -209,9 +220,7 @@ inline sr_status launch(sr_plan_s* p, const Geo& g, int k, int kind, const PassA
     a.s_win = std::max(sy, std::max(sz, syo));  // measurement-shaped buffers share one stride
     a.step_v = p->stk.steps;
     if (a.part_in != nullptr || a.part_out != nullptr) {  // per-problem partial sums: whole problems per tile
-      int bt = p->tile(pass_len(g, k), pass_col(k));
-      if (bt <= 0) bt = default_tile(pass_len(g, k), pass_col(k));
-      bt &= kSingleBuffer - 1;
+      const int bt = tile_other(p, pass_len(g, k), pass_col(k)) & (kSingleBuffer - 1);
       if (a.ntr_p % bt != 0) return fail(SR_E_STATE, "stacked pass with partial sums: a tile spans two problems");
     }
   }

@@ -277,12 +277,14 @@ sr_status spec_steady_public(sr_plan_s* p, const Geo& g, const float* y, float2*
 }
 }  // namespace sr
 
-static int last_pass_groups(const sr_plan_s* p, const Geo& g) { return pass_groups(g.M1, true, p->tile(g.M1, true), g.N2); }
+static int last_pass_groups(const sr_plan_s* p, const Geo& g) {
+  return pass_groups(g.M1, true, tile_other(p, g.M1, true), g.N2);
+}
 static int turn_groups(const sr_plan_s* p, const Geo& g) {
   const int k = g.L + 1;
   const int ntr = (k == 2) ? g.M1 : (pass_col(k) ? g.M2 : g.M1);
   const int N = pass_len(g, k);
-  return pass_groups(N, pass_col(k), p->tile(N, pass_col(k)), ntr);
+  return pass_groups(N, pass_col(k), tile_other(p, N, pass_col(k)), ntr);
 }
 
 // ------------------------------------------------------------------ tuner
@@ -918,9 +920,7 @@ sr_status sr_adjoint(sr_plan p, const void* r, void* x_out) {
 static bool stack_trace_ok(const sr_plan_s* p, const Geo& g) {
   const int k = g.L + 1;
   const int ntr = (k == 2) ? g.M1 : (pass_col(k) ? g.M2 : g.M1);
-  int bt = p->tile(pass_len(g, k), pass_col(k));
-  if (bt <= 0) bt = default_tile(pass_len(g, k), pass_col(k));
-  bt &= kSingleBuffer - 1;
+  const int bt = tile_other(p, pass_len(g, k), pass_col(k)) & (kSingleBuffer - 1);
   return ntr % bt == 0;
 }
 
@@ -1100,9 +1100,7 @@ sr_status sr_gd_solve_noalloc(sr_plan p, const float* y, void* x_inout, int32_t 
 // Whether a stack's spectral passes keep each tile inside one problem (the
 // passes that read and write per-problem norm partials need it).
 static bool stack_spectral_ok(const sr_plan_s* p, const Geo& g) {
-  int bt = p->tile(g.M1, true);
-  if (bt <= 0) bt = default_tile(g.M1, true);
-  bt &= kSingleBuffer - 1;
+  const int bt = tile_other(p, g.M1, true) & (kSingleBuffer - 1);
   return g.N2 % bt == 0;
 }
 

@@ -8,11 +8,12 @@ last pass fused with the next iteration's first) and 2048-point row passes
 grids, 2048 x 128 and 128 x 2048, run each of those kernels on the tile
 choice the tuner makes for the large workload (four-column tiles, one-row
 tiles, phases evaluated with sincos) while keeping the oracle's explicit DFT
-matrices affordable; GD iterates (section II-B.1, Eq. (2)) are compared at
-steps 1, 7 and 50, power-iteration iterates (Eq. (3)-(4)) at 1 and 10, and
-the loss trace over 7 steps.  The full 2048^2 grid then takes one GD step and
-one power iteration from the same start as the oracle, with the tuner's own
-choice and with the pinned one.  Bars: 1e-4 on iterates after global-phase
+matrices affordable, and again with the wide shape's eight-column tiles
+(radix-16 stages) for the [F D F] column passes; GD iterates (section
+II-B.1, Eq. (2)) are compared at steps 1, 7 and 50, power-iteration iterates
+(Eq. (3)-(4)) at 1 and 10, and the loss trace over 7 steps.  The full 2048^2
+grid then takes one GD step and one power iteration from the same start as
+the oracle, with the tuner's own choice and with both pinned ones.  Bars: 1e-4 on iterates after global-phase
 alignment, 1e-4 on loss-trace entries.
 """
 import numpy as np
@@ -26,6 +27,9 @@ pytestmark = pytest.mark.gpu
 
 TOL_IT = 1e-4
 LARGE_CHOICE = "4,1,0"  # column tile 4, row tile 1, sincos phases
+# eight-column single-buffered tiles of the sixteen-elements-per-thread shape
+# (radix-16 stages) for the [F D F] column passes, the rest as above
+WIDE_CHOICE = f"{8 | 256 | 1024},1,0"
 
 
 def _gd(plan, y, x0, iters, eta, dev, loss=False):
@@ -47,9 +51,10 @@ def _spec(plan, y, v0, iters, dev):
     return to_host(out)
 
 
+@pytest.mark.parametrize("choice", [LARGE_CHOICE, WIDE_CHOICE])
 @pytest.mark.parametrize("n_shape,m_shape", [((600, 102), (2048, 128)), ((102, 600), (128, 2048))])
-def test_gd_and_spectral_on_2048_point_axes(gpu, monkeypatch, n_shape, m_shape):
-    monkeypatch.setenv("SR_TUNE_FORCE", LARGE_CHOICE)
+def test_gd_and_spectral_on_2048_point_axes(gpu, monkeypatch, n_shape, m_shape, choice):
+    monkeypatch.setenv("SR_TUNE_FORCE", choice)
     rng = np.random.default_rng(sum(m_shape))
     L = 3
     th = sr_inputs.phase_masks(rng, L, m_shape)
@@ -59,7 +64,7 @@ def test_gd_and_spectral_on_2048_point_axes(gpu, monkeypatch, n_shape, m_shape):
     x0 = (xs + 0.5 * sr_inputs.complex_gaussian(rng, n_shape)).astype(np.complex64)
     eta = np.float32(oracle.default_step(op, y, 0.2))
     plan = make_plan([(n_shape, m_shape, L)], [th], gpu)
-    print(f"large-axis GD/spectral parity: {n_shape} -> {m_shape}, L = {L}", flush=True)
+    print(f"large-axis GD/spectral parity: {n_shape} -> {m_shape}, L = {L}, tiles {choice}", flush=True)
 
     _, its, losses = oracle.gd_solve(op, y, x0, 50, float(eta), return_iterates=True, return_loss=True)
     for k in (1, 7, 50):
@@ -80,7 +85,7 @@ def test_gd_and_spectral_on_2048_point_axes(gpu, monkeypatch, n_shape, m_shape):
 def test_full_large_grid_one_step(gpu, monkeypatch):
     """1024^2 image padded to 2048^2, L = 3, Poisson noise at 1000 photons
     (the large workload's inputs): one GD step from a start near the image and
-    one power iteration, on the tuner's choice and on the pinned one."""
+    one power iteration, on the tuner's choice and on both pinned ones."""
     d = sr_inputs.large_2d(4)
     n_shape, m_shape, L = d["n_shape"], d["m_shape"], d["layers"]
     th, xs = d["theta"], d["x_star"]
@@ -92,7 +97,7 @@ def test_full_large_grid_one_step(gpu, monkeypatch):
     print("large-grid one-step parity: oracle", flush=True)
     x1 = oracle.gd_solve(op, y, x0, 1, float(eta))
     s1 = oracle.spectral_init(op, y, d["v0"], 1, d["lam"])
-    for force in (None, LARGE_CHOICE):
+    for force in (None, LARGE_CHOICE, WIDE_CHOICE):
         if force is None:
             monkeypatch.delenv("SR_TUNE_FORCE", raising=False)
         else:

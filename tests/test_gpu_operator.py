@@ -151,18 +151,20 @@ def test_sampled_outputs_at_large_size(gpu):
 
 
 NARROW = 512  # tile-width flag of the four-elements-per-thread shape
+WIDE = 1024   # ... of the sixteen-elements-per-thread shape (2048-point columns, single-buffered)
 
 
 @pytest.mark.parametrize("n_shape,m_shape,L", [((256, 256), (512, 512), 2), ((600, 300), (2048, 512), 3),
                                                ((300, 700), (768, 2048), 2), ((40, 50), (96, 128), 3),
                                                ((100, 30), (256, 64), 2), ((500, 200), (1024, 256), 3)])
 @pytest.mark.parametrize("col_tile", [2, 4, 8, 16, 2 | 256, 4 | 256, 8 | 256, 16 | 256,
-                                      2 | NARROW, 4 | NARROW, 8 | NARROW])
+                                      2 | NARROW, 4 | NARROW, 8 | NARROW, 8 | 256 | WIDE])
 def test_every_tile_variant(gpu, monkeypatch, n_shape, m_shape, L, col_tile):
-    """Every compiled column tile (double- and single-buffered LDS, default and
-    narrow thread shape) and the row tiles of both shapes, with and without
-    the exp(i theta) table, against the oracle.  Widths a length does not
-    offer fall back to its default tile."""
+    """Every compiled column tile (double- and single-buffered LDS, default,
+    narrow and wide thread shape) and the row tiles of both shapes, with and
+    without the exp(i theta) table, against the oracle.  Widths a length does
+    not offer fall back to its default tile (and the wide shape, built for the
+    [F D F] column passes only, to the default tile in every other pass)."""
     import torch
     import paper_2409_05734_amd as srpr
     rng = np.random.default_rng(col_tile + L)
