@@ -121,7 +121,8 @@ void run_plan(const std::vector<sr_problem>& ps, const std::vector<float>& th, c
   expect(sr_adjoint_vjp(p, z, x, gr, gth) == SR_OK, "adjoint vjp");
   expect(sr_gd_step_vjp(p, y, x, eta.data(), v, gx, gy, gth) == SR_OK, "gd step vjp");
   expect(sr_intensity_vjp(p, x, y, gx, gth) == SR_OK, "intensity vjp");
-  const bool all2d = ps[0].ndim == 2;
+  bool all2d = true;
+  for (const sr_problem& q : ps) all2d = all2d && q.ndim == 2;
   if (all2d) expect(sr_gd_solve_noalloc(p, y, v, 3, eta.data()) == SR_OK, "noalloc gd");
   expect(sr_gd_solve(p, y, v, -1, eta.data(), nullptr) == SR_E_ARG, "negative iterations");
   std::vector<float> bad(eta);
@@ -158,6 +159,12 @@ void gpu_checks() {
   }
   run_plan(uneven, std::vector<float>((size_t)off, 1.f), "uneven, batched levels", SR_SCHED_BATCHED);
   run_plan({prob(1, 64, 1, 256, 1, 2)}, std::vector<float>(512, 1.f), "1D", SR_SCHED_AUTO);
+  // level problems of both length classes beside a 1D problem and a 2D
+  // length the level kernel does not take (the level tuner skips those two)
+  run_plan({prob(2, 20, 20, 32, 64, 1, SR_STRUCTURED, 0), prob(2, 40, 36, 96, 64, 3, SR_STRUCTURED, 2048),
+            prob(2, 30, 30, 64, 64, 2, SR_STRUCTURED, 2048 + 3 * 6144), prob(1, 16, 1, 64, 1, 2, SR_STRUCTURED, 28672),
+            prob(2, 60, 20, 768, 32, 1, SR_STRUCTURED, 28800)},
+           std::vector<float>(28800 + 24576, 1.f), "mixed, batched", SR_SCHED_BATCHED);
   // dense
   const int m = 256, n = 64;
   float2* A = dev_alloc<float2>((size_t)m * n, 0.5f);

@@ -137,6 +137,44 @@ def test_batched_rectangular_mixed_lengths(gpu):
         assert aligned(xi, xr) <= 1e-4, (n_shape, m_shape, L)
 
 
+def test_batched_plan_with_problems_off_the_levels(gpu):
+    """A batched plan whose level problems (both length classes) share it with
+    a 1D problem and a 2D problem of a length the level kernel does not take
+    (768): GD past one captured chunk (Eq. (2)) and power iteration
+    (Eq. (3)-(4)) against the oracle for every problem.  The level tuner,
+    which runs on the plan's first batched solve, must leave the other two
+    alone (they have no private level buffers)."""
+    import torch
+    import paper_2409_05734_amd as srpr
+    rng = np.random.default_rng(23)
+    specs = [((20, 20), (32, 64), 1), ((40, 36), (96, 64), 3), ((30, 30), (64, 64), 2), ((16,), (64,), 2),
+             ((60, 20), (768, 32), 1)]
+    cases = []
+    for n_shape, m_shape, L in specs:
+        th = sr_inputs.phase_masks(rng, L, m_shape)
+        xs = sr_inputs.complex_gaussian(rng, n_shape)
+        op = oracle.StructuredOperator(th, n_shape)
+        y = oracle.measurements(xs, th).astype(np.float32)
+        x0 = (xs + 0.5 * sr_inputs.complex_gaussian(rng, n_shape)).astype(np.complex64)
+        v0 = sr_inputs.complex_gaussian(rng, n_shape)
+        cases.append((th, op, y, x0, v0, np.float32(oracle.default_step(op, y, 0.2))))
+    plan = srpr.Plan([srpr.Problem(*sp) for sp in specs], np.concatenate([c[0].ravel() for c in cases]))
+    srpr.sr_plan_set_schedule(plan, srpr.SR_SCHED_BATCHED)
+    yd = to_dev(np.concatenate([c[2].ravel() for c in cases]), gpu)
+    out = torch.empty(plan.n_total, dtype=torch.complex64, device=gpu)
+    srpr.sr_spectral_init(plan, yd, to_dev(np.concatenate([c[4].ravel() for c in cases]), gpu), 12, -1.0, out)
+    x = to_dev(np.concatenate([c[3].ravel() for c in cases]), gpu)
+    srpr.sr_gd_solve(plan, yd, x, 60, np.array([c[5] for c in cases], np.float32))
+    srpr.sr_plan_sync(plan)
+    sh, xh = to_host(out), to_host(x)
+    for i, ((n_shape, m_shape, L), (th, op, y, x0, v0, eta)) in enumerate(zip(specs, cases)):
+        sl = slice(plan.x_off[i], plan.x_off[i + 1])
+        sr_ref = oracle.spectral_init(op, y, v0, 12, -1.0)
+        assert rel_l2(sh[sl].reshape(n_shape), sr_ref) <= 1e-4, ("spectral", n_shape, m_shape)
+        xr = oracle.gd_solve(op, y, x0, 60, float(eta))
+        assert aligned(xh[sl].reshape(n_shape), xr) <= 1e-4, ("gd", n_shape, m_shape)
+
+
 def test_batched_matches_tuned_loop(gpu):
     """Against the loop on the tuner's tile shapes (which may use the narrow
     thread shape, a different FFT factorisation): agreement to rounding over
