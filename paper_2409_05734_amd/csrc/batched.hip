@@ -1149,7 +1149,11 @@ static sr_status spec_prepare(sr_plan_s* p, const std::vector<int>& which, const
       st->fgroups = std::max(st->fgroups, (int)std::min<int64_t>((g.n + 255) / 256, 1024));
       dp.push_back(q);
     }
-    if (st->d_prob) (void)hipFree(st->d_prob);  // (build_levels above waited for the stream)
+    if (st->d_prob != nullptr || st->ws != nullptr) {
+      // set-up and finish launches already queued may still read the old ones
+      if (hipError_t w = hipStreamSynchronize(p->stream); w != hipSuccess) return hip_fail(w, "stream wait");
+    }
+    if (st->d_prob) (void)hipFree(st->d_prob);
     if (st->ws) (void)hipFree(st->ws);
     st->d_prob = nullptr;
     st->ws = nullptr;
