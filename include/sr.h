@@ -24,9 +24,12 @@
  *    arrays are row-major and contiguous.
  *  - Every data pointer is a DEVICE pointer owned by the caller unless the
  *    comment says "host".  The library never frees caller memory.
- *  - Calls are asynchronous and ordered on the plan's HIP stream; argument and
- *    shape errors are reported synchronously by the return value, before any
- *    work is enqueued.  Device-side failures surface at sr_plan_sync().
+ *  - Calls are asynchronous and ordered on the plan's HIP stream (a call may
+ *    run part of its work on a second stream the plan owns, forked from and
+ *    joined back into the plan's stream within the call, so the ordering
+ *    holds); argument and shape errors are reported synchronously by the
+ *    return value, before any work is enqueued.  Device-side failures
+ *    surface at sr_plan_sync().
  *  - A plan holds several problems; per-problem arrays are concatenated in
  *    problem order (offsets from sr_plan_offsets).
  *  - No call aborts the process and no C++ exception crosses this boundary.
@@ -79,8 +82,10 @@ typedef enum {
  * (one launch per pass level over all problems: A, A^H, GD, power
  * iteration and both derivatives, the latter where no two problems share
  * a phase block);
- * problems whose grid fits one workgroup's LDS solve there instead (power
- * iteration by default; GD with SR_LDS_RESIDENT=1), beside the levels.     */
+ * GD and power iteration run the problems with a 96-, 192- or 384-point axis
+ * on a second stream beside the others; with SR_LDS_RESIDENT=1, problems
+ * whose grid fits one workgroup's LDS solve there instead, beside the
+ * levels.                                                                   */
 typedef enum {
   SR_SCHED_AUTO = 0,       /* library's choice (above) */
   SR_SCHED_LOOP = 1,       /* one problem after another, one launch per fused pass */
