@@ -508,6 +508,8 @@ __global__ void pack_br_kernel(const float2* __restrict__ r, const float* __rest
 
 }  // namespace
 
+constexpr int kLibCandidates = 8;  // library algorithms timed per product at plan creation
+
 struct DenseLib {
   hipblasLtHandle_t h = nullptr;
   hipblasLtMatmulDesc_t desc = nullptr;
@@ -653,17 +655,26 @@ sr_status dense_lib_setup(sr_plan_s* p) {
   if (hipblasLtMatmulPreferenceCreate(&pref) != HIPBLAS_STATUS_SUCCESS) return give_up();
   const uint64_t wmax = kLibWorkspace;
   (void)hipblasLtMatmulPreferenceSetAttribute(pref, HIPBLASLT_MATMUL_PREF_MAX_WORKSPACE_BYTES, &wmax, sizeof(wmax));
+  // up to kLibCandidates of the library's algorithms per product, in its
+  // heuristic's order
+  hipblasLtMatmulAlgo_t cand[2][kLibCandidates];
+  int ncand[2] = {0, 0};
   size_t need = 0;
   for (int g = 0; g < 2; ++g) {
     const hipblasLtMatrixLayout_t* l = g == 0 ? d->l1 : d->l2;
-    hipblasLtMatmulHeuristicResult_t res[1];
+    hipblasLtMatmulHeuristicResult_t res[kLibCandidates];
     int cnt = 0;
-    if (hipblasLtMatmulAlgoGetHeuristic(d->h, d->desc, l[0], l[1], l[2], l[2], pref, 1, res, &cnt) ==
-            HIPBLAS_STATUS_SUCCESS &&
-        cnt > 0 && res[0].state == HIPBLAS_STATUS_SUCCESS) {
-      d->algo[g] = res[0].algo;
+    if (hipblasLtMatmulAlgoGetHeuristic(d->h, d->desc, l[0], l[1], l[2], l[2], pref, kLibCandidates, res, &cnt) !=
+        HIPBLAS_STATUS_SUCCESS)
+      cnt = 0;
+    for (int i = 0; i < cnt; ++i) {
+      if (res[i].state != HIPBLAS_STATUS_SUCCESS) continue;
+      cand[g][ncand[g]++] = res[i].algo;
+      need = std::max(need, res[i].workspaceSize);
+    }
+    if (ncand[g] > 0) {
+      d->algo[g] = cand[g][0];
       d->ok[g] = true;
-      need = std::max(need, res[0].workspaceSize);
     }
   }
   (void)hipblasLtMatmulPreferenceDestroy(pref);
@@ -671,41 +682,58 @@ sr_status dense_lib_setup(sr_plan_s* p) {
   if (need > 0 && hipMalloc(&d->ws, need) != hipSuccess) return give_up();
   d->ws_bytes = need;
   if (hipMalloc(&d->pack, sizeof(float) * std::max(q * n2, m * q)) != hipSuccess) return give_up();
-  // per product: the faster of the library and dense_mm_kernel (best of three
-  // applications each, on the plan's own matrix; the source is scratch of the
-  // right size, the epilogue writes nothing but scratch)
+  // per product: the fastest of dense_mm_kernel and the library's candidates
+  // (best of three applications each after a warm-up, on the plan's own
+  // matrix; the source is scratch of the right size, the epilogue writes
+  // nothing but scratch); SR_DENSE_GEMM=lib leaves dense_mm_kernel out
   const bool all_lib = force != nullptr && std::strcmp(force, "lib") == 0;
   const bool can_time = (size_t)a.n <= (size_t)a.m;  // bufB (m x nb) holds the A^H R output
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (!all_lib && (!can_time || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
+  if (!can_time || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
-    return give_up();
-  }
-  for (int g = 0; g < 2; ++g) {
-    if (!d->ok[g]) continue;
-    if (all_lib) {
-      d->use[g] = true;
-      continue;
-    }
-    float best[2] = {1e30f, 1e30f};
-    for (int v = 0; v < 2; ++v) {
-      d->use[g] = v == 1;
-      DenseArgs t = a;
-      t.src = p->bufA;
-      t.x = p->bufB;
-      t.step = 1.f;
-      for (int rep = 0; rep < 4; ++rep) {
-        (void)hipEventRecord(e0, p->stream);
-        const hipError_t e = g == 0 ? gemm<1, E1_STORE>(t, p->dsplit, p->stream, d)
-                                    : gemm<2, E2_STORE>(t, p->dsplit, p->stream, d);
-        (void)hipEventRecord(e1, p->stream);
-        if (e != hipSuccess || hipEventSynchronize(e1) != hipSuccess) break;
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (rep > 0) best[v] = std::min(best[v], ms);  // the first is a warm-up
+    if (!all_lib) return give_up();
+    for (int g = 0; g < 2; ++g) d->use[g] = d->ok[g];  // the heuristic's first choice, untimed
+    e0 = e1 = nullptr;
+  } else {
+    for (int g = 0; g < 2; ++g) {
+      if (!d->ok[g]) continue;
+      auto time_it = [&]() -> float {
+        DenseArgs t = a;
+        t.src = p->bufA;
+        t.x = p->bufB;
+        t.step = 1.f;
+        float best = 1e30f;
+        for (int rep = 0; rep < 4; ++rep) {
+          (void)hipEventRecord(e0, p->stream);
+          const hipError_t e = g == 0 ? gemm<1, E1_STORE>(t, p->dsplit, p->stream, d)
+                                      : gemm<2, E2_STORE>(t, p->dsplit, p->stream, d);
+          (void)hipEventRecord(e1, p->stream);
+          if (e != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return 1e30f;
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0) best = std::min(best, ms);  // the first is a warm-up
+        }
+        return best;
+      };
+      float best = 1e30f;
+      int pick = -1;  // -1: dense_mm_kernel
+      if (!all_lib) {
+        d->use[g] = false;
+        best = time_it();
       }
+      d->use[g] = true;
+      for (int c = 0; c < ncand[g]; ++c) {
+        d->algo[g] = cand[g][c];
+        const float t = time_it();
+        if (t < best) {
+          best = t;
+          pick = c;
+        }
+      }
+      if (all_lib && pick < 0) pick = 0;
+      d->use[g] = pick >= 0;
+      if (pick >= 0) d->algo[g] = cand[g][pick];
     }
-    d->use[g] = best[1] < best[0];
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
