@@ -324,3 +324,22 @@ def test_stacked_extremes(gpu, monkeypatch, n_shape, m_shape, L, P, shared):
     assert rel_l2(y[i * m:(i + 1) * m].reshape(m_shape), np.abs(zr) ** 2) <= 4e-5
     assert rel_l2(v[i * n:(i + 1) * n].reshape(n_shape),
                   oracle.adjoint(to_host(r)[i * m:(i + 1) * m].reshape(m_shape), th, n_shape)) <= 2e-5
+
+
+# eight-column tiles of the sixteen-elements-per-thread shape (radix-16
+# stages) for the 2048-point [F D F] column passes; the other passes keep
+# their default tiles
+WIDE = f"{8 | 256 | 1024},1,0"
+WIDE_CASES = [((300, 12), (2048, 16), 3, 3, False), ((256, 8), (2048, 16), 3, 2, True)]
+
+
+@pytest.mark.parametrize("n_shape,m_shape,L,P,shared", WIDE_CASES)
+def test_stacked_on_wide_column_tiles(gpu, monkeypatch, n_shape, m_shape, L, P, shared):
+    """The operator, derivative, GD and power-iteration checks above on
+    2048-point columns with the wide shape pinned: stacks bit for bit
+    against the problem-by-problem loop, first and last problems against
+    the oracle."""
+    monkeypatch.setenv("SR_TUNE_FORCE", WIDE)
+    test_stacked_matches_loop_and_oracle(gpu, n_shape, m_shape, L, P, shared)
+    test_stacked_gd_matches_loop_and_oracle(gpu, n_shape, m_shape, L, P, shared)
+    test_stacked_spectral_matches_loop_and_oracle(gpu, monkeypatch, n_shape, m_shape, L, P, shared, WIDE)
